@@ -1,0 +1,214 @@
+"""Benchmark of the PURSE hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+
+A step is one pass of the whole forward hot path over one batch: the sampler
+(prologue + trajectories, purse_sample) followed by the MEGB (purse_megb),
+through the C ABI, on inputs already resident in HBM.  The default workload is
+the 2D-3D single instance: N = 12 keypoints, 65,536 trajectories, 100
+alternating iterations.  Prints one JSON line.
+
+Also reported: the sampler and MEGB times separately, the roofline of the
+dominant kernel (the 2D-3D trajectory kernel; algorithmic float32 FLOPs per
+launch over its average duration, measured with HIP events on the launch
+stream) and the FP64 oracle timed on this host on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pose samples/sec (alt-projection iters) & per-instance MEGB ms, fwd vs fwd+bwd"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed)
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    "c1": dict(desc="3D-3D single instance, N=8, M=1024, 50 iterations", iters=50),
+    "c2": dict(desc="2D-3D single instance, N=12, M=65536, 100 iterations", iters=100),
+    "c3": dict(desc="512 uneven instances (50% 3D-3D / 50% 2D-3D), N~U{6..48}, M~U{1024..16384}, "
+                    "50 iterations", iters=50),
+    "c4": dict(desc="2D-3D single instance, N=24, M=262144, 20 iterations", iters=20),
+    "c5": dict(desc="64 instances 2D-3D, N=48, M=1048576 each, 50 iterations", iters=50),
+}
+
+
+def make_batch(cfg, seed=0):
+    from paper_2403_09990_amd import workloads as W
+    return {"c1": W.config_c1, "c2": W.config_c2, "c3": W.config_c3, "c4": W.config_c4,
+            "c5": W.config_c5}[cfg](seed)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2403_09990_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM traffic of the kernel from the committed rocprofv3 PMC summary, or
+    None if the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_events(fn, reps, stream):
+    import torch
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def cpu_baseline(batch, iters, megb_iters, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: its first
+    trajectories (count chosen to take roughly budget_s) plus the MEGB of
+    those samples; scaled to samples/s."""
+    import torch
+
+    from oracle.megb import megb_from_poses
+    from oracle.params import OracleParams
+    from oracle.purse import Problem, prologue, sample
+    inst = batch.instances[0]
+    prob = Problem.from_instance(inst)
+    p = OracleParams(n_iters=iters, megb_iters=megb_iters)
+    pro = prologue(prob, p)
+    t0 = time.perf_counter()
+    sample(prob, p, inst.seed, 64, pro=pro)
+    t_probe = (time.perf_counter() - t0) / 64
+    m = int(max(256, min(inst.n_samples, budget_s * 0.5 / max(t_probe, 1e-6))))
+    m = 1 << int(np.log2(m))
+    t0 = time.perf_counter()
+    out = sample(prob, p, inst.seed, m, pro=pro)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    megb_from_poses(out["poses"], out["mask"], megb_iters, 10)
+    t_m = time.perf_counter() - t0
+    return dict(value=m / (t_s + t_m), unit="samples/s", cores=torch.get_num_threads(), kind="oracle",
+                sample="first %d of %d trajectories of instance 0 (%d iterations) + MEGB (T=%d) of "
+                       "those samples; sampler %.2f s, MEGB %.2f s" % (m, inst.n_samples, iters,
+                                                                       megb_iters, t_s, t_m))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_09990_amd as P
+    from paper_2403_09990_amd import flops as F
+
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[args.config]
+    batch = make_batch(args.config)
+    gp = P.purse_default_params(n_iters=cfg["iters"])
+    db = P.DeviceBatch(batch)
+    ws = P.workspace(db, gp)
+    dev = db.kind.device
+    poses = torch.empty(db.total_samples, 12, dtype=torch.float32, device=dev)
+    mask = torch.empty(db.total_samples, dtype=torch.uint8, device=dev)
+    status = torch.empty(db.n_inst, dtype=torch.int32, device=dev)
+    centre = torch.empty(db.n_inst, 12, dtype=torch.float32, device=dev)
+    radii = torch.empty(db.n_inst, 2, dtype=torch.float64, device=dev)
+    nfeas = torch.empty(db.n_inst, dtype=torch.int64, device=dev)
+    trace = torch.empty(db.n_inst, gp.megb_iters, 2, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def do_sample(params=gp):
+        P.purse_sample(db, params, poses, mask, status, ws, stream)
+
+    def do_megb():
+        P.purse_megb(db, gp, poses, mask, centre, radii, nfeas, trace, status, ws, stream)
+
+    def step():
+        do_sample()
+        do_megb()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms_step = time_events(step, args.steps, stream)
+    total_m = db.total_samples
+    value = total_m / (ms_step * 1e-3)
+
+    # breakdown and roofline of the trajectory kernel (prologue reused so the
+    # events bracket the trajectory launches alone)
+    ms_sample = time_events(do_sample, args.roofline_reps, stream)
+    ms_megb = time_events(do_megb, args.roofline_reps, stream)
+    gp_reuse = P.purse_default_params(n_iters=cfg["iters"], flags=P.PURSE_FLAG_REUSE_PROLOGUE)
+    ms_traj = time_events(lambda: do_sample(gp_reuse), args.roofline_reps, stream)
+    flops = F.batch_flops(batch, cfg["iters"], gp.n_gn)
+    achieved = flops / (ms_traj * 1e-3) / 1e12
+    traffic = read_traffic("k_sample", args.config)
+    m = mask.cpu().numpy()
+    st = status.cpu().numpy()
+    rad = radii.cpu().numpy()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator shaped like the paper's 2D-3D / 3D-3D workloads)",
+        "config": {"workload": "%s: %s" % (args.config, cfg["desc"]), "n_inst": db.n_inst,
+                   "samples": total_m, "megb_iters": gp.megb_iters, "parallelism": "single GPU"},
+        "sampler_ms": ms_sample,
+        "trajectory_kernel_ms": ms_traj,
+        "megb_ms": ms_megb,
+        "megb_ms_per_instance": ms_megb / db.n_inst,
+        "sampler_samples_per_s": total_m / (ms_sample * 1e-3),
+        "sample_iters_per_s": total_m * cfg["iters"] / (ms_sample * 1e-3),
+        "feasible_fraction": float((m & 1).mean()),
+        "pulled_in_fraction": float(((m & 2) != 0).mean()),
+        "inst_status_nonzero": int((st & 0xFF != 0).sum()),
+        "radii_first_instance": [float(rad[0, 0]), float(rad[0, 1])],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": "k_sample (2D-3D and 3D-3D trajectory kernels)",
+                     "flops_per_launch": flops,
+                     "non_packed_fp32_ceiling_frac": 0.5},
+        "hbm_write_gbs": total_m * 13 / (ms_traj * 1e-3) / 1e9,
+    }
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "c4"):
+        out["cpu_baseline"] = cpu_baseline(batch, cfg["iters"], gp.megb_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

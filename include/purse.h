@@ -1,0 +1,210 @@
+/*
+ * purse.h -- C ABI of the MI355X (gfx950) PURSE boundary sampler and MEGB.
+ *
+ * The operation is the inner approximation of the minimum enclosing geodesic
+ * ball (MEGB) of a pose uncertainty set (PURSE) from "CLOSURE: Fast
+ * Quantification of Pose Uncertainty Sets" (arXiv 2403.09990):
+ *
+ *   S = { x = (R, t) in SE(3) : ||g(x, y_i)||_{Lambda_i} <= beta_i, i = 1..N }
+ *
+ * (eq. PURSE; the 2D-3D form eq. PURSE2D3D with g = z_i - Pi(R Z_i + t), the
+ * 3D-3D form eq. PURSE3D3D with g = b_i - (R a_i + t)).  purse_sample draws
+ * boundary samples of S with independent randomly started trajectories;
+ * purse_megb returns the centre pose and the rotation / translation radii of
+ * the geodesic balls enclosing the samples (Section "Minimum Enclosing
+ * Geodesic Ball", eqs. megb-rot and megb-tran, Proposition 1); purse_megb_backward
+ * returns the gradient of those outputs with respect to the measurements.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named in purse_batch and the array arguments are DEVICE
+ *    pointers owned by the caller; the library never frees or keeps them.
+ *  - Scalars (n_inst, totals, params) are read on the host during the call.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) and performs no host synchronisation and no device allocation:
+ *    scratch comes from the caller's workspace `ws` of at least
+ *    purse_workspace_size() bytes, 256-byte aligned.
+ *  - Return values: PURSE_OK, or a negative PURSE_E_* code for API misuse
+ *    detected synchronously on the host (nothing is launched).  Data-dependent
+ *    per-instance outcomes are written asynchronously to inst_status.
+ *  - Concurrent calls sharing one workspace race; give each in-flight call
+ *    its own workspace.
+ */
+#ifndef PURSE_H
+#define PURSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t purse_status;
+
+#define PURSE_OK 0
+#define PURSE_E_NULL (-1)      /* a required pointer is NULL */
+#define PURSE_E_BAD_ARG (-2)   /* a host scalar or parameter is out of range */
+#define PURSE_E_WORKSPACE (-3) /* workspace too small or misaligned */
+#define PURSE_E_NO_DEVICE (-4) /* no usable HIP device */
+#define PURSE_E_HIP (-5)       /* a HIP runtime call failed; see purse_last_error */
+
+/* Per-instance status (low byte) and flags. */
+#define PURSE_INST_OK 0
+#define PURSE_INST_EMPTY 1          /* no feasible sample: MEGB radii are NaN */
+#define PURSE_INST_BAD_SHAPE 2      /* Lambda not SPD, beta < 0, non-finite data, fx or fy <= 0 */
+#define PURSE_INST_FIT_FAILED 3     /* centre fit failed (depth <= z_min or singular normal matrix) */
+#define PURSE_INST_BAD_SIZE 4       /* N < 3 (3D-3D), N < 6 (2D-3D), N > PURSE_MAX_KP, or M < 1 */
+#define PURSE_INST_NO_ANCHOR (1 << 8)        /* no feasible anchor: infeasible ends are dropped */
+#define PURSE_INST_ANCHOR_ITERATED (1 << 9)  /* the centre was not inside; the anchor was iterated */
+
+/* Per-sample mask bits (uint8). */
+#define PURSE_MASK_FEASIBLE 1  /* the sample is in S and feeds the MEGB */
+#define PURSE_MASK_PULLED_IN 2 /* the trajectory ended outside S and was pulled back by bisection */
+#define PURSE_MASK_FAILED 4    /* a 2D-3D Gauss-Newton step failed; the sample is dropped */
+
+#define PURSE_KIND_3D3D 0 /* balls around target points b_i (eq. PURSE3D3D, Lambda_i = I) */
+#define PURSE_KIND_2D3D 1 /* ellipses around image points z_i (eq. PURSE2D3D) */
+
+#define PURSE_MAX_KP 64
+
+/* Debug flags (purse_params.flags). */
+#define PURSE_FLAG_FORCE_FP64_POLAR 1 /* always take the float64 3x3 polar step */
+#define PURSE_FLAG_NO_PRUNING 2       /* MEGB: scan every feasible sample at every step */
+#define PURSE_FLAG_REUSE_PROLOGUE 4   /* purse_sample: keep the per-instance centre fit and anchor that a
+                                         previous purse_sample call with the same batch and params left
+                                         in this workspace (draws more trajectories without refitting;
+                                         inst_status is left as that call wrote it) */
+
+/*
+ * A ragged batch of PURSE instances.  Instance j owns keypoints
+ * [kp_off[j], kp_off[j+1]) and samples [sample_off[j], sample_off[j+1]).
+ */
+typedef struct purse_batch {
+  int32_t n_inst;         /* host: number of instances, >= 1 */
+  int32_t max_kp;         /* host: max over instances of N_j, 3..PURSE_MAX_KP */
+  int64_t total_kp;       /* host: sum of N_j */
+  int64_t total_samples;  /* host: sum of M_j */
+  int64_t max_samples;    /* host: max over instances of M_j */
+  const int32_t *kind;        /* [n_inst] PURSE_KIND_* */
+  const int32_t *n_kp;        /* [n_inst] N_j */
+  const int64_t *kp_off;      /* [n_inst+1] prefix sums of N_j */
+  const int64_t *sample_off;  /* [n_inst+1] prefix sums of M_j */
+  const float *model_pts;     /* [total_kp][3] a_i or Z_i, metres, model frame */
+  const float *centres;       /* [total_kp][3] b_i (m) | (z_i.x, z_i.y, unused) (px) */
+  const float *shapes;        /* [total_kp][4] Lambda_i row-major (2D-3D, px^-2); ignored for 3D-3D */
+  const float *bounds;        /* [total_kp] beta_i >= 0 (m for 3D-3D, Lambda-units for 2D-3D) */
+  const float *intrinsics;    /* [n_inst][4] fx, fy, cx, cy (2D-3D; ignored for 3D-3D) */
+  const uint64_t *seed;       /* [n_inst] Philox key word of each instance */
+} purse_batch;
+
+/* Method parameters (see purse_default_params for the defaults). */
+typedef struct purse_params {
+  int32_t n_iters;     /* alternating iterations per trajectory (>= 0) */
+  int32_t n_gn;        /* Gauss-Newton steps per 2D-3D refit (>= 1) */
+  int32_t n_bis;       /* bisection steps of the pull-in (0..30) */
+  int32_t megb_iters;  /* geodesic descent steps T (>= 1) */
+  int32_t megb_avg;    /* iterates averaged for the centre (1..T) */
+  float omega0;        /* initial angular offset (rad) of rotation-seeking trajectories */
+  float v0;            /* initial centre offset (m) of translation-seeking trajectories */
+  float kappa;         /* projection shrink factor in (0, 1] */
+  float tau_abs_3d;    /* feasibility tolerance, metres */
+  float tau_abs_2d;    /* feasibility tolerance, Lambda-units */
+  float z_min;         /* minimum valid depth for 2D-3D (m) */
+  int32_t ckpt_every;  /* checkpoint spacing of the backward recompute (>= 1) */
+  int32_t centre_gn;   /* Gauss-Newton steps of the 2D-3D centre fit */
+  int32_t tile;        /* samples per workgroup: 64, 128, 256 or 512; 0 = library choice */
+  int32_t flags;       /* PURSE_FLAG_* */
+} purse_params;
+
+/* Fill *p with the defaults: n_iters 50, n_gn 2, n_bis 16, megb_iters 4096,
+ * megb_avg 10, omega0 0.5, v0 0.2, kappa 0.999, tau 1e-5 / 1e-4, z_min 1e-3,
+ * ckpt_every 5, centre_gn 10, tile 0, flags 0.  Returns PURSE_E_NULL if p is NULL. */
+purse_status purse_default_params(purse_params *p);
+
+/* Bytes of workspace every call below needs for this batch and params. */
+purse_status purse_workspace_size(const purse_batch *b, const purse_params *p, size_t *bytes);
+
+/*
+ * Boundary samples of every instance (the alternating projection sampler
+ * built from Section "Geometric Structures" and Step I / Step II of
+ * Section "The CLOSURE Algorithm").  Per instance: centre fit (Arun's method
+ * for 3D-3D; DLT then centre_gn Gauss-Newton steps for 2D-3D), pivot and
+ * feasible anchor; per trajectory s: a Philox4x64-10 draw (key (seed, 0),
+ * counter (s, 0, 0, 0)) picks an outward rotation (even s) or shift (odd s),
+ * then n_iters iterations each project every predicted keypoint onto its
+ * ball / ellipse shrunk by kappa and refit the pose, and a final in_purse test
+ * keeps the pose or pulls it back to the boundary by bisection towards the
+ * anchor.
+ *
+ * Outputs (device, caller-owned):
+ *   poses       [total_samples][12] float: R row-major (9), then t (3); the pose
+ *               maps model points into the camera / target frame.
+ *   mask        [total_samples] uint8: PURSE_MASK_* bits.
+ *   inst_status [n_inst] int32: PURSE_INST_* code | flags.
+ */
+purse_status purse_sample(const purse_batch *b, const purse_params *p, float *poses,
+                          uint8_t *mask, int32_t *inst_status, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/*
+ * Minimum enclosing geodesic balls of the feasible samples of each instance
+ * by geodesic gradient descent (Section "Minimum Enclosing Geodesic Ball",
+ * paragraph "Geodesic Gradient Descent"; appendix "Geodesic Gradient
+ * Descent": the step fraction 1/i, the average of the last iterates, the
+ * Frobenius argmax of the Riemannian Danskin theorem's takeaway).  From the
+ * first feasible sample, megb_iters steps each move the rotation centre
+ * along the geodesic towards the farthest sample by 1/i (the translation
+ * centre likewise in R^3); ties go to the lowest sample index.  The centre is
+ * proj_SO3 of the sum (rotation) and the mean (translation) of the last
+ * megb_avg iterates; the radii are the largest geodesic angle and distance
+ * from it, reduced in float64.
+ *
+ * Inputs: poses and mask as written by purse_sample (same batch layout).
+ * Outputs:
+ *   centre      [n_inst][12] float (R row-major, t); NaN for an empty instance.
+ *   radii       [n_inst][2] double: D_hat (rad), d_hat (m); NaN if empty.
+ *   n_feasible  [n_inst] int64.
+ *   trace       [n_inst][megb_iters][2] int32: argmax sample (instance-local
+ *               index) of each step, rotation then translation; -1 if empty.
+ *   inst_status [n_inst] int32: PURSE_INST_EMPTY is OR-ed in for empty instances.
+ */
+purse_status purse_megb(const purse_batch *b, const purse_params *p, const float *poses,
+                        const uint8_t *mask, float *centre, double *radii,
+                        int64_t *n_feasible, int32_t *trace, int32_t *inst_status,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Reverse-mode derivative of the map (measurements) -> (radii, centre) as
+ * computed by purse_sample + purse_megb, with every discrete decision held
+ * fixed (clamp sets, masks, bisection bits, argmax trace).  Only the samples
+ * the trace touches (and the first feasible one) carry cotangent; their
+ * trajectories are recomputed from their Philox counters with checkpoints
+ * every ckpt_every iterations and swept backwards, then through the centre
+ * fit.
+ *
+ * Inputs: poses, mask, trace as produced by the forward calls;
+ *   g_radii  [n_inst][2] double: cotangents of D_hat and d_hat;
+ *   g_centre [n_inst][6] float: cotangent of the centre as a left so(3)
+ *            3-vector at R* followed by the R^3 cotangent of t*.
+ * Outputs (overwritten):
+ *   g_centres [total_kp][3] float: d/d centres (b_i, or z_i in x, y; third unused = 0)
+ *   g_shapes  [total_kp][4] float: d/d Lambda_i, symmetrised (zeros for 3D-3D)
+ *   g_bounds  [total_kp]    float: d/d beta_i
+ */
+purse_status purse_megb_backward(const purse_batch *b, const purse_params *p,
+                                 const float *poses, const uint8_t *mask,
+                                 const int32_t *trace, const double *g_radii,
+                                 const float *g_centre, float *g_centres, float *g_shapes,
+                                 float *g_bounds, void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *purse_status_string(purse_status s);
+
+/* Message of the last PURSE_E_HIP / PURSE_E_BAD_ARG on this thread ("" if none). */
+const char *purse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PURSE_H */

@@ -1,0 +1,245 @@
+// Host side of the C ABI: argument validation, workspace carving, launches.
+// Nothing here allocates device memory or synchronises the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "purse_launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+purse_status fail(purse_status s, const char *msg) {
+  g_last_error = msg;
+  return s;
+}
+
+purse_status hip_check(hipError_t e, const char *where) {
+  if (e == hipSuccess) return PURSE_OK;
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return PURSE_E_HIP;
+}
+
+purse_status check_device() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) {
+    g_last_error = "no HIP device";
+    return PURSE_E_NO_DEVICE;
+  }
+  return PURSE_OK;
+}
+
+purse_status check_batch(const purse_batch *b) {
+  if (!b) return fail(PURSE_E_NULL, "batch is NULL");
+  if (!b->kind || !b->n_kp || !b->kp_off || !b->sample_off || !b->model_pts || !b->centres || !b->shapes ||
+      !b->bounds || !b->intrinsics || !b->seed)
+    return fail(PURSE_E_NULL, "a batch array is NULL");
+  if (b->n_inst < 1 || b->n_inst > 65535) return fail(PURSE_E_BAD_ARG, "n_inst must be in [1, 65535]");
+  if (b->max_kp < 3 || b->max_kp > PURSE_MAX_KP) return fail(PURSE_E_BAD_ARG, "max_kp must be in [3, 64]");
+  if (b->total_kp < 3 || b->total_kp > (int64_t)b->n_inst * PURSE_MAX_KP)
+    return fail(PURSE_E_BAD_ARG, "total_kp out of range");
+  if (b->total_samples < 1 || b->max_samples < 1 || b->max_samples > b->total_samples ||
+      b->max_samples > (int64_t)INT32_MAX - 1024)
+    return fail(PURSE_E_BAD_ARG, "sample counts out of range");
+  return PURSE_OK;
+}
+
+purse_status check_params(const purse_params *p) {
+  if (!p) return fail(PURSE_E_NULL, "params is NULL");
+  if (p->n_iters < 0 || p->n_iters > 100000) return fail(PURSE_E_BAD_ARG, "n_iters out of range");
+  if (p->n_gn < 1 || p->n_gn > 64) return fail(PURSE_E_BAD_ARG, "n_gn out of range");
+  if (p->n_bis < 0 || p->n_bis > 30) return fail(PURSE_E_BAD_ARG, "n_bis out of range");
+  if (p->megb_iters < 1 || p->megb_iters > (1 << 24)) return fail(PURSE_E_BAD_ARG, "megb_iters out of range");
+  if (p->megb_avg < 1 || p->megb_avg > p->megb_iters) return fail(PURSE_E_BAD_ARG, "megb_avg out of range");
+  if (!(p->kappa > 0.f && p->kappa <= 1.f)) return fail(PURSE_E_BAD_ARG, "kappa must be in (0, 1]");
+  if (!(p->tau_abs_3d >= 0.f) || !(p->tau_abs_2d >= 0.f)) return fail(PURSE_E_BAD_ARG, "tau must be >= 0");
+  if (!(p->z_min > 0.f)) return fail(PURSE_E_BAD_ARG, "z_min must be > 0");
+  if (!(p->omega0 >= 0.f && p->omega0 < 3.f) || !(p->v0 >= 0.f) || !std::isfinite(p->v0))
+    return fail(PURSE_E_BAD_ARG, "omega0 / v0 out of range");
+  if (p->ckpt_every < 1) return fail(PURSE_E_BAD_ARG, "ckpt_every must be >= 1");
+  if (p->centre_gn < 1 || p->centre_gn > 100) return fail(PURSE_E_BAD_ARG, "centre_gn out of range");
+  if (!(p->tile == 0 || p->tile == 64 || p->tile == 128 || p->tile == 256))
+    return fail(PURSE_E_BAD_ARG, "tile must be 0, 64, 128 or 256");
+  return PURSE_OK;
+}
+
+purse::DevBatch dev_batch(const purse_batch *b) {
+  purse::DevBatch d;
+  d.n_inst = b->n_inst;
+  d.max_kp = b->max_kp;
+  d.total_kp = b->total_kp;
+  d.total_samples = b->total_samples;
+  d.max_samples = b->max_samples;
+  d.kind = b->kind;
+  d.n_kp = b->n_kp;
+  d.kp_off = b->kp_off;
+  d.sample_off = b->sample_off;
+  d.model_pts = b->model_pts;
+  d.centres = b->centres;
+  d.shapes = b->shapes;
+  d.bounds = b->bounds;
+  d.intrinsics = b->intrinsics;
+  d.seed = b->seed;
+  return d;
+}
+
+purse::DevParams dev_params(const purse_params *p) {
+  purse::DevParams d;
+  d.n_iters = p->n_iters;
+  d.n_gn = p->n_gn;
+  d.n_bis = p->n_bis;
+  d.megb_iters = p->megb_iters;
+  d.megb_avg = p->megb_avg;
+  d.centre_gn = p->centre_gn;
+  d.ckpt_every = p->ckpt_every;
+  d.flags = p->flags;
+  d.omega0 = p->omega0;
+  d.v0 = p->v0;
+  d.kappa = p->kappa;
+  d.tau3 = p->tau_abs_3d;
+  d.tau2 = p->tau_abs_2d;
+  d.z_min = p->z_min;
+  return d;
+}
+
+size_t backward_bytes(const purse_batch *b, const purse_params *p);
+
+purse::WsLayout layout_for(const purse_batch *b, const purse_params *p) {
+  return purse::ws_layout(b->n_inst, b->total_kp, b->total_samples, backward_bytes(b, p));
+}
+
+purse_status check_ws(const purse_batch *b, const purse_params *p, void *ws, size_t ws_bytes) {
+  if (!ws) return fail(PURSE_E_NULL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % purse::kAlign) return fail(PURSE_E_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < layout_for(b, p).total) return fail(PURSE_E_WORKSPACE, "workspace too small");
+  return PURSE_OK;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+}  // namespace
+
+namespace {
+size_t backward_bytes(const purse_batch *b, const purse_params *p) {
+  (void)b;
+  (void)p;
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+purse_status purse_default_params(purse_params *p) {
+  if (!p) return fail(PURSE_E_NULL, "params is NULL");
+  p->n_iters = 50;
+  p->n_gn = 2;
+  p->n_bis = 16;
+  p->megb_iters = 4096;
+  p->megb_avg = 10;
+  p->omega0 = 0.5f;
+  p->v0 = 0.2f;
+  p->kappa = 0.999f;
+  p->tau_abs_3d = 1e-5f;
+  p->tau_abs_2d = 1e-4f;
+  p->z_min = 1e-3f;
+  p->ckpt_every = 5;
+  p->centre_gn = 10;
+  p->tile = 0;
+  p->flags = 0;
+  return PURSE_OK;
+}
+
+purse_status purse_workspace_size(const purse_batch *b, const purse_params *p, size_t *bytes) {
+  if (!bytes) return fail(PURSE_E_NULL, "bytes is NULL");
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  *bytes = layout_for(b, p).total;
+  return PURSE_OK;
+}
+
+purse_status purse_sample(const purse_batch *b, const purse_params *p, float *poses, uint8_t *mask,
+                          int32_t *inst_status, void *ws, size_t ws_bytes, void *stream) {
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  if (!poses || !mask || !inst_status) return fail(PURSE_E_NULL, "an output is NULL");
+  if ((s = check_ws(b, p, ws, ws_bytes))) return s;
+  if ((s = check_device())) return s;
+  const purse::WsLayout L = layout_for(b, p);
+  const purse::DevBatch db = dev_batch(b);
+  const purse::DevParams dp = dev_params(p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto *inst = at<purse::InstRec>(ws, L.inst);
+  auto *kp = at<purse::KpRec>(ws, L.kp);
+  if (!(p->flags & PURSE_FLAG_REUSE_PROLOGUE)) {
+    purse::launch_prologue(db, dp, inst, kp, inst_status, st);
+    if ((s = hip_check(hipGetLastError(), "prologue launch"))) return s;
+  }
+  const int tile = p->tile ? p->tile : 256;
+  purse::launch_sample(db, dp, inst, kp, poses, mask, tile, b->max_samples, st);
+  return hip_check(hipGetLastError(), "sampler launch");
+}
+
+purse_status purse_megb(const purse_batch *b, const purse_params *p, const float *poses, const uint8_t *mask,
+                        float *centre, double *radii, int64_t *n_feasible, int32_t *trace, int32_t *inst_status,
+                        void *ws, size_t ws_bytes, void *stream) {
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  if (!poses || !mask || !centre || !radii || !n_feasible || !trace || !inst_status)
+    return fail(PURSE_E_NULL, "an argument is NULL");
+  if ((s = check_ws(b, p, ws, ws_bytes))) return s;
+  if ((s = check_device())) return s;
+  const purse::WsLayout L = layout_for(b, p);
+  const purse::DevBatch db = dev_batch(b);
+  const purse::DevParams dp = dev_params(p);
+  purse::launch_megb(db, dp, poses, mask, at<purse::MegbRec>(ws, L.megb), at<float4>(ws, L.quat),
+                     at<float4>(ws, L.trans), at<float>(ws, L.dref), centre, radii, n_feasible, trace, inst_status,
+                     b->max_samples, b->total_samples, static_cast<hipStream_t>(stream));
+  return hip_check(hipGetLastError(), "megb launch");
+}
+
+purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, const float *poses,
+                                 const uint8_t *mask, const int32_t *trace, const double *g_radii,
+                                 const float *g_centre, float *g_centres, float *g_shapes, float *g_bounds, void *ws,
+                                 size_t ws_bytes, void *stream) {
+  (void)poses;
+  (void)mask;
+  (void)trace;
+  (void)g_radii;
+  (void)g_centre;
+  (void)g_centres;
+  (void)g_shapes;
+  (void)g_bounds;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  return fail(PURSE_E_BAD_ARG, "purse_megb_backward: not available in this build");
+}
+
+const char *purse_status_string(purse_status s) {
+  switch (s) {
+    case PURSE_OK: return "ok";
+    case PURSE_E_NULL: return "a required pointer is NULL";
+    case PURSE_E_BAD_ARG: return "argument out of range";
+    case PURSE_E_WORKSPACE: return "workspace too small or misaligned";
+    case PURSE_E_NO_DEVICE: return "no usable HIP device";
+    case PURSE_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *purse_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

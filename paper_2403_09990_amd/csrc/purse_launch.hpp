@@ -1,0 +1,22 @@
+// Host-side launchers of the kernels (one per translation unit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "purse_layout.hpp"
+
+namespace purse {
+
+void launch_prologue(const DevBatch &b, const DevParams &p, InstRec *inst, KpRec *kp, int32_t *inst_status,
+                     hipStream_t stream);
+
+// tile: samples per workgroup (64, 128 or 256); max_samples: host bound on M_j.
+void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, float *poses,
+                   uint8_t *mask, int tile, int64_t max_samples, hipStream_t stream);
+
+void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
+                 MegbRec *rec, float4 *quat, float4 *trans, float *dref, float *centre, double *radii,
+                 int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
+                 int64_t total_samples, hipStream_t stream);
+
+}  // namespace purse

@@ -1,0 +1,118 @@
+// Workspace records shared by the host library and the kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/purse.h"
+
+namespace purse {
+
+// Per-keypoint record written by the prologue (48 bytes, read wave-uniformly
+// by the sampler).
+//   3D-3D: m = a_i - abar (centred model point), c = b_i, w unused.
+//   2D-3D: m = Z_i, c = (z_i.x, z_i.y, 0), w = (u00, u01, u11) with
+//          [[u00, u01], [0, u11]]^T [[u00, u01], [0, u11]] = Lambda_i.
+//   kb = kappa beta_i, kb2 = kb^2, bt = beta_i + tau_abs.
+struct KpRec {
+  float m[3];
+  float c[3];
+  float w[3];
+  float kb;
+  float kb2;
+  float bt;
+};
+static_assert(sizeof(KpRec) == 48, "KpRec layout");
+
+// Per-instance record written by the prologue.
+struct InstRec {
+  int32_t kind, n_kp, status, has_anchor;
+  int64_t kp_off, sample_off, n_samples;
+  uint64_t seed;
+  float Rc[9], tc[3];   // centre pose x_c
+  float oc[3];          // pivot o_c = R_c mean(model) + t_c
+  float Ra[9], ta[3];   // feasible anchor
+  float abar[3];        // model centroid
+  float K[4];           // fx, fy, cx, cy
+  float pad[2];
+};
+
+// MEGB per-instance scratch.
+struct MegbRec {
+  int32_t first;          // first feasible instance-local index (INT32_MAX if none)
+  int32_t n_rescan[2];    // diagnostics: rescans per chain
+  int32_t n_global[2];    // diagnostics: full-scan stages per chain
+  int32_t pad;
+  unsigned long long n_feasible;
+  unsigned long long max_rot;    // float64 bit pattern of max ||R* - R_s||_F^2
+  unsigned long long max_trans;  // float64 bit pattern of max ||t* - t_s||^2
+  float centre[12];       // R* row-major, t*
+};
+
+constexpr size_t kAlign = 256;
+__host__ __device__ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct WsLayout {
+  size_t inst, kp, megb, quat, trans, dref, bwd, total;
+};
+
+// Byte offsets of the workspace regions.  The backward region is sized by
+// the caller of ws_layout (bwd_bytes).
+inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, size_t bwd_bytes) {
+  WsLayout L;
+  size_t o = 0;
+  L.inst = o;
+  o += align_up(sizeof(InstRec) * (size_t)n_inst);
+  L.kp = o;
+  o += align_up(sizeof(KpRec) * (size_t)total_kp);
+  L.megb = o;
+  o += align_up(sizeof(MegbRec) * (size_t)n_inst);
+  L.quat = o;
+  o += align_up(16 * (size_t)total_samples);
+  L.trans = o;
+  o += align_up(16 * (size_t)total_samples);
+  L.dref = o;
+  o += align_up(8 * (size_t)total_samples);  // one float per sample per chain
+  L.bwd = o;
+  o += align_up(bwd_bytes);
+  L.total = o;
+  return L;
+}
+
+// Instance-local sample range [off, off + M) clipped to a valid range of the
+// batch (an inconsistent prefix array yields M = 0).
+__host__ __device__ inline void sample_range(const int64_t *sample_off, int j, int64_t total, int64_t max_m,
+                                             int64_t &off, int64_t &M) {
+  off = sample_off[j];
+  M = sample_off[j + 1] - off;
+  if (off < 0 || M < 0 || M > max_m || off + M > total) {
+    off = 0;
+    M = 0;
+  }
+}
+
+// Kernel-side view of the batch (device pointers + host scalars).
+struct DevBatch {
+  int32_t n_inst;
+  int32_t max_kp;
+  int64_t total_kp;
+  int64_t total_samples;
+  int64_t max_samples;
+  const int32_t *kind;
+  const int32_t *n_kp;
+  const int64_t *kp_off;
+  const int64_t *sample_off;
+  const float *model_pts;
+  const float *centres;
+  const float *shapes;
+  const float *bounds;
+  const float *intrinsics;
+  const uint64_t *seed;
+};
+
+struct DevParams {
+  int32_t n_iters, n_gn, n_bis, megb_iters, megb_avg, centre_gn, ckpt_every, flags;
+  float omega0, v0, kappa, tau3, tau2, z_min;
+};
+
+}  // namespace purse

@@ -1,0 +1,496 @@
+// Minimum enclosing geodesic balls of the feasible samples by geodesic
+// gradient descent, one workgroup per (instance, chain): chain 0 is the
+// rotation ball (unit quaternions, Frobenius key ||C - R||_F^2 =
+// 2 |a - b|^2 |a + b|^2), chain 1 the translation ball.
+//
+// Each step needs the farthest sample from the current centre.  The chain
+// keeps a shell of candidates in LDS: at a rescan with reference centre C_ref
+// and radius r_ref it keeps every sample with d(C_ref, s) >= theta (theta from
+// a histogram, so the shell fits).  By the triangle inequality a sample
+// outside the shell is at most theta + d(C, C_ref) from the current centre C,
+// so when the shell's best exceeds that bound (with a rounding slack) the
+// shell argmax is the argmax over all samples and the step is exact; when it
+// does not, the chain rescans around the current centre.  Steps on the shell
+// run in one wavefront with shuffles only.
+#include <float.h>
+
+#include "purse_launch.hpp"
+#include "purse_traj.hpp"
+
+namespace purse {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kBins = 256;
+constexpr int kGlobalSteps = 256;
+
+__device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
+  return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
+}
+
+__device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
+  if (chain == 0) {
+    float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
+    float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
+    return 2.f * (m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3) * (p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3);
+  }
+  float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
+  return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+// C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
+__device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
+  if (chain == 1) {
+    float fi = (float)i;
+    return make_float4(a.x + (b.x - a.x) / fi, a.y + (b.y - a.y) / fi, a.z + (b.z - a.z) / fi, 1.f);
+  }
+  float dt = a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+  if (dt < 0.f) b = make_float4(-b.x, -b.y, -b.z, -b.w);
+  float4 ac = make_float4(a.x, -a.y, -a.z, -a.w);
+  float4 r = quat_mul(ac, b);
+  float sn = sqrtf(r.y * r.y + r.z * r.z + r.w * r.w);
+  if (!(sn > 0.f)) return a;
+  float half = atan2f(sn, r.x);
+  float ph = half / (float)i;
+  float s, c;
+  sincosf(ph, &s, &c);
+  float f = s / sn;
+  float4 e = make_float4(c, f * r.y, f * r.z, f * r.w);
+  float4 q = quat_mul(a, e);
+  float nn = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  return make_float4(q.x * nn, q.y * nn, q.z * nn, q.w * nn);
+}
+
+// (key desc, id asc) comparison
+__device__ __forceinline__ bool better(float k1, int i1, float k2, int i2) {
+  return k1 > k2 || (k1 == k2 && i1 < i2);
+}
+
+__device__ __forceinline__ void wave_argmax(float &k, int &id, int &e) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    float k2 = __shfl_xor(k, off, 64);
+    int i2 = __shfl_xor(id, off, 64);
+    int e2 = __shfl_xor(e, off, 64);
+    if (better(k2, i2, k, id)) {
+      k = k2;
+      id = i2;
+      e = e2;
+    }
+  }
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+}  // namespace
+
+__global__ void k_megb_init(int n_inst, MegbRec *rec) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_inst) return;
+  rec[j].first = INT32_MAX;
+  rec[j].n_feasible = 0ull;
+  rec[j].max_rot = 0ull;
+  rec[j].max_trans = 0ull;
+}
+
+// Per sample: quaternion (w >= 0; w = -2 marks an infeasible sample) and
+// translation (w = 1 feasible, 0 not); first feasible index; feasible count.
+__global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict__ sample_off, int64_t total,
+                                                      int64_t max_m, const float *__restrict__ poses,
+                                                      const uint8_t *__restrict__ mask, MegbRec *rec,
+                                                      float4 *quat, float4 *trans) {
+  const int j = blockIdx.y;
+  int64_t off, M;
+  sample_range(sample_off, j, total, max_m, off, M);
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ int cnt[kWaves];
+  __shared__ int firsts[kWaves];
+  int feas = 0, first = INT32_MAX;
+  if (s < M) {
+    const int64_t g = off + s;
+    if (mask[g] & PURSE_MASK_FEASIBLE) {
+      const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * g);
+      float4 a = pp[0], b = pp[1], c = pp[2];
+      float R[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
+      quat[g] = quat_from_rot(R);
+      trans[g] = make_float4(c.y, c.z, c.w, 1.f);
+      feas = 1;
+      first = (int)s;
+    } else {
+      quat[g] = make_float4(-2.f, 0.f, 0.f, 0.f);
+      trans[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  // block reduction, one atomic per block
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    feas += __shfl_xor(feas, o, 64);
+    first = min(first, __shfl_xor(first, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    cnt[w] = feas;
+    firsts[w] = first;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0, f = INT32_MAX;
+    for (int k = 0; k < kWaves; ++k) {
+      c += cnt[k];
+      f = min(f, firsts[k]);
+    }
+    if (c) {
+      atomicAdd(&rec[j].n_feasible, (unsigned long long)c);
+      atomicMin(&rec[j].first, f);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+                                                       const float4 *__restrict__ quat,
+                                                       const float4 *__restrict__ trans, MegbRec *rec,
+                                                       float *dref_all, int64_t total_samples, int32_t *trace,
+                                                       int T, int avg, int cap, int no_prune) {
+  extern __shared__ float4 sh_pt[];
+  int *sh_id = reinterpret_cast<int *>(sh_pt + cap);
+  __shared__ unsigned int hist[kBins];
+  __shared__ float red_k[2][kWaves];
+  __shared__ int red_i[2][kWaves];
+  __shared__ float4 st_C;
+  __shared__ int st_i;
+  __shared__ float st_theta;
+  __shared__ int st_mode;  // 0 shell in LDS, 1 scan of every sample
+  __shared__ unsigned int sh_n;
+
+  const int j = blockIdx.x >> 1;
+  const int chain = blockIdx.x & 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t off, M64;
+  sample_range(sample_off, j, total_samples, max_m, off, M64);
+  const int M = (int)M64;
+  const float4 *D = (chain == 0 ? quat : trans) + off;
+  float *dref = dref_all + chain * total_samples + off;
+  int32_t *tr = trace + (int64_t)j * T * 2 + chain;
+  const int first = rec[j].first;
+  if (first == INT32_MAX) {
+    for (int k = tid; k < T; k += kBlock) tr[2 * k] = -1;
+    return;
+  }
+  const int n_feas = (int)rec[j].n_feasible;
+  if (tid == 0) {
+    st_C = D[first];
+    st_i = 1;
+  }
+  __syncthreads();
+  float acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+  bool stalled = false;
+  int n_rescan = 0, n_global = 0;
+
+  while (true) {
+    const float4 Cref = st_C;
+    const int i0 = st_i;
+    if (i0 > T) break;
+    // ---------------------------------------------------------------- rescan
+    float mx = 0.f;
+    for (int s = tid; s < M; s += kBlock) {
+      float4 a = D[s];
+      float d = -1.f;
+      if (feasible_pt(a, chain)) {
+        d = sqrtf(sqdist(Cref, a, chain));
+        mx = fmaxf(mx, d);
+      }
+      dref[s] = d;
+    }
+    mx = wave_max(mx);
+    if (lane == 0) red_k[0][wave] = mx;
+    __syncthreads();
+    float rref = 0.f;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) rref = fmaxf(rref, red_k[0][k]);
+    // threshold theta: -1 keeps every feasible sample; otherwise the upper
+    // histogram bins that fit the capacity; -2 = no threshold fits
+    if (tid == 0) {
+      st_theta = -1.f;
+      st_mode = ((no_prune || stalled) && n_feas > cap) ? 1 : 0;
+    }
+    __syncthreads();
+    if (st_mode == 0 && n_feas > cap) {
+      float lo = 0.f, hi = rref;
+      for (int level = 0; level < 2; ++level) {
+        const float wdt = (hi - lo) / (float)kBins;
+        if (!(wdt > 0.f)) {
+          if (tid == 0) st_theta = -2.f;
+          break;
+        }
+        for (int k = tid; k < kBins; k += kBlock) hist[k] = 0u;
+        __syncthreads();
+        for (int s = tid; s < M; s += kBlock) {
+          float d = dref[s];
+          if (d >= lo) {
+            int bb = (int)((d - lo) / wdt);
+            bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
+            atomicAdd(&hist[bb], 1u);
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int cum = 0, bb = kBins - 1;
+          for (; bb >= 0; --bb) {
+            if (cum + (int)hist[bb] > cap) break;
+            cum += (int)hist[bb];
+          }
+          st_theta = (bb < kBins - 1) ? lo + (float)(bb + 1) * wdt : -2.f;
+        }
+        __syncthreads();
+        if (st_theta != -2.f) break;
+        lo = lo + (float)(kBins - 1) * wdt;  // refine inside the top bin
+      }
+      if (tid == 0 && st_theta == -2.f) st_mode = 1;
+      __syncthreads();
+    }
+    const float theta = st_theta;
+    // ---------------------------------------------------------------- collect
+    if (st_mode == 0) {
+      if (tid == 0) sh_n = 0u;
+      __syncthreads();
+      for (int s = tid; s < M; s += kBlock) {
+        float d = dref[s];
+        if (d >= 0.f && d >= theta) {
+          unsigned int pos = atomicAdd(&sh_n, 1u);
+          if (pos < (unsigned)cap) {
+            sh_pt[pos] = D[s];
+            sh_id[pos] = s;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0 && sh_n > (unsigned)cap) st_mode = 1;
+      __syncthreads();
+    }
+    const float slack = 4e-6f * rref;
+    ++n_rescan;
+    if (st_mode == 0) {
+      // ---------------------------------------------------------- shell steps
+      const int K = (int)sh_n;
+      if (wave == 0) {
+        float4 C = Cref;
+        int i = i0;
+        while (i <= T) {
+          float bk = -1.f;
+          int bi = INT32_MAX, be = 0;
+          for (int e = lane; e < K; e += 64) {
+            float k = sqdist(C, sh_pt[e], chain);
+            int id = sh_id[e];
+            if (better(k, id, bk, bi)) {
+              bk = k;
+              bi = id;
+              be = e;
+            }
+          }
+          wave_argmax(bk, bi, be);
+          if (theta >= 0.f) {
+            float dC = sqrtf(sqdist(C, Cref, chain));
+            if (!(sqrtf(bk) > theta + dC + slack)) break;  // the shell no longer suffices
+          }
+          const float4 pt = sh_pt[be];
+          C = geodesic_step(C, pt, i, chain);
+          if (lane == 0) tr[2 * (i - 1)] = bi;
+          if (i > T - avg) {
+            if (chain == 0) {
+              float Rm[9];
+              rot_from_quat(C, Rm);
+#pragma unroll
+              for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
+            } else {
+              acc[0] += C.x;
+              acc[1] += C.y;
+              acc[2] += C.z;
+            }
+          }
+          ++i;
+        }
+        if (lane == 0) {
+          st_C = C;
+          st_i = i;
+        }
+      }
+      __syncthreads();
+      stalled = st_i == i0;
+    } else {
+      // ---------------------------------------------------- global-scan steps
+      // (every feasible sample, all waves; at most kGlobalSteps per stage)
+      float4 C = Cref;
+      int i = i0;
+      int par = 0;
+      ++n_global;
+      stalled = false;
+      const int i_end = no_prune ? T : min(T, i0 + kGlobalSteps - 1);
+      while (i <= i_end) {
+        float bk = -1.f;
+        int bi = INT32_MAX, be = 0;
+        for (int s = tid; s < M; s += kBlock) {
+          float4 a = D[s];
+          if (feasible_pt(a, chain)) {
+            float k = sqdist(C, a, chain);
+            if (better(k, s, bk, bi)) {
+              bk = k;
+              bi = s;
+            }
+          }
+        }
+        wave_argmax(bk, bi, be);
+        if (lane == 0) {
+          red_k[par][wave] = bk;
+          red_i[par][wave] = bi;
+        }
+        __syncthreads();
+        bk = red_k[par][0];
+        bi = red_i[par][0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w)
+          if (better(red_k[par][w], red_i[par][w], bk, bi)) {
+            bk = red_k[par][w];
+            bi = red_i[par][w];
+          }
+        par ^= 1;
+        C = geodesic_step(C, D[bi], i, chain);
+        if (tid == 0) tr[2 * (i - 1)] = bi;
+        if (i > T - avg && wave == 0) {
+          if (chain == 0) {
+            float Rm[9];
+            rot_from_quat(C, Rm);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
+          } else {
+            acc[0] += C.x;
+            acc[1] += C.y;
+            acc[2] += C.z;
+          }
+        }
+        ++i;
+      }
+      if (tid == 0) {
+        st_C = C;
+        st_i = i;
+      }
+      __syncthreads();
+    }
+  }
+  // ------------------------------------------------------------------ centre
+  if (tid == 0) {
+    rec[j].n_rescan[chain] = n_rescan;
+    rec[j].n_global[chain] = n_global;
+    if (chain == 0) {
+      double Md[9], Rd[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Md[k] = (double)acc[k];
+      polar_so3<double>(Md, Rd, 12);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) rec[j].centre[k] = (float)Rd[k];
+    } else {
+      const int na = avg < T ? avg : T;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) rec[j].centre[9 + k] = acc[k] / (float)na;
+    }
+  }
+}
+
+// float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.
+__global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict__ sample_off, int64_t total,
+                                                       int64_t max_m, const float *__restrict__ poses,
+                                                       const uint8_t *__restrict__ mask, MegbRec *rec) {
+  const int j = blockIdx.y;
+  int64_t off, M;
+  sample_range(sample_off, j, total, max_m, off, M);
+  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  __shared__ double red[2][kWaves];
+  double fr = 0.0, ft = 0.0;
+  if (s < M && rec[j].first != INT32_MAX) {
+    const int64_t g = off + s;
+    if (mask[g] & PURSE_MASK_FEASIBLE) {
+      const float *P = poses + 12 * g;
+      const float *C = rec[j].centre;
+      for (int k = 0; k < 9; ++k) {
+        double d = (double)C[k] - (double)P[k];
+        fr += d * d;
+      }
+      for (int k = 9; k < 12; ++k) {
+        double d = (double)C[k] - (double)P[k];
+        ft += d * d;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    fr = fmax(fr, __shfl_xor(fr, o, 64));
+    ft = fmax(ft, __shfl_xor(ft, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = fr;
+    red[1][w] = ft;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWaves; ++k) {
+      fr = fmax(fr, red[0][k]);
+      ft = fmax(ft, red[1][k]);
+    }
+    fr = fmax(fr, red[0][0]);
+    ft = fmax(ft, red[1][0]);
+    if (fr > 0.0) atomicMax(&rec[j].max_rot, (unsigned long long)__double_as_longlong(fr));
+    if (ft > 0.0) atomicMax(&rec[j].max_trans, (unsigned long long)__double_as_longlong(ft));
+  }
+}
+
+__global__ void k_megb_final(int n_inst, const MegbRec *rec, float *centre, double *radii, int64_t *n_feasible,
+                             int32_t *inst_status) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_inst) return;
+  const MegbRec r = rec[j];
+  n_feasible[j] = (int64_t)r.n_feasible;
+  if (r.first == INT32_MAX) {
+    const float nanf_ = __int_as_float(0x7fc00000);
+    for (int k = 0; k < 12; ++k) centre[12 * j + k] = nanf_;
+    radii[2 * j] = radii[2 * j + 1] = __longlong_as_double(0x7ff8000000000000ll);
+    if ((inst_status[j] & 0xFF) == PURSE_INST_OK) inst_status[j] = (inst_status[j] & ~0xFF) | PURSE_INST_EMPTY;
+    return;
+  }
+  for (int k = 0; k < 12; ++k) centre[12 * j + k] = r.centre[k];
+  double fr = __longlong_as_double((long long)r.max_rot);
+  double ft = __longlong_as_double((long long)r.max_trans);
+  double x = sqrt(fr) / (2.0 * sqrt(2.0));
+  radii[2 * j] = 2.0 * asin(x < 1.0 ? x : 1.0);
+  radii[2 * j + 1] = sqrt(ft);
+}
+
+void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask, MegbRec *rec,
+                 float4 *quat, float4 *trans, float *dref, float *centre, double *radii, int64_t *n_feasible,
+                 int32_t *trace, int32_t *inst_status, int64_t max_samples, int64_t total_samples,
+                 hipStream_t stream) {
+  const int n = b.n_inst;
+  hipLaunchKernelGGL(k_megb_init, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec);
+  dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
+  hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
+                     mask, rec, quat, trans);
+  const int cap = 2048;
+  const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
+  const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
+  hipLaunchKernelGGL(k_megb_chain, dim3(2 * n), dim3(kBlock), lds, stream, b.sample_off, max_samples, quat, trans,
+                     rec, dref,
+                     total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
+  hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
+                     poses, mask, rec);
+  hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,
+                     n_feasible, inst_status);
+}
+
+}  // namespace purse

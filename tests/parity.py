@@ -1,0 +1,93 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and the FP64 oracle on the same float32 inputs, and compare them."""
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from oracle.megb import megb as oracle_megb_fn
+from oracle.params import OracleParams
+from oracle.purse import Problem, sample as oracle_sample
+
+ROT_TOL = 1e-4      # rad, per sample
+TRANS_TOL = 1e-4    # m (3D-3D) or m (2D-3D translation), per sample
+RADIUS_RTOL = 1e-3  # MEGB radii, relative
+CENTRE_TOL = 1e-4   # MEGB centre, rad and m
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def as_f32_instance(inst):
+    """The instance as the device sees it: every float rounded to float32."""
+    return dataclasses.replace(inst, model_pts=f32(inst.model_pts), centres=f32(inst.centres),
+                               shapes=f32(inst.shapes), bounds=f32(inst.bounds),
+                               intrinsics=f32(inst.intrinsics))
+
+
+def oracle_params(gp) -> OracleParams:
+    """The oracle's parameters with the same (float32) values the device uses."""
+    return OracleParams(n_iters=gp.n_iters, n_gn=gp.n_gn, n_bis=gp.n_bis,
+                        megb_iters=gp.megb_iters, megb_avg=gp.megb_avg,
+                        omega0=float(np.float32(gp.omega0)), v0=float(np.float32(gp.v0)),
+                        kappa=float(np.float32(gp.kappa)),
+                        tau_abs_3d=float(np.float32(gp.tau_abs_3d)),
+                        tau_abs_2d=float(np.float32(gp.tau_abs_2d)),
+                        z_min=float(np.float32(gp.z_min)), centre_gn=gp.centre_gn)
+
+
+def run_gpu(batch, params, with_megb=True):
+    import paper_2403_09990_amd as P
+    db = P.DeviceBatch(batch)
+    ws = P.workspace(db, params)
+    out = P.sample(db, params, ws=ws)
+    res = dict(db=db, ws=ws, poses=out["poses"], mask=out["mask"], inst_status=out["inst_status"])
+    if with_megb:
+        m = P.megb(db, params, out["poses"], out["mask"], out["inst_status"], ws=ws)
+        res.update(m)
+    torch.cuda.synchronize()
+    return res
+
+
+def rot_angle(Ra, Rb):
+    """2 asin(||Ra - Rb||_F / (2 sqrt 2)), elementwise over (M,3,3)."""
+    f = np.sqrt(((Ra - Rb) ** 2).sum((-1, -2)))
+    return 2 * np.arcsin(np.minimum(1.0, f / (2 * math.sqrt(2))))
+
+
+def compare_samples(gpu_poses, gpu_mask, ora_poses, ora_mask, max_flip_frac=2e-3):
+    """Per-sample agreement.  Returns stats; asserts the bar: feasibility bits
+    equal except for a few decision flips, and every sample whose bits agree
+    within ROT_TOL / TRANS_TOL except for a few bisection-decision flips."""
+    gp = np.asarray(gpu_poses, dtype=np.float64)
+    op = np.asarray(ora_poses, dtype=np.float64)
+    gm = np.asarray(gpu_mask).astype(np.int64)
+    om = np.asarray(ora_mask).astype(np.int64)
+    same = (gm & 1) == (om & 1)
+    ang = rot_angle(gp[:, :9].reshape(-1, 3, 3), op[:, :9].reshape(-1, 3, 3))
+    dt = np.linalg.norm(gp[:, 9:] - op[:, 9:], axis=1)
+    bad = same & ((ang > ROT_TOL) | (dt > TRANS_TOL))
+    stats = dict(n=len(gm), mask_flips=int((~same).sum()), pose_out=int(bad.sum()),
+                 max_rot=float(ang[same].max()) if same.any() else 0.0,
+                 max_trans=float(dt[same].max()) if same.any() else 0.0,
+                 median_rot=float(np.median(ang[same])) if same.any() else 0.0,
+                 pulled=int(((om & 2) != 0).sum()))
+    n = len(gm)
+    assert stats["mask_flips"] <= max(1, int(max_flip_frac * n)), stats
+    assert stats["pose_out"] <= max(1, int(max_flip_frac * n)), stats
+    return stats
+
+
+def oracle_for_instance(inst, gp, sample_ids):
+    prob = Problem.from_instance(as_f32_instance(inst))
+    return oracle_sample(prob, oracle_params(gp), inst.seed, len(sample_ids), sample_ids=sample_ids)
+
+
+def oracle_megb(poses, mask, T, avg):
+    P = torch.as_tensor(np.asarray(poses, dtype=np.float64))
+    sel = torch.nonzero(torch.as_tensor((np.asarray(mask) & 1) != 0))[:, 0]
+    R = P[sel, :9].reshape(-1, 3, 3)
+    t = P[sel, 9:]
+    return oracle_megb_fn(R, t, sel, T, avg)
