@@ -52,17 +52,26 @@ MASK_PULLED_IN = 2
 MASK_FAILED = 4
 
 
+def _t(x) -> torch.Tensor:
+    """float64 tensor; torch inputs keep their autograd graph."""
+    if isinstance(x, torch.Tensor):
+        return x.to(DT)
+    return torch.as_tensor(np.asarray(x), dtype=DT)
+
+
 class Problem:
     """One PURSE instance as float64 tensors."""
 
     def __init__(self, kind, model_pts, centres, shapes, bounds, intrinsics):
         self.kind = int(kind)
-        self.model = torch.as_tensor(np.asarray(model_pts), dtype=DT).reshape(-1, 3)
-        c = torch.as_tensor(np.asarray(centres), dtype=DT).reshape(-1, 3)
-        self.centres = c if self.kind == KIND_3D3D else c[:, :2].contiguous()
-        self.shapes = torch.as_tensor(np.asarray(shapes), dtype=DT).reshape(-1, 2, 2)
-        self.beta = torch.as_tensor(np.asarray(bounds), dtype=DT).reshape(-1)
-        self.K = torch.as_tensor(np.asarray(intrinsics), dtype=DT).reshape(4)
+        self.model = _t(model_pts).reshape(-1, 3)
+        c = _t(centres)
+        if c.shape[-1] == 3 and self.kind == KIND_2D3D:
+            c = c[:, :2]
+        self.centres = c.reshape(-1, 3) if self.kind == KIND_3D3D else c.reshape(-1, 2)
+        self.shapes = _t(shapes).reshape(-1, 2, 2)
+        self.beta = _t(bounds).reshape(-1)
+        self.K = _t(intrinsics).reshape(4)
 
     @classmethod
     def from_instance(cls, inst):
@@ -116,12 +125,22 @@ def feasible(prob: Problem, R, t, p: OracleParams, margin: float = 1.0):
     return ok
 
 
-def project_targets(prob: Problem, e, r, kappa: float):
+DERIV_EPS = 1e-5
+
+
+def project_targets(prob: Problem, e, r, kappa: float, deriv_convention: bool = False):
     """Move every predicted keypoint onto its ball/ellipse shrunk by kappa:
     q_i = centre_i + s_i e_i with s_i = 1 if r_i <= kappa beta_i else
-    kappa beta_i / r_i (the nearest point of the set in the Lambda metric)."""
+    kappa beta_i / r_i (the nearest point of the set in the Lambda metric).
+
+    deriv_convention: the map used for derivatives, where a constraint within
+    DERIV_EPS (relative) inside its shrunk ball counts as projected.  Converged
+    trajectories end on that boundary, approaching it from outside, so their
+    clamp sits on its kink to rounding; this side is the one the limit takes."""
     kb = kappa * prob.beta
     inside = r <= kb
+    if deriv_convention:
+        inside = r <= kb * (1.0 - DERIV_EPS)
     s = torch.where(inside, torch.ones_like(r), kb / torch.where(inside, torch.ones_like(r), r))
     return prob.centres + s[..., None] * e
 
@@ -197,25 +216,60 @@ def dlt_2d(prob: Problem):
     return proj_so3(Pm[:, :3]), Pm[:, 3] / s
 
 
+def affine_2d(prob: Problem):
+    """Weak-perspective initialisation: least-squares fit of the normalised
+    image points by x_n = A Z + b (a scaled orthographic camera, which the
+    object's small depth range makes a good model); s = mean row norm of A,
+    R = proj_SO3 of the rows of A/s and their cross product, t = (b/s, 1/s)."""
+    fx, fy, cx, cy = prob.K
+    xn = torch.stack([(prob.centres[:, 0] - cx) / fx, (prob.centres[:, 1] - cy) / fy], 1)
+    X = torch.cat([prob.model, torch.ones(prob.n, 1, dtype=DT)], 1)
+    sol = torch.linalg.lstsq(X, xn).solution            # (4, 2)
+    A = sol[:3].T
+    b = sol[3]
+    s = 0.5 * (torch.linalg.norm(A[0]) + torch.linalg.norm(A[1]))
+    r3 = torch.linalg.cross(A[0], A[1]) / (s * s)
+    R = proj_so3(torch.stack([A[0] / s, A[1] / s, r3]))
+    t = torch.cat([b / s, (1.0 / s).reshape(1)])
+    return R, t
+
+
+def gn_cost_2d(prob: Problem, R, t) -> float:
+    e, r, depth = residual(prob, R[None], t[None])
+    return float((r * r).sum().detach())
+
+
 def centre_fit(prob: Problem, p: OracleParams):
     """Maximum-likelihood centre x_c (eq. MLE with rho = ||.||^2_Lambda).
-    3D-3D: Arun's method on all N pairs.  2D-3D: DLT, then `centre_gn`
-    Gauss-Newton steps towards the ellipse centres, each about the pivot
-    R Zbar + t of the current pose.  Returns (R, t, ok)."""
+    3D-3D: Arun's method on all N pairs.  2D-3D: `centre_gn` Gauss-Newton
+    steps towards the ellipse centres, each about the pivot R Zbar + t of the
+    current pose, from two initialisations, the DLT and the weak-perspective
+    fit; the successful fit with the lower cost is kept (ties: the DLT one).
+    Returns (R, t, ok)."""
     if prob.kind == KIND_3D3D:
         R, t = kabsch(prob.model, prob.centres[None])
         return R[0], t[0], True
-    R, t = dlt_2d(prob)
-    R, t = R[None], t[None]
-    ok = True
+    best = None
     zbar = prob.model.mean(0)
-    for _ in range(p.centre_gn):
-        o = R @ zbar + t
-        R, t, okk = gn_step_2d(prob, R, t, prob.centres[None], o, p.z_min)
-        ok = ok and bool(okk.all())
-    P = transform(prob, R, t)
-    ok = ok and bool((P[..., 2] > p.z_min).all())
-    return R[0], t[0], ok
+    # the initialisations only start the fit; their influence is below rounding
+    # after the Gauss-Newton steps, and derivatives are taken at the converged fit
+    for init in (dlt_2d, affine_2d):
+        R, t = init(prob)
+        R, t = R.detach()[None], t.detach()[None]
+        ok = True
+        for _ in range(p.centre_gn):
+            o = R @ zbar + t
+            R, t, okk = gn_step_2d(prob, R, t, prob.centres[None], o, p.z_min)
+            ok = ok and bool(okk.all())
+        P = transform(prob, R, t)
+        ok = ok and bool((P[..., 2] > p.z_min).all())
+        if ok:
+            cost = gn_cost_2d(prob, R[0], t[0])
+            if best is None or cost < best[2]:
+                best = (R[0], t[0], cost)
+    if best is None:
+        return R[0], t[0], False
+    return best[0], best[1], True
 
 
 def check_instance(prob: Problem) -> int:
@@ -290,7 +344,7 @@ def initial_poses(pro: dict, p: OracleParams, seed: int, ids: np.ndarray):
     return R0, t0
 
 
-def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams):
+def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams, deriv_convention: bool = False):
     """n_iters alternating iterations from (R, t): project every keypoint onto
     its constraint (shrunk by kappa), then refit the pose (Arun for 3D-3D,
     n_gn Gauss-Newton steps about o_c for 2D-3D).  A 2D-3D trajectory whose
@@ -300,7 +354,7 @@ def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams):
     o = o_c.expand(M, 3)
     for _ in range(p.n_iters):
         e, r, _ = residual(prob, R, t)
-        q = project_targets(prob, e, r, p.kappa)
+        q = project_targets(prob, e, r, p.kappa, deriv_convention)
         if prob.kind == KIND_3D3D:
             R, t = kabsch(prob.model, q)
         else:
@@ -312,22 +366,27 @@ def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams):
     return R, t, failed
 
 
-def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams):
+def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None):
     """Bisection on the geodesic segment x(l) = (R_a Exp(l Log(R_a^T R)),
     t_a + l (t - t_a)) from the feasible anchor (l = 0) to the infeasible end
-    (l = 1); returns x(lo) after n_bis steps, which is in S."""
+    (l = 1); returns x(lo) after n_bis steps, which is in S, and lo.  With
+    lo_fixed the bisection's outcome is taken as given (frozen decisions)."""
     w = log_so3(Ra.transpose(-1, -2) @ R)
     M = R.shape[0]
-    lo = torch.zeros(M, dtype=DT)
-    hi = torch.ones(M, dtype=DT)
-    for _ in range(p.n_bis):
-        mid = 0.5 * (lo + hi)
-        Rm = Ra @ exp_so3(mid[:, None] * w)
-        tm = ta + mid[:, None] * (t - ta)
-        f = feasible(prob, Rm, tm, p)
-        lo = torch.where(f, mid, lo)
-        hi = torch.where(f, hi, mid)
-    return Ra @ exp_so3(lo[:, None] * w), ta + lo[:, None] * (t - ta)
+    if lo_fixed is None:
+        lo = torch.zeros(M, dtype=DT)
+        hi = torch.ones(M, dtype=DT)
+        with torch.no_grad():
+            for _ in range(p.n_bis):
+                mid = 0.5 * (lo + hi)
+                Rm = Ra @ exp_so3(mid[:, None] * w)
+                tm = ta + mid[:, None] * (t - ta)
+                f = feasible(prob, Rm, tm, p)
+                lo = torch.where(f, mid, lo)
+                hi = torch.where(f, hi, mid)
+    else:
+        lo = torch.as_tensor(np.asarray(lo_fixed), dtype=DT)
+    return Ra @ exp_so3(lo[:, None] * w), ta + lo[:, None] * (t - ta), lo
 
 
 def sample(prob: Problem, p: OracleParams, seed: int, n_samples: int,
@@ -350,14 +409,16 @@ def sample(prob: Problem, p: OracleParams, seed: int, n_samples: int,
     mask = torch.where(feas, MASK_FEASIBLE, 0)
     mask = torch.where(failed, MASK_FAILED, mask)
     need = ~feas & ~failed
+    lo_out = torch.full((M,), -1.0, dtype=DT)
     if pro["R_a"] is not None and bool(need.any()):
         idx = torch.nonzero(need)[:, 0]
-        Rb, tb = pull_in(prob, pro["R_a"], pro["t_a"], R[idx], t[idx], p)
+        Rb, tb, lo = pull_in(prob, pro["R_a"], pro["t_a"], R[idx], t[idx], p)
         R = R.clone()
         t = t.clone()
         R[idx] = Rb
         t[idx] = tb
+        lo_out[idx] = lo
         mask[idx] = MASK_FEASIBLE | MASK_PULLED_IN
     poses = torch.cat([R.reshape(M, 9), t], 1)
     return dict(poses=poses, mask=mask.to(torch.uint8), prologue=pro,
-                status=pro["status"])
+                status=pro["status"], lo=lo_out)

@@ -68,6 +68,18 @@ def proj_so3(M: torch.Tensor) -> torch.Tensor:
     return U @ (D[..., :, None] * Vh)
 
 
+def proj_so3_newton(M: torch.Tensor, iters: int = 12) -> torch.Tensor:
+    """The same nearest rotation for det(M) > 0 by the Newton iteration
+    X <- (X + X^-T)/2 on the polar factor (scaled to unit determinant first).
+    Used where derivatives are needed and M is close to a multiple of a
+    rotation: there the singular values are nearly equal and the SVD's own
+    derivative is ill-conditioned, while this iteration's is not."""
+    X = M / torch.linalg.det(M).abs().pow(1.0 / 3.0)
+    for _ in range(iters):
+        X = 0.5 * (X + torch.linalg.inv(X).transpose(-1, -2))
+    return X
+
+
 def angle(C: torch.Tensor, R: torch.Tensor) -> torch.Tensor:
     """Geodesic distance on SO(3), 2 asin(||C - R||_F / (2 sqrt 2))."""
     f = torch.sqrt(((C - R) ** 2).sum((-1, -2)))

@@ -24,7 +24,13 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBins = 256;
-constexpr int kGlobalSteps = 256;
+constexpr int kGlobalSteps = 64;
+constexpr int kChainBlock = 1024;
+constexpr int kChainWaves = kChainBlock / 64;
+constexpr int kUnroll = 8;
+constexpr int kCap = 3072;
+constexpr int kMaxChunks = kCap / 64;
+constexpr int kEarlySteps = 32;
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
   return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
@@ -79,6 +85,20 @@ __device__ __forceinline__ void wave_argmax(float &k, int &id, int &e) {
       id = i2;
       e = e2;
     }
+  }
+}
+
+// Running sum of the last iterates: rotation matrices (chain 0) or centres.
+__device__ __forceinline__ void accumulate_iterate(float4 C, int chain, float acc[9]) {
+  if (chain == 0) {
+    float Rm[9];
+    rot_from_quat(C, Rm);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
+  } else {
+    acc[0] += C.x;
+    acc[1] += C.y;
+    acc[2] += C.z;
   }
 }
 
@@ -152,19 +172,24 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
-                                                       const float4 *__restrict__ quat,
-                                                       const float4 *__restrict__ trans, MegbRec *rec,
-                                                       float *dref_all, int64_t total_samples, int32_t *trace,
-                                                       int T, int avg, int cap, int no_prune) {
+// One workgroup of kChainBlock threads per (instance, chain).
+__global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+                                                            const float4 *__restrict__ quat,
+                                                            const float4 *__restrict__ trans, MegbRec *rec,
+                                                            float *dref_all, int64_t total_samples,
+                                                            int32_t *trace, int T, int avg, int cap,
+                                                            int no_prune) {
   extern __shared__ float4 sh_pt[];
   int *sh_id = reinterpret_cast<int *>(sh_pt + cap);
   __shared__ unsigned int hist[kBins];
-  __shared__ float red_k[2][kWaves];
-  __shared__ int red_i[2][kWaves];
+  __shared__ unsigned int cursor[kBins];
+  __shared__ float chunk_ub[kMaxChunks];
+  __shared__ float red_k[2][kChainWaves];
+  __shared__ int red_i[2][kChainWaves];
   __shared__ float4 st_C;
   __shared__ int st_i;
-  __shared__ float st_theta;
+  __shared__ float st_theta, st_lo, st_w;
+  __shared__ int st_bstar;
   __shared__ int st_mode;  // 0 shell in LDS, 1 scan of every sample
   __shared__ unsigned int sh_n;
 
@@ -179,7 +204,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
   int32_t *tr = trace + (int64_t)j * T * 2 + chain;
   const int first = rec[j].first;
   if (first == INT32_MAX) {
-    for (int k = tid; k < T; k += kBlock) tr[2 * k] = -1;
+    for (int k = tid; k < T; k += kChainBlock) tr[2 * k] = -1;
     return;
   }
   const int n_feas = (int)rec[j].n_feasible;
@@ -198,47 +223,71 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
     const float4 Cref = st_C;
     const int i0 = st_i;
     if (i0 > T) break;
-    // ---------------------------------------------------------------- rescan
-    float mx = 0.f;
-    for (int s = tid; s < M; s += kBlock) {
-      float4 a = D[s];
-      float d = -1.f;
-      if (feasible_pt(a, chain)) {
-        d = sqrtf(sqdist(Cref, a, chain));
-        mx = fmaxf(mx, d);
-      }
-      dref[s] = d;
-    }
-    mx = wave_max(mx);
-    if (lane == 0) red_k[0][wave] = mx;
-    __syncthreads();
-    float rref = 0.f;
+    const bool early = i0 <= kEarlySteps;
+    const bool global = (no_prune || stalled || early) && n_feas > cap;
+    if (!global) {
+      // -------------------------------------------------------------- rescan
+      ++n_rescan;
+      float mx = 0.f;
+      for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
+        float4 a[kUnroll];
 #pragma unroll
-    for (int k = 0; k < kWaves; ++k) rref = fmaxf(rref, red_k[0][k]);
-    // threshold theta: -1 keeps every feasible sample; otherwise the upper
-    // histogram bins that fit the capacity; -2 = no threshold fits
-    if (tid == 0) {
-      st_theta = -1.f;
-      st_mode = ((no_prune || stalled) && n_feas > cap) ? 1 : 0;
-    }
-    __syncthreads();
-    if (st_mode == 0 && n_feas > cap) {
-      float lo = 0.f, hi = rref;
+        for (int u = 0; u < kUnroll; ++u) {
+          int s = s0 + u * kChainBlock + tid;
+          a[u] = s < M ? D[s] : make_float4(-2.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          int s = s0 + u * kChainBlock + tid;
+          if (s < M) {
+            float d = -1.f;
+            if (feasible_pt(a[u], chain)) {
+              d = sqrtf(sqdist(Cref, a[u], chain));
+              mx = fmaxf(mx, d);
+            }
+            dref[s] = d;
+          }
+        }
+      }
+      mx = wave_max(mx);
+      if (lane == 0) red_k[0][wave] = mx;
+      __syncthreads();
+      float rref = 0.f;
+#pragma unroll
+      for (int k = 0; k < kChainWaves; ++k) rref = fmaxf(rref, red_k[0][k]);
+      // histogram of d over [lo, rref]; the shell is every bin from bstar up,
+      // theta = lower edge of bin bstar (-1: every feasible sample fits)
+      if (tid == 0) {
+        st_mode = 0;
+        st_theta = -1.f;
+        st_lo = 0.f;
+        st_w = rref / (float)kBins;
+        st_bstar = 0;
+      }
+      __syncthreads();
       for (int level = 0; level < 2; ++level) {
-        const float wdt = (hi - lo) / (float)kBins;
+        const float lo = st_lo, wdt = st_w;
         if (!(wdt > 0.f)) {
-          if (tid == 0) st_theta = -2.f;
+          if (tid == 0) st_mode = 1;
+          __syncthreads();
           break;
         }
-        for (int k = tid; k < kBins; k += kBlock) hist[k] = 0u;
+        for (int k = tid; k < kBins; k += kChainBlock) hist[k] = 0u;
         __syncthreads();
-        for (int s = tid; s < M; s += kBlock) {
-          float d = dref[s];
-          if (d >= lo) {
-            int bb = (int)((d - lo) / wdt);
-            bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
-            atomicAdd(&hist[bb], 1u);
+        for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
+          float dd[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            int s = s0 + u * kChainBlock + tid;
+            dd[u] = s < M ? dref[s] : -1.f;
           }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+            if (dd[u] >= lo) {
+              int bb = (int)((dd[u] - lo) / wdt);
+              bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
+              atomicAdd(&hist[bb], 1u);
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -247,102 +296,111 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
             if (cum + (int)hist[bb] > cap) break;
             cum += (int)hist[bb];
           }
-          st_theta = (bb < kBins - 1) ? lo + (float)(bb + 1) * wdt : -2.f;
+          if (bb < 0) {  // everything at or above lo fits
+            st_bstar = 0;
+            st_theta = level == 0 ? -1.f : lo;
+          } else if (bb < kBins - 1) {
+            st_bstar = bb + 1;
+            st_theta = lo + (float)(bb + 1) * wdt;
+          } else if (level == 0) {  // the top bin alone overflows: refine inside it
+            st_lo = lo + (float)(kBins - 1) * wdt;
+            st_w = wdt / (float)kBins;
+            st_theta = -2.f;
+          } else {
+            st_mode = 1;
+          }
         }
         __syncthreads();
-        if (st_theta != -2.f) break;
-        lo = lo + (float)(kBins - 1) * wdt;  // refine inside the top bin
+        if (st_theta != -2.f || st_mode == 1) break;
       }
-      if (tid == 0 && st_theta == -2.f) st_mode = 1;
-      __syncthreads();
-    }
-    const float theta = st_theta;
-    // ---------------------------------------------------------------- collect
-    if (st_mode == 0) {
-      if (tid == 0) sh_n = 0u;
-      __syncthreads();
-      for (int s = tid; s < M; s += kBlock) {
-        float d = dref[s];
-        if (d >= 0.f && d >= theta) {
-          unsigned int pos = atomicAdd(&sh_n, 1u);
-          if (pos < (unsigned)cap) {
-            sh_pt[pos] = D[s];
-            sh_id[pos] = s;
+      // -------------------------------------------- collect, sorted by bin
+      if (st_mode == 0) {
+        const float lo = st_lo, wdt = st_w, theta = st_theta;
+        const int bstar = st_bstar;
+        if (tid == 0) {
+          // entries in decreasing bin order: cursor[b] = first slot of bin b
+          unsigned int c = 0;
+          for (int bb = kBins - 1; bb >= bstar; --bb) {
+            cursor[bb] = c;
+            c += hist[bb];
           }
+          sh_n = c;
         }
-      }
-      __syncthreads();
-      if (tid == 0 && sh_n > (unsigned)cap) st_mode = 1;
-      __syncthreads();
-    }
-    const float slack = 4e-6f * rref;
-    ++n_rescan;
-    if (st_mode == 0) {
-      // ---------------------------------------------------------- shell steps
-      const int K = (int)sh_n;
-      if (wave == 0) {
-        float4 C = Cref;
-        int i = i0;
-        while (i <= T) {
-          float bk = -1.f;
-          int bi = INT32_MAX, be = 0;
-          for (int e = lane; e < K; e += 64) {
-            float k = sqdist(C, sh_pt[e], chain);
-            int id = sh_id[e];
-            if (better(k, id, bk, bi)) {
-              bk = k;
-              bi = id;
-              be = e;
-            }
-          }
-          wave_argmax(bk, bi, be);
-          if (theta >= 0.f) {
-            float dC = sqrtf(sqdist(C, Cref, chain));
-            if (!(sqrtf(bk) > theta + dC + slack)) break;  // the shell no longer suffices
-          }
-          const float4 pt = sh_pt[be];
-          C = geodesic_step(C, pt, i, chain);
-          if (lane == 0) tr[2 * (i - 1)] = bi;
-          if (i > T - avg) {
-            if (chain == 0) {
-              float Rm[9];
-              rot_from_quat(C, Rm);
+        __syncthreads();
+        if (sh_n > (unsigned)cap) {
+          if (tid == 0) st_mode = 1;
+        } else {
+          for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
+            float dd[kUnroll];
 #pragma unroll
-              for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
-            } else {
-              acc[0] += C.x;
-              acc[1] += C.y;
-              acc[2] += C.z;
+            for (int u = 0; u < kUnroll; ++u) {
+              int s = s0 + u * kChainBlock + tid;
+              dd[u] = s < M ? dref[s] : -1.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+              int s = s0 + u * kChainBlock + tid;
+              if (dd[u] >= 0.f && dd[u] >= theta) {
+                int bb = dd[u] >= lo ? (int)((dd[u] - lo) / wdt) : 0;
+                bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
+                if (bb >= bstar) {
+                  unsigned int pos = atomicAdd(&cursor[bb], 1u);
+                  if (pos < (unsigned)cap) {
+                    sh_pt[pos] = D[s];
+                    sh_id[pos] = s;
+                  }
+                }
+              }
             }
           }
-          ++i;
         }
-        if (lane == 0) {
-          st_C = C;
-          st_i = i;
+        __syncthreads();
+        // upper bound of d_ref over each chunk of 64 entries: the upper edge
+        // of the bin holding its first entry (entries are in decreasing bins)
+        if (st_mode == 0) {
+          const int K = (int)sh_n;
+          for (int c = tid; c * 64 < K && c < kMaxChunks; c += kChainBlock) {
+            int e = c * 64;
+            // bin of entry e: the bb with cursor_end... recount from hist
+            unsigned int acc_n = 0;
+            int bb = kBins - 1;
+            for (; bb >= bstar; --bb) {
+              if ((unsigned)e < acc_n + hist[bb]) break;
+              acc_n += hist[bb];
+            }
+            chunk_ub[c] = (bb >= kBins - 1) ? 3.0e38f : lo + (float)(bb + 1) * wdt;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
-      stalled = st_i == i0;
-    } else {
+    }
+    if (global || st_mode == 1) {
       // ---------------------------------------------------- global-scan steps
-      // (every feasible sample, all waves; at most kGlobalSteps per stage)
+      // every feasible sample, all waves; a bounded number of steps per stage
       float4 C = Cref;
       int i = i0;
       int par = 0;
       ++n_global;
-      stalled = false;
-      const int i_end = no_prune ? T : min(T, i0 + kGlobalSteps - 1);
+      const int i_end = no_prune ? T : (early ? min(T, kEarlySteps) : min(T, i0 + kGlobalSteps - 1));
       while (i <= i_end) {
         float bk = -1.f;
         int bi = INT32_MAX, be = 0;
-        for (int s = tid; s < M; s += kBlock) {
-          float4 a = D[s];
-          if (feasible_pt(a, chain)) {
-            float k = sqdist(C, a, chain);
-            if (better(k, s, bk, bi)) {
-              bk = k;
-              bi = s;
+        for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
+          float4 a[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            int s = s0 + u * kChainBlock + tid;
+            a[u] = s < M ? D[s] : make_float4(-2.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            int s = s0 + u * kChainBlock + tid;
+            if (s < M && feasible_pt(a[u], chain)) {
+              float k = sqdist(C, a[u], chain);
+              if (better(k, s, bk, bi)) {
+                bk = k;
+                bi = s;
+              }
             }
           }
         }
@@ -355,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
         bk = red_k[par][0];
         bi = red_i[par][0];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w)
+        for (int w = 1; w < kChainWaves; ++w)
           if (better(red_k[par][w], red_i[par][w], bk, bi)) {
             bk = red_k[par][w];
             bi = red_i[par][w];
@@ -363,18 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
         par ^= 1;
         C = geodesic_step(C, D[bi], i, chain);
         if (tid == 0) tr[2 * (i - 1)] = bi;
-        if (i > T - avg && wave == 0) {
-          if (chain == 0) {
-            float Rm[9];
-            rot_from_quat(C, Rm);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
-          } else {
-            acc[0] += C.x;
-            acc[1] += C.y;
-            acc[2] += C.z;
-          }
-        }
+        if (i > T - avg && wave == 0) accumulate_iterate(C, chain, acc);
         ++i;
       }
       if (tid == 0) {
@@ -382,6 +429,50 @@ __global__ void __launch_bounds__(kBlock) k_megb_chain(const int64_t *__restrict
         st_i = i;
       }
       __syncthreads();
+      stalled = false;
+    } else {
+      // ---------------------------------------------------------- shell steps
+      // wave 0 alone; chunks of 64 entries in decreasing distance bins, cut
+      // off once no later entry can beat the best found
+      const int K = (int)sh_n;
+      const float theta = st_theta;
+      const float slack = 4e-6f * sqrtf(sqdist(Cref, sh_pt[0], chain)) + 1e-30f;
+      const int nchunks = (K + 63) / 64;
+      if (wave == 0) {
+        float4 C = Cref;
+        int i = i0;
+        while (i <= T) {
+          float dC = sqrtf(sqdist(C, Cref, chain));
+          float bk = -1.f;
+          int bi = INT32_MAX, be = 0;
+          for (int c = 0; c < nchunks; ++c) {
+            if (c > 0 && c < kMaxChunks && sqrtf(bk) > chunk_ub[c] + dC + slack) break;
+            int e = c * 64 + lane;
+            if (e < K) {
+              float k = sqdist(C, sh_pt[e], chain);
+              int id = sh_id[e];
+              if (better(k, id, bk, bi)) {
+                bk = k;
+                bi = id;
+                be = e;
+              }
+            }
+            wave_argmax(bk, bi, be);
+          }
+          if (theta >= 0.f && !(sqrtf(bk) > theta + dC + slack)) break;  // the shell no longer suffices
+          const float4 pt = sh_pt[be];
+          C = geodesic_step(C, pt, i, chain);
+          if (lane == 0) tr[2 * (i - 1)] = bi;
+          if (i > T - avg) accumulate_iterate(C, chain, acc);
+          ++i;
+        }
+        if (lane == 0) {
+          st_C = C;
+          st_i = i;
+        }
+      }
+      __syncthreads();
+      stalled = st_i == i0;
     }
   }
   // ------------------------------------------------------------------ centre
@@ -481,10 +572,10 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
   hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      mask, rec, quat, trans);
-  const int cap = 2048;
+  const int cap = kCap;
   const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
   const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
-  hipLaunchKernelGGL(k_megb_chain, dim3(2 * n), dim3(kBlock), lds, stream, b.sample_off, max_samples, quat, trans,
+  hipLaunchKernelGGL(k_megb_chain, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat, trans,
                      rec, dref,
                      total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,

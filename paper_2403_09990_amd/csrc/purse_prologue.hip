@@ -117,6 +117,66 @@ __device__ bool dlt_2d(const float *Z, const float *z, int n, const float K[4], 
   return true;
 }
 
+// Weak-perspective initialisation: least squares x_n = A Z + b (a scaled
+// orthographic camera) by the 4x4 normal equations; s = mean row norm of A,
+// R = proj_SO3 [A0/s; A1/s; A0 x A1 / s^2], t = (b / s, 1 / s).
+__device__ bool affine_2d(const float *Z, const float *z, int n, const float K[4], double R[9], double t[3]) {
+  double G[16], r0[4], r1[4];
+  for (int k = 0; k < 16; ++k) G[k] = 0;
+  for (int k = 0; k < 4; ++k) r0[k] = r1[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    double x[4] = {Z[3 * i], Z[3 * i + 1], Z[3 * i + 2], 1.0};
+    double xn = ((double)z[3 * i] - K[2]) / K[0];
+    double yn = ((double)z[3 * i + 1] - K[3]) / K[1];
+    for (int a = 0; a < 4; ++a) {
+      for (int b = 0; b < 4; ++b) G[4 * a + b] += x[a] * x[b];
+      r0[a] += x[a] * xn;
+      r1[a] += x[a] * yn;
+    }
+  }
+  // Cholesky of G (4x4) and two solves
+  double L[16];
+  for (int k = 0; k < 16; ++k) L[k] = 0;
+  for (int j = 0; j < 4; ++j) {
+    double d = G[4 * j + j];
+    for (int k = 0; k < j; ++k) d -= L[4 * j + k] * L[4 * j + k];
+    if (!(d > 0)) return false;
+    L[4 * j + j] = sqrt(d);
+    for (int i = j + 1; i < 4; ++i) {
+      double v = G[4 * i + j];
+      for (int k = 0; k < j; ++k) v -= L[4 * i + k] * L[4 * j + k];
+      L[4 * i + j] = v / L[4 * j + j];
+    }
+  }
+  double *rhs[2] = {r0, r1};
+  for (int c = 0; c < 2; ++c) {
+    double *x = rhs[c];
+    for (int i = 0; i < 4; ++i) {
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= L[4 * i + k] * x[k];
+      x[i] = v / L[4 * i + i];
+    }
+    for (int i = 3; i >= 0; --i) {
+      double v = x[i];
+      for (int k = i + 1; k < 4; ++k) v -= L[4 * k + i] * x[k];
+      x[i] = v / L[4 * i + i];
+    }
+  }
+  double a0[3] = {r0[0], r0[1], r0[2]}, a1[3] = {r1[0], r1[1], r1[2]};
+  double s = 0.5 * (sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]) +
+                    sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]));
+  if (!(s > 0)) return false;
+  double c3[3];
+  cross3(a0, a1, c3);
+  double M[9] = {a0[0] / s, a0[1] / s, a0[2] / s, a1[0] / s, a1[1] / s, a1[2] / s,
+                 c3[0] / (s * s), c3[1] / (s * s), c3[2] / (s * s)};
+  polar_so3<double>(M, R, 12);
+  t[0] = r0[3] / s;
+  t[1] = r1[3] / s;
+  t[2] = 1.0 / s;
+  return true;
+}
+
 // Whitening factor U = [[u00, u01], [0, u11]] with U^T U = Lambda.
 template <typename T>
 __device__ __forceinline__ void whiten_factor(const float *Lam, T w[3]) {
@@ -167,6 +227,25 @@ __device__ bool gn_centre_2d(const float *Z, const float *z, const float *shapes
     if (!(P[2] + t[2] > z_min)) return false;
   }
   return true;
+}
+
+// Weighted cost sum ||z_i - Pi(R Z_i + t)||^2_Lambda_i of a 2D-3D pose.
+__device__ double cost_2d(const float *Z, const float *z, const float *shapes, int n, const float K[4],
+                          const double R[9], const double t[3]) {
+  double c = 0;
+  for (int i = 0; i < n; ++i) {
+    double m[3] = {Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]}, P[3];
+    matvec3(R, m, P);
+    for (int r = 0; r < 3; ++r) P[r] += t[r];
+    double iz = 1.0 / P[2];
+    double u = (double)K[0] * (P[0] * iz) + K[2], v = (double)K[1] * (P[1] * iz) + K[3];
+    double w[3];
+    whiten_factor<double>(shapes + 4 * i, w);
+    double r0 = (double)z[3 * i] - u, r1 = (double)z[3 * i + 1] - v;
+    double a = w[0] * r0 + w[1] * r1, b = w[2] * r1;
+    c += a * a + b * b;
+  }
+  return c;
 }
 
 // Arun's method in float64: R = proj_SO3(sum (b_i - bbar)(a_i - abar)^T).
@@ -276,8 +355,18 @@ __global__ void __launch_bounds__(64) k_prologue(DevBatch b, DevParams p, InstRe
   double Rd[9], td[3];
   bool fit_ok = true;
   if (is2d) {
-    fit_ok = dlt_2d(a, c, n, I.K, Rd, td);
-    if (fit_ok) fit_ok = gn_centre_2d(a, c, L, n, I.K, p.centre_gn, (double)p.z_min, Rd, td);
+    // Gauss-Newton from the DLT and from the weak-perspective fit; the
+    // successful fit with the lower cost is kept (ties: the DLT one)
+    double Ra_[9], ta_[3];
+    bool ok1 = dlt_2d(a, c, n, I.K, Rd, td);
+    if (ok1) ok1 = gn_centre_2d(a, c, L, n, I.K, p.centre_gn, (double)p.z_min, Rd, td);
+    bool ok2 = affine_2d(a, c, n, I.K, Ra_, ta_);
+    if (ok2) ok2 = gn_centre_2d(a, c, L, n, I.K, p.centre_gn, (double)p.z_min, Ra_, ta_);
+    if (ok2 && (!ok1 || cost_2d(a, c, L, n, I.K, Ra_, ta_) < cost_2d(a, c, L, n, I.K, Rd, td))) {
+      for (int k = 0; k < 9; ++k) Rd[k] = Ra_[k];
+      for (int k = 0; k < 3; ++k) td[k] = ta_[k];
+    }
+    fit_ok = ok1 || ok2;
   } else {
     kabsch_centre(a, c, n, Rd, td);
   }

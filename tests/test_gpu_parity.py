@@ -83,6 +83,18 @@ def test_ragged_batch_mixed_kinds():
         _log(j, st)
 
 
+def test_centre_fit_needs_weak_perspective_start():
+    """A small 2D-3D instance whose DLT start lands behind the camera (weak
+    perspective): the fit started from the scaled-orthographic solution wins."""
+    _log("case: weak-perspective start")
+    rng = np.random.default_rng(100)
+    b = W.Batch([W.make_2d3d(rng, 8, 2.0, (5.0, 20.0), 512)])
+    gp = _params(n_iters=40)
+    res = PT.run_gpu(b, gp, with_megb=False)
+    assert int(res["inst_status"][0]) & 0xFF == 0
+    _check_instance(b, res, 0, gp)
+
+
 def test_pull_in_path():
     """Few iterations leave many trajectories outside the set; they are pulled
     back by bisection towards the anchor."""
