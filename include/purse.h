@@ -111,14 +111,16 @@ typedef struct purse_params {
   float tau_abs_2d;    /* feasibility tolerance, Lambda-units */
   float z_min;         /* minimum valid depth for 2D-3D (m) */
   int32_t ckpt_every;  /* checkpoint spacing of the backward recompute (>= 1) */
-  int32_t centre_gn;   /* Gauss-Newton steps of the 2D-3D centre fit */
+  int32_t centre_gn;   /* cap on the Gauss-Newton steps of the 2D-3D centre fit, which
+                          stops once the step is below 1e-13 (rotation, rad) and
+                          1e-13 (1 + |t|_inf) (translation, m) */
   int32_t tile;        /* samples per workgroup: 64, 128, 256 or 512; 0 = library choice */
   int32_t flags;       /* PURSE_FLAG_* */
 } purse_params;
 
 /* Fill *p with the defaults: n_iters 50, n_gn 2, n_bis 16, megb_iters 4096,
  * megb_avg 10, omega0 0.5, v0 0.2, kappa 0.999, tau 1e-5 / 1e-4, z_min 1e-3,
- * ckpt_every 5, centre_gn 10, tile 0, flags 0.  Returns PURSE_E_NULL if p is NULL. */
+ * ckpt_every 5, centre_gn 50, tile 0, flags 0.  Returns PURSE_E_NULL if p is NULL. */
 purse_status purse_default_params(purse_params *p);
 
 /* Bytes of workspace every call below needs for this batch and params. */
@@ -128,7 +130,8 @@ purse_status purse_workspace_size(const purse_batch *b, const purse_params *p, s
  * Boundary samples of every instance (the alternating projection sampler
  * built from Section "Geometric Structures" and Step I / Step II of
  * Section "The CLOSURE Algorithm").  Per instance: centre fit (Arun's method
- * for 3D-3D; DLT then centre_gn Gauss-Newton steps for 2D-3D), pivot and
+ * for 3D-3D; DLT and weak-perspective starts, Gauss-Newton to convergence, for
+ * 2D-3D), pivot and
  * feasible anchor; per trajectory s: a Philox4x64-10 draw (key (seed, 0),
  * counter (s, 0, 0, 0)) picks an outward rotation (even s) or shift (odd s),
  * then n_iters iterations each project every predicted keypoint onto its

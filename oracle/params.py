@@ -16,4 +16,5 @@ class OracleParams:
     tau_abs_2d: float = 1e-4  # feasibility tolerance, Lambda-units
     z_min: float = 1e-3      # minimum depth (m) for a valid 2D-3D pose
     ckpt_every: int = 5      # checkpoint spacing of the adjoint recompute
-    centre_gn: int = 10      # Gauss-Newton steps of the 2D-3D centre fit
+    centre_gn: int = 50      # cap on the Gauss-Newton steps of the 2D-3D centre fit
+    centre_tol: float = 1e-13  # its convergence test on the step

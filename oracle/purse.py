@@ -159,13 +159,13 @@ def kabsch(a: torch.Tensor, q: torch.Tensor):
     return R, t
 
 
-def gn_step_2d(prob: Problem, R, t, q, o, z_min: float):
+def gn_step_2d(prob: Problem, R, t, q, o, z_min: float, return_delta: bool = False):
     """One undamped Gauss-Newton step on sum_i ||q_i - Pi_K(R Z_i + t)||^2_Lambda_i
     with the left update about the pivot o:
       R <- Exp(dw) R,  t <- Exp(dw)(t - o) + o + dv,
     J_i = dPi/dP * [ -[P_i - o]_x | I ], A = sum J^T Lambda J, g = sum J^T Lambda (q - u),
-    A delta = g by Cholesky.  Returns (R, t, ok); ok is False where a depth is
-    <= z_min or A is not positive definite."""
+    A delta = g by Cholesky.  Returns (R, t, ok) (and delta if asked); ok is
+    False where a depth is <= z_min or A is not positive definite."""
     fx, fy = prob.K[0], prob.K[1]
     P = transform(prob, R, t)
     X, Y, Z = P[..., 0], P[..., 1], P[..., 2]
@@ -190,6 +190,8 @@ def gn_step_2d(prob: Problem, R, t, q, o, z_min: float):
     E = exp_so3(delta[:, :3])
     Rn = E @ R
     tn = torch.einsum("mij,mj->mi", E, t - o) + o + delta[:, 3:]
+    if return_delta:
+        return Rn, tn, ok, delta
     return Rn, tn, ok
 
 
@@ -241,11 +243,12 @@ def gn_cost_2d(prob: Problem, R, t) -> float:
 
 def centre_fit(prob: Problem, p: OracleParams):
     """Maximum-likelihood centre x_c (eq. MLE with rho = ||.||^2_Lambda).
-    3D-3D: Arun's method on all N pairs.  2D-3D: `centre_gn` Gauss-Newton
-    steps towards the ellipse centres, each about the pivot R Zbar + t of the
-    current pose, from two initialisations, the DLT and the weak-perspective
-    fit; the successful fit with the lower cost is kept (ties: the DLT one).
-    Returns (R, t, ok)."""
+    3D-3D: Arun's method on all N pairs.  2D-3D: Gauss-Newton steps towards
+    the ellipse centres, each about the pivot R Zbar + t of the current pose,
+    run to convergence (until the step has |dw|_inf <= centre_tol and
+    |dv|_inf <= centre_tol (1 + |t|_inf), at most `centre_gn` steps), from two
+    initialisations, the DLT and the weak-perspective fit; the successful fit
+    with the lower cost is kept (ties: the DLT one).  Returns (R, t, ok)."""
     if prob.kind == KIND_3D3D:
         R, t = kabsch(prob.model, prob.centres[None])
         return R[0], t[0], True
@@ -259,8 +262,14 @@ def centre_fit(prob: Problem, p: OracleParams):
         ok = True
         for _ in range(p.centre_gn):
             o = R @ zbar + t
-            R, t, okk = gn_step_2d(prob, R, t, prob.centres[None], o, p.z_min)
+            R, t, okk, delta = gn_step_2d(prob, R, t, prob.centres[None], o, p.z_min, return_delta=True)
             ok = ok and bool(okk.all())
+            if not ok:
+                break
+            dw = float(delta[0, :3].detach().abs().max())
+            dv = float(delta[0, 3:].detach().abs().max())
+            if dw <= p.centre_tol and dv <= p.centre_tol * (1.0 + float(t.detach().abs().max())):
+                break
         P = transform(prob, R, t)
         ok = ok and bool((P[..., 2] > p.z_min).all())
         if ok:

@@ -106,10 +106,8 @@ purse::DevParams dev_params(const purse_params *p) {
   return d;
 }
 
-size_t backward_bytes(const purse_batch *b, const purse_params *p);
-
 purse::WsLayout layout_for(const purse_batch *b, const purse_params *p) {
-  return purse::ws_layout(b->n_inst, b->total_kp, b->total_samples, backward_bytes(b, p));
+  return purse::ws_layout(b->n_inst, b->total_kp, b->total_samples, b->max_kp, p->megb_iters, p->ckpt_every);
 }
 
 purse_status check_ws(const purse_batch *b, const purse_params *p, void *ws, size_t ws_bytes) {
@@ -124,14 +122,6 @@ T *at(void *ws, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
-}  // namespace
-
-namespace {
-size_t backward_bytes(const purse_batch *b, const purse_params *p) {
-  (void)b;
-  (void)p;
-  return 0;
-}
 }  // namespace
 
 extern "C" {
@@ -150,7 +140,7 @@ purse_status purse_default_params(purse_params *p) {
   p->tau_abs_2d = 1e-4f;
   p->z_min = 1e-3f;
   p->ckpt_every = 5;
-  p->centre_gn = 10;
+  p->centre_gn = 50;
   p->tile = 0;
   p->flags = 0;
   return PURSE_OK;
@@ -211,21 +201,21 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
                                  const uint8_t *mask, const int32_t *trace, const double *g_radii,
                                  const float *g_centre, float *g_centres, float *g_shapes, float *g_bounds, void *ws,
                                  size_t ws_bytes, void *stream) {
-  (void)poses;
-  (void)mask;
-  (void)trace;
-  (void)g_radii;
-  (void)g_centre;
-  (void)g_centres;
-  (void)g_shapes;
-  (void)g_bounds;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
   purse_status s = check_batch(b);
   if (s) return s;
   if ((s = check_params(p))) return s;
-  return fail(PURSE_E_BAD_ARG, "purse_megb_backward: not available in this build");
+  if (!poses || !mask || !trace || !g_radii || !g_centre || !g_centres || !g_shapes || !g_bounds)
+    return fail(PURSE_E_NULL, "an argument is NULL");
+  if ((s = check_ws(b, p, ws, ws_bytes))) return s;
+  if ((s = check_device())) return s;
+  const purse::WsLayout L = layout_for(b, p);
+  const purse::DevBatch db = dev_batch(b);
+  const purse::DevParams dp = dev_params(p);
+  purse::launch_backward(db, dp, poses, mask, trace, g_radii, g_centre, at<purse::InstRec>(ws, L.inst),
+                         at<purse::KpRec>(ws, L.kp), at<purse::BwdRec>(ws, L.bwd), at<double>(ws, L.ckpt),
+                         at<float>(ws, L.tan), at<float>(ws, L.contrib), g_centres, g_shapes, g_bounds,
+                         static_cast<hipStream_t>(stream));
+  return hip_check(hipGetLastError(), "backward launch");
 }
 
 const char *purse_status_string(purse_status s) {

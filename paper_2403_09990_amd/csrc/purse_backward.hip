@@ -1,0 +1,800 @@
+// Backward of purse_sample + purse_megb with every discrete decision held as
+// taken (argmax trace, feasibility and bisection outcomes, clamp sides).
+//
+// 1. k_bwd_megb (one workgroup per instance): the descent is replayed in
+//    float64 from the trace, keeping every ckpt_every-th rotation iterate;
+//    the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
+//    centre projection, the last-iterate average and the T geodesic steps
+//    (segments recomputed from their checkpoint), onto the few samples the
+//    trace touches (the active set).
+// 2. k_bwd_frame: per input direction, the tangent of the centre fit, pivot
+//    and anchor (the fit re-run in float64 dual numbers from its start).
+// 3. k_bwd_traj: per (active sample, input direction), the trajectory re-run
+//    in float32 dual numbers gives the tangent of the sample's pose, dotted
+//    with its cotangent.
+// 4. k_bwd_reduce: per direction, the sum over active samples in a fixed
+//    order, scattered into the gradient arrays.
+#include "purse_fit.hpp"
+#include "purse_launch.hpp"
+#include "purse_traj.hpp"
+
+namespace purse {
+
+namespace {
+
+constexpr int kBwdBlock = 1024;
+constexpr int kBwdWaves = kBwdBlock / 64;
+
+using D = double;
+
+__device__ __forceinline__ void mat_t(const D A[9], D B[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) B[3 * r + c] = A[3 * c + r];
+}
+
+// C = A^T B
+__device__ __forceinline__ void matmul_tn(const D A[9], const D B[9], D C[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[r] * B[c] + A[3 + r] * B[3 + c] + A[6 + r] * B[6 + c];
+}
+
+// C = A B^T
+__device__ __forceinline__ void matmul_nt(const D A[9], const D B[9], D C[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[3 * c] + A[3 * r + 1] * B[3 * c + 1] + A[3 * r + 2] * B[3 * c + 2];
+}
+
+// v(X) = vee(X - X^T), so that <X, [w]x> = w . v(X)
+__device__ __forceinline__ void vskew(const D X[9], D v[3]) {
+  v[0] = X[7] - X[5];
+  v[1] = X[2] - X[6];
+  v[2] = X[3] - X[1];
+}
+
+__device__ __forceinline__ void hat_d(const D w[3], D W[9]) {
+  W[0] = 0;
+  W[1] = -w[2];
+  W[2] = w[1];
+  W[3] = w[2];
+  W[4] = 0;
+  W[5] = -w[0];
+  W[6] = -w[1];
+  W[7] = w[0];
+  W[8] = 0;
+}
+
+// One descent step C_i = C Exp(Log(C^T R) / i) (float64 matrix form).
+__device__ __forceinline__ void step_rot(const D C[9], const D R[9], int i, D Cn[9], D Y[9], D phi[3]) {
+  matmul_tn(C, R, Y);
+  D w[3];
+  log_so3<D>(Y, w);
+  phi[0] = w[0] / i;
+  phi[1] = w[1] / i;
+  phi[2] = w[2] / i;
+  D E[9];
+  exp_so3<D>(phi, E);
+  matmul3<D>(C, E, Cn);
+}
+
+// VJP of E = Exp(phi) = cos(th) I + A [phi]x + B phi phi^T:
+// phi_bar = (-(sin th/th) tr Eb + (A'/th) phi.v(Eb) + (B'/th) phi^T Eb phi) phi
+//           + A v(Eb) + B (Eb + Eb^T) phi.
+__device__ __forceinline__ void vjp_exp(const D phi[3], const D Eb[9], D pb[3]) {
+  D th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  D A, B, sA, dA, dB;  // sA = sin th / th, dA = A'/th, dB = B'/th
+  if (th2 < 1e-12) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    sA = A;
+    dA = -1.0 / 3.0 + th2 / 30.0;
+    dB = -1.0 / 12.0 + th2 / 180.0;
+  } else {
+    D th = sqrt(th2), s = sin(th), c = cos(th);
+    A = s / th;
+    B = (1.0 - c) / th2;
+    sA = A;
+    dA = (th * c - s) / (th2 * th);
+    dB = (th * s - 2.0 * (1.0 - c)) / (th2 * th2);
+  }
+  D v[3];
+  vskew(Eb, v);
+  D trE = Eb[0] + Eb[4] + Eb[8];
+  D pv = phi[0] * v[0] + phi[1] * v[1] + phi[2] * v[2];
+  D Ep[3], ETp[3];
+  for (int r = 0; r < 3; ++r) {
+    Ep[r] = Eb[3 * r] * phi[0] + Eb[3 * r + 1] * phi[1] + Eb[3 * r + 2] * phi[2];
+    ETp[r] = Eb[r] * phi[0] + Eb[3 + r] * phi[1] + Eb[6 + r] * phi[2];
+  }
+  D pEp = phi[0] * Ep[0] + phi[1] * Ep[1] + phi[2] * Ep[2];
+  D k = -sA * trE + dA * pv + dB * pEp;
+  for (int r = 0; r < 3; ++r) pb[r] = k * phi[r] + A * v[r] + B * (Ep[r] + ETp[r]);
+}
+
+// VJP of phi = Log(Y) = f s, s = vee((Y - Y^T)/2), c = (tr Y - 1)/2,
+// th = atan2(|s|, c), f = th / |s|: returns Y_bar.
+__device__ __forceinline__ void vjp_log(const D Y[9], const D pb[3], D Yb[9]) {
+  D s[3] = {0.5 * (Y[7] - Y[5]), 0.5 * (Y[2] - Y[6]), 0.5 * (Y[3] - Y[1])};
+  D c = 0.5 * (Y[0] + Y[4] + Y[8] - 1.0);
+  D n2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+  D sb[3], cb;
+  if (n2 < 1e-20) {
+    sb[0] = pb[0];
+    sb[1] = pb[1];
+    sb[2] = pb[2];
+    cb = 0.0;
+  } else {
+    D n = sqrt(n2);
+    D th = atan2(n, c);
+    D f = th / n;
+    D den = n2 + c * c;
+    D th_n = c / den, th_c = -n / den;
+    D f_n = (th_n * n - th) / n2, f_c = th_c / n;
+    D ps = pb[0] * s[0] + pb[1] * s[1] + pb[2] * s[2];
+    for (int r = 0; r < 3; ++r) sb[r] = f * pb[r] + ps * f_n * s[r] / n;
+    cb = ps * f_c;
+  }
+  // s = v(Y) / 2 -> Y_bar = [s_bar]x / 2; c = (tr Y - 1)/2 -> Y_bar += c_bar I / 2
+  D W[9];
+  hat_d(sb, W);
+  for (int k = 0; k < 9; ++k) Yb[k] = 0.5 * W[k];
+  Yb[0] += 0.5 * cb;
+  Yb[4] += 0.5 * cb;
+  Yb[8] += 0.5 * cb;
+}
+
+__device__ __forceinline__ void load_R(const float *poses, int64_t g, D R[9]) {
+  const float *P = poses + 12 * g;
+  for (int k = 0; k < 9; ++k) R[k] = (D)P[k];
+}
+
+__device__ __forceinline__ int find_active(const int *act, int n, int s) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    if (act[mid] == s) return mid;
+    if (act[mid] < s)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p, const float *__restrict__ poses,
+                                                        const uint8_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ trace,
+                                                        const double *__restrict__ g_radii,
+                                                        const float *__restrict__ g_centre, BwdRec *recs,
+                                                        double *ckpt_all, int ck) {
+  __shared__ int act[kMaxActive];
+  __shared__ int n_act_s, overflow_s;
+  __shared__ double cot[kMaxActive][12];
+  __shared__ double Rstar[9], tstar[3], Ssum[9];
+  __shared__ double red_v[kBwdWaves];
+  __shared__ int red_i[kBwdWaves];
+  __shared__ int s0_s, sD_s, sd_s;
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int T = p.megb_iters;
+  const int avg = p.megb_avg < T ? p.megb_avg : T;
+  int64_t off, M64;
+  sample_range(b.sample_off, j, b.total_samples, b.max_samples, off, M64);
+  const int M = (int)M64;
+  BwdRec *rec = recs + j;
+  // ---- first feasible sample
+  int first = INT32_MAX;
+  for (int s = tid; s < M; s += kBwdBlock)
+    if (mask[off + s] & PURSE_MASK_FEASIBLE) first = min(first, s);
+  for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+  if (lane == 0) red_i[wave] = first;
+  __syncthreads();
+  if (tid == 0) {
+    int f = INT32_MAX;
+    for (int w = 0; w < kBwdWaves; ++w) f = min(f, red_i[w]);
+    s0_s = f;
+  }
+  __syncthreads();
+  const int s0 = s0_s;
+  if (s0 == INT32_MAX) {
+    if (tid == 0) {
+      rec->n_act = 0;
+      rec->status = 1;
+    }
+    return;
+  }
+  // ---- active set: the sorted distinct samples of the trace and the first
+  // sample, extracted by repeated block minima (the set has tens of members)
+  const int32_t *tr = trace + (int64_t)j * T * 2;
+  {
+    int bad = 0;
+    for (int k = tid; k < 2 * T; k += kBwdBlock) {
+      int v = tr[k];
+      if (v < 0 || v >= M || !(mask[off + v] & PURSE_MASK_FEASIBLE)) bad = 1;
+    }
+    bad = __syncthreads_or(bad);
+    if (bad) {
+      if (tid == 0) {
+        rec->n_act = 0;
+        rec->status = 3;
+      }
+      return;
+    }
+  }
+  if (tid == 0) {
+    n_act_s = 0;
+    overflow_s = 0;
+  }
+  __syncthreads();
+  int last = -1;
+  while (true) {
+    int mn = INT32_MAX;
+    for (int k = tid; k <= 2 * T; k += kBwdBlock) {
+      int v = k < 2 * T ? tr[k] : s0;
+      if (v > last && v < mn) mn = v;
+    }
+    for (int o = 32; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
+    if (lane == 0) red_i[wave] = mn;
+    __syncthreads();
+    mn = INT32_MAX;
+    for (int w = 0; w < kBwdWaves; ++w) mn = min(mn, red_i[w]);
+    __syncthreads();
+    if (mn == INT32_MAX) break;
+    if (tid == 0) {
+      if (n_act_s < kMaxActive)
+        act[n_act_s++] = mn;
+      else
+        overflow_s = 1;
+    }
+    last = mn;
+  }
+  __syncthreads();
+  // ---- replay the descent in float64 (thread 0: rotation, thread 64: translation)
+  double *ckpt = ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9;
+  if (tid == 0) {
+    D C[9], S[9];
+    load_R(poses, off + s0, C);
+    for (int k = 0; k < 9; ++k) S[k] = 0;
+    for (int i = 1; i <= T; ++i) {
+      if ((i - 1) % ck == 0)
+        for (int k = 0; k < 9; ++k) ckpt[((i - 1) / ck) * 9 + k] = C[k];
+      D R[9], Y[9], phi[3], Cn[9];
+      load_R(poses, off + tr[2 * (i - 1)], R);
+      step_rot(C, R, i, Cn, Y, phi);
+      for (int k = 0; k < 9; ++k) C[k] = Cn[k];
+      if (i > T - avg)
+        for (int k = 0; k < 9; ++k) S[k] += C[k];
+    }
+    D Rs[9];
+    polar_so3<D>(S, Rs, 12);
+    for (int k = 0; k < 9; ++k) {
+      Rstar[k] = Rs[k];
+      Ssum[k] = S[k];
+    }
+  } else if (tid == 64) {
+    D c[3], acc[3] = {0, 0, 0};
+    for (int r = 0; r < 3; ++r) c[r] = poses[12 * (off + s0) + 9 + r];
+    for (int i = 1; i <= T; ++i) {
+      const float *P = poses + 12 * (off + tr[2 * (i - 1) + 1]);
+      for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) / i;
+      if (i > T - avg)
+        for (int r = 0; r < 3; ++r) acc[r] += c[r];
+    }
+    for (int r = 0; r < 3; ++r) tstar[r] = acc[r] / avg;
+  }
+  __syncthreads();
+  // ---- samples realising the radii about (R*, t*)
+  D br = -1, bt = -1;
+  int ir = INT32_MAX, it = INT32_MAX;
+  for (int s = tid; s < M; s += kBwdBlock) {
+    if (!(mask[off + s] & PURSE_MASK_FEASIBLE)) continue;
+    const float *P = poses + 12 * (off + s);
+    D fr = 0, ft = 0;
+    for (int k = 0; k < 9; ++k) {
+      D d = Rstar[k] - (D)P[k];
+      fr += d * d;
+    }
+    for (int k = 0; k < 3; ++k) {
+      D d = tstar[k] - (D)P[9 + k];
+      ft += d * d;
+    }
+    if (fr > br || (fr == br && s < ir)) {
+      br = fr;
+      ir = s;
+    }
+    if (ft > bt || (ft == bt && s < it)) {
+      bt = ft;
+      it = s;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    D v2 = __shfl_xor(br, o, 64);
+    int i2 = __shfl_xor(ir, o, 64);
+    if (v2 > br || (v2 == br && i2 < ir)) {
+      br = v2;
+      ir = i2;
+    }
+  }
+  if (lane == 0) {
+    red_v[wave] = br;
+    red_i[wave] = ir;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    D v = red_v[0];
+    int ii = red_i[0];
+    for (int w = 1; w < kBwdWaves; ++w)
+      if (red_v[w] > v || (red_v[w] == v && red_i[w] < ii)) {
+        v = red_v[w];
+        ii = red_i[w];
+      }
+    sD_s = ii;
+  }
+  __syncthreads();
+  for (int o = 32; o >= 1; o >>= 1) {
+    D v2 = __shfl_xor(bt, o, 64);
+    int i2 = __shfl_xor(it, o, 64);
+    if (v2 > bt || (v2 == bt && i2 < it)) {
+      bt = v2;
+      it = i2;
+    }
+  }
+  if (lane == 0) {
+    red_v[wave] = bt;
+    red_i[wave] = it;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    D v = red_v[0];
+    int ii = red_i[0];
+    for (int w = 1; w < kBwdWaves; ++w)
+      if (red_v[w] > v || (red_v[w] == v && red_i[w] < ii)) {
+        v = red_v[w];
+        ii = red_i[w];
+      }
+    sd_s = ii;
+    // insert the radius samples into the sorted active set
+    int extra[2] = {sD_s, sd_s};
+    for (int e = 0; e < 2; ++e) {
+      int s = extra[e];
+      if (find_active(act, n_act_s, s) >= 0) continue;
+      if (n_act_s >= kMaxActive) {
+        overflow_s = 1;
+        continue;
+      }
+      int k = n_act_s++;
+      while (k > 0 && act[k - 1] > s) {
+        act[k] = act[k - 1];
+        --k;
+      }
+      act[k] = s;
+    }
+  }
+  for (int k = tid; k < kMaxActive * 12; k += kBwdBlock) cot[k / 12][k % 12] = 0.0;
+  __syncthreads();
+  const int n_act = n_act_s;
+  // ---- reverse sweeps
+  if (tid == 0 && !overflow_s) {
+    // cotangent of R*: (g_w . left tangent) and the rotation radius
+    D G[9], W[9];
+    const float *gc = g_centre + 6 * j;
+    D gw[3] = {gc[0], gc[1], gc[2]};
+    hat_d(gw, W);
+    matmul3<D>(W, Rstar, G);
+    for (int k = 0; k < 9; ++k) G[k] *= 0.5;
+    D RD[9];
+    load_R(poses, off + sD_s, RD);
+    D f2 = 0;
+    for (int k = 0; k < 9; ++k) f2 += (Rstar[k] - RD[k]) * (Rstar[k] - RD[k]);
+    const D gD = g_radii[2 * j];
+    if (f2 > 0 && gD != 0) {
+      D f = sqrt(f2);
+      D x = f / (2.0 * sqrt(2.0));
+      D kD = gD / (sqrt(2.0) * sqrt(fmax(1e-30, 1.0 - x * x)) * f);
+      int pD = find_active(act, n_act, sD_s);
+      for (int k = 0; k < 9; ++k) {
+        D v = kD * (Rstar[k] - RD[k]);
+        G[k] += v;
+        cot[pD][k] -= v;
+      }
+    }
+    // through R* = polar(S): S_bar = R* [b]x, b = (tr H I - H)^-1 v(R*^T G), H = sym(R*^T S)
+    D RtG[9], H[9], vv[3];
+    matmul_tn(Rstar, G, RtG);
+    vskew(RtG, vv);
+    D RtS[9];
+    matmul_tn(Rstar, Ssum, RtS);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) H[3 * r + c] = 0.5 * (RtS[3 * r + c] + RtS[3 * c + r]);
+    D trH = H[0] + H[4] + H[8];
+    D h00 = trH - H[0], h11 = trH - H[4], h22 = trH - H[8], h01 = -H[1], h02 = -H[2], h12 = -H[5];
+    D a00 = h11 * h22 - h12 * h12, a01 = h02 * h12 - h01 * h22, a02 = h01 * h12 - h02 * h11;
+    D a11 = h00 * h22 - h02 * h02, a12 = h01 * h02 - h00 * h12, a22 = h00 * h11 - h01 * h01;
+    D det = h00 * a00 + h01 * a01 + h02 * a02;
+    D bb[3] = {(a00 * vv[0] + a01 * vv[1] + a02 * vv[2]) / det, (a01 * vv[0] + a11 * vv[1] + a12 * vv[2]) / det,
+               (a02 * vv[0] + a12 * vv[1] + a22 * vv[2]) / det};
+    D Bh[9], Sbar[9];
+    hat_d(bb, Bh);
+    matmul3<D>(Rstar, Bh, Sbar);
+    // reverse over the steps, segments recomputed from their checkpoints
+    D Cb[9];
+    for (int k = 0; k < 9; ++k) Cb[k] = 0;
+    const int nseg = (T + ck - 1) / ck;
+    D seg[kMaxCkpt][9];
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int i_lo = sg * ck + 1, i_hi = min(T, (sg + 1) * ck);
+      // seg[q] = C_{i_lo - 1 + q}
+      for (int k = 0; k < 9; ++k) seg[0][k] = ckpt[sg * 9 + k];
+      for (int i = i_lo; i < i_hi; ++i) {
+        D R[9], Y[9], phi[3];
+        load_R(poses, off + tr[2 * (i - 1)], R);
+        step_rot(seg[i - i_lo], R, i, seg[i - i_lo + 1], Y, phi);
+      }
+      for (int i = i_hi; i >= i_lo; --i) {
+        if (i > T - avg)
+          for (int k = 0; k < 9; ++k) Cb[k] += Sbar[k];
+        const D *Cp = seg[i - i_lo];
+        const int s = tr[2 * (i - 1)];
+        D R[9], Y[9], phi[3], Cn[9];
+        load_R(poses, off + s, R);
+        step_rot(Cp, R, i, Cn, Y, phi);
+        D E[9];
+        exp_so3<D>(phi, E);
+        D Eb[9], Cbp[9], pb[3], Yb[9];
+        matmul_tn(Cp, Cb, Eb);       // E_bar = C^T C_bar
+        matmul_nt(Cb, E, Cbp);       // C_bar_prev = C_bar E^T
+        vjp_exp(phi, Eb, pb);
+        for (int r = 0; r < 3; ++r) pb[r] /= i;
+        vjp_log(Y, pb, Yb);
+        D t1[9], t2[9];
+        matmul_nt(R, Yb, t1);        // C_bar_prev += R Y_bar^T
+        matmul3<D>(Cp, Yb, t2);      // R_bar += C Y_bar
+        const int pa = find_active(act, n_act, s);
+        for (int k = 0; k < 9; ++k) {
+          Cb[k] = Cbp[k] + t1[k];
+          if (pa >= 0) cot[pa][k] += t2[k];
+        }
+      }
+    }
+    const int p0 = find_active(act, n_act, s0);
+    for (int k = 0; k < 9; ++k) cot[p0][k] += Cb[k];
+  } else if (tid == 64 && !overflow_s) {
+    const float *gc = g_centre + 6 * j;
+    D tb[3] = {gc[3], gc[4], gc[5]};
+    const D gd = g_radii[2 * j + 1];
+    const float *Pd = poses + 12 * (off + sd_s);
+    D dv[3] = {tstar[0] - Pd[9], tstar[1] - Pd[10], tstar[2] - Pd[11]};
+    D dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (dn > 0 && gd != 0) {
+      const int pd = find_active(act, n_act, sd_s);
+      for (int r = 0; r < 3; ++r) {
+        tb[r] += gd * dv[r] / dn;
+        cot[pd][9 + r] -= gd * dv[r] / dn;
+      }
+    }
+    D cb[3] = {0, 0, 0};
+    for (int i = T; i >= 1; --i) {
+      if (i > T - avg)
+        for (int r = 0; r < 3; ++r) cb[r] += tb[r] / avg;
+      const int pa = find_active(act, n_act, tr[2 * (i - 1) + 1]);
+      for (int r = 0; r < 3; ++r) {
+        if (pa >= 0) cot[pa][9 + r] += cb[r] / i;
+        cb[r] *= (1.0 - 1.0 / i);
+      }
+    }
+    const int p0 = find_active(act, n_act, s0);
+    for (int r = 0; r < 3; ++r) cot[p0][9 + r] += cb[r];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    rec->n_act = overflow_s ? 0 : n_act;
+    rec->status = overflow_s ? 2 : 0;
+    rec->s0 = s0;
+    rec->sD = sD_s;
+    rec->sd = sd_s;
+  }
+  for (int k = tid; k < n_act * 12; k += kBwdBlock) rec->cot[k / 12][k % 12] = cot[k / 12][k % 12];
+  for (int k = tid; k < n_act; k += kBwdBlock) rec->active[k] = act[k];
+}
+
+// ---------------------------------------------------------------------------
+// input directions: 3D-3D d = 4 i + c (b_i.x, b_i.y, b_i.z, beta_i);
+// 2D-3D d = 6 i + c (z_i.x, z_i.y, Lambda_00, Lambda_01 = Lambda_10, Lambda_11, beta_i)
+__device__ __forceinline__ int dirs_per_kp(int kind) { return kind == PURSE_KIND_2D3D ? 6 : 4; }
+
+// Tangent of keypoint i_d's constraint data along direction component c.
+__device__ void kp_tangent(const InstRec &I, const KpRec &k, const float *shapes_i, float beta_i, float kappa,
+                           int c, KpT<Dual<float>> &o) {
+  for (int r = 0; r < 3; ++r) {
+    o.m[r] = k.m[r];
+    o.c[r] = Dual<float>(k.c[r], 0.f);
+    o.w[r] = Dual<float>(k.w[r], 0.f);
+  }
+  o.kb = Dual<float>(k.kb, 0.f);
+  o.kb2 = Dual<float>(k.kb2, 0.f);
+  o.bt = Dual<float>(k.bt, 0.f);
+  const bool is2d = I.kind == PURSE_KIND_2D3D;
+  const int cb = is2d ? 5 : 3;
+  if (c == cb) {
+    o.kb.d = kappa;
+    o.kb2.d = 2.f * k.kb * kappa;
+    o.bt.d = 1.f;
+  } else if (!is2d || c < 2) {
+    o.c[c].d = 1.f;
+  } else {
+    double w[3];
+    whiten_factor<double>(shapes_i, w);
+    double dw0 = 0, dw1 = 0, dw2 = 0;
+    if (c == 2) {
+      dw0 = 0.5 / w[0];
+      dw1 = -w[1] * dw0 / w[0];
+      dw2 = -w[1] * dw1 / w[2];
+    } else if (c == 3) {
+      dw1 = 1.0 / w[0];
+      dw2 = -w[1] * dw1 / w[2];
+    } else {
+      dw2 = 0.5 / w[2];
+    }
+    o.w[0].d = (float)dw0;
+    o.w[1].d = (float)dw1;
+    o.w[2].d = (float)dw2;
+  }
+}
+
+struct KpDual {
+  static constexpr bool kPrefetch = false;
+  const KpRec *__restrict__ kp;
+  int i_d;
+  KpT<Dual<float>> tk;
+  __device__ __forceinline__ KpT<Dual<float>> operator()(int i) const {
+    if (i == i_d) return tk;
+    const KpRec k = kp[i];
+    KpT<Dual<float>> o;
+    for (int r = 0; r < 3; ++r) {
+      o.m[r] = k.m[r];
+      o.c[r] = Dual<float>(k.c[r], 0.f);
+      o.w[r] = Dual<float>(k.w[r], 0.f);
+    }
+    o.kb = Dual<float>(k.kb, 0.f);
+    o.kb2 = Dual<float>(k.kb2, 0.f);
+    o.bt = Dual<float>(k.bt, 0.f);
+    return o;
+  }
+};
+
+// 2D-3D observations with the tangent of one keypoint.
+struct ObsDual {
+  const float *z;
+  const float *shapes;
+  int i_d, c;
+  __device__ void operator()(int i, Dual<double> zz[2], Dual<double> w[3]) const {
+    double wv[3];
+    whiten_factor<double>(shapes + 4 * i, wv);
+    zz[0] = Dual<double>((double)z[3 * i], 0.0);
+    zz[1] = Dual<double>((double)z[3 * i + 1], 0.0);
+    for (int r = 0; r < 3; ++r) w[r] = Dual<double>(wv[r], 0.0);
+    if (i != i_d) return;
+    if (c < 2) {
+      zz[c].d = 1.0;
+    } else if (c == 2) {
+      w[0].d = 0.5 / wv[0];
+      w[1].d = -wv[1] * w[0].d / wv[0];
+      w[2].d = -wv[1] * w[1].d / wv[2];
+    } else if (c == 3) {
+      w[1].d = 1.0 / wv[0];
+      w[2].d = -wv[1] * w[1].d / wv[2];
+    } else if (c == 4) {
+      w[2].d = 0.5 / wv[2];
+    }
+  }
+};
+
+// Tangent of the centre, pivot and anchor along one input direction.
+__global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
+                                                       const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                       float *tan_all, int max_dirs) {
+  const int j = blockIdx.x;
+  const int d = threadIdx.x;
+  const InstRec I = inst[j];
+  if ((I.status & 0xFF) != PURSE_INST_OK || recs[j].n_act == 0) return;
+  const bool is2d = I.kind == PURSE_KIND_2D3D;
+  const int dpk = dirs_per_kp(I.kind);
+  if (d >= I.n_kp * dpk) return;
+  const int i_d = d / dpk, c = d % dpk;
+  const int n = I.n_kp;
+  const float *a = b.model_pts + 3 * I.kp_off;
+  const float *cz = b.centres + 3 * I.kp_off;
+  const float *L = b.shapes + 4 * I.kp_off;
+  Dual<double> Rd[9], td[3];
+  if (!is2d) {
+    // Arun's fit with b_{i_d} perturbed
+    double ab[3] = {0, 0, 0};
+    Dual<double> bb[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < n; ++i)
+      for (int r = 0; r < 3; ++r) {
+        ab[r] += a[3 * i + r];
+        bb[r] += Dual<double>((double)cz[3 * i + r], (i == i_d && r == c) ? 1.0 : 0.0);
+      }
+    for (int r = 0; r < 3; ++r) {
+      ab[r] /= n;
+      bb[r] = bb[r] / (double)n;
+    }
+    Dual<double> H[9];
+    for (int k = 0; k < 9; ++k) H[k] = Dual<double>(0.0, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int r = 0; r < 3; ++r) {
+        Dual<double> br = Dual<double>((double)cz[3 * i + r], (i == i_d && r == c) ? 1.0 : 0.0) - bb[r];
+        for (int q = 0; q < 3; ++q) H[3 * r + q] += br * ((double)a[3 * i + q] - ab[q]);
+      }
+    polar_so3<Dual<double>>(H, Rd, 12);
+    for (int r = 0; r < 3; ++r) td[r] = bb[r] - (Rd[3 * r] * ab[0] + Rd[3 * r + 1] * ab[1] + Rd[3 * r + 2] * ab[2]);
+  } else {
+    // both starts, the one the forward kept (lower cost) decides
+    double R1[9], t1[3], R2[9], t2[3];
+    const ObsPlain obs{cz, L};
+    bool ok1 = dlt_2d(a, cz, n, I.K, R1, t1);
+    if (ok1) ok1 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, R1, t1);
+    bool ok2 = affine_2d(a, cz, n, I.K, R2, t2);
+    if (ok2) ok2 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, R2, t2);
+    const bool use2 = ok2 && (!ok1 || cost_2d(a, cz, L, n, I.K, R2, t2) < cost_2d(a, cz, L, n, I.K, R1, t1));
+    double Ri[9], ti[3];
+    ok1 = use2 ? affine_2d(a, cz, n, I.K, Ri, ti) : dlt_2d(a, cz, n, I.K, Ri, ti);
+    for (int k = 0; k < 9; ++k) Rd[k] = Dual<double>(Ri[k], 0.0);
+    for (int k = 0; k < 3; ++k) td[k] = Dual<double>(ti[k], 0.0);
+    const ObsDual od{cz, L, i_d, c};
+    gn_centre_2d<Dual<double>>(a, od, n, I.K, p.centre_gn, (double)p.z_min, Rd, td);
+  }
+  FrameT<Dual<float>> F;
+  for (int k = 0; k < 9; ++k) F.Rc[k] = Dual<float>(I.Rc[k], (float)Rd[k].d);
+  for (int r = 0; r < 3; ++r) F.tc[r] = Dual<float>(I.tc[r], (float)td[r].d);
+  for (int r = 0; r < 3; ++r) {
+    double od = Rd[3 * r].d * I.abar[0] + Rd[3 * r + 1].d * I.abar[1] + Rd[3 * r + 2].d * I.abar[2] + td[r].d;
+    F.oc[r] = Dual<float>(I.oc[r], (float)od);
+  }
+  for (int k = 0; k < 9; ++k) F.Ra[k] = F.Rc[k];
+  for (int r = 0; r < 3; ++r) F.ta[r] = F.tc[r];
+  if ((I.status & PURSE_INST_ANCHOR_ITERATED) && I.has_anchor) {
+    KpDual kpl;
+    kpl.kp = kprec + I.kp_off;
+    kpl.i_d = i_d;
+    kp_tangent(I, kprec[I.kp_off + i_d], L + 4 * i_d, b.bounds[I.kp_off + i_d], p.kappa, c, kpl.tk);
+    PoseT<Dual<float>> x;
+    for (int k = 0; k < 9; ++k) x.R[k] = F.Rc[k];
+    for (int r = 0; r < 3; ++r) x.t[r] = F.tc[r];
+    int nfb = 0;
+    if (is2d)
+      run_trajectory<PURSE_KIND_2D3D>(I, F, kpl, x, p, false, nfb);
+    else
+      run_trajectory<PURSE_KIND_3D3D>(I, F, kpl, x, p, false, nfb);
+    for (int k = 0; k < 9; ++k) F.Ra[k] = Dual<float>(I.Ra[k], x.R[k].d);
+    for (int r = 0; r < 3; ++r) F.ta[r] = Dual<float>(I.ta[r], x.t[r].d);
+  }
+  float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
+  for (int k = 0; k < 9; ++k) tan[k] = F.Rc[k].d;
+  for (int r = 0; r < 3; ++r) tan[9 + r] = F.tc[r].d;
+  for (int r = 0; r < 3; ++r) tan[12 + r] = F.oc[r].d;
+  for (int k = 0; k < 9; ++k) tan[15 + k] = F.Ra[k].d;
+  for (int r = 0; r < 3; ++r) tan[24 + r] = F.ta[r].d;
+}
+
+// Tangent of active sample a's pose along 64 directions, dotted with its cotangent.
+template <int KIND>
+__global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
+                                                 const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                 const float *__restrict__ tan_all, float *contrib, int max_dirs) {
+  const int a = blockIdx.x, j = blockIdx.y;
+  const int d = blockIdx.z * 64 + threadIdx.x;
+  const InstRec I = inst[j];
+  if (I.kind != KIND || (I.status & 0xFF) != PURSE_INST_OK) return;
+  const BwdRec *rec = recs + j;
+  if (a >= rec->n_act) return;
+  const int dpk = dirs_per_kp(KIND);
+  if (d >= I.n_kp * dpk) return;
+  const int i_d = d / dpk, c = d % dpk;
+  const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
+  FrameT<Dual<float>> F;
+  for (int k = 0; k < 9; ++k) {
+    F.Rc[k] = Dual<float>(I.Rc[k], tan[k]);
+    F.Ra[k] = Dual<float>(I.Ra[k], tan[15 + k]);
+  }
+  for (int r = 0; r < 3; ++r) {
+    F.tc[r] = Dual<float>(I.tc[r], tan[9 + r]);
+    F.oc[r] = Dual<float>(I.oc[r], tan[12 + r]);
+    F.ta[r] = Dual<float>(I.ta[r], tan[24 + r]);
+  }
+  KpDual kpl;
+  kpl.kp = kprec + I.kp_off;
+  kpl.i_d = i_d;
+  kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
+             kpl.tk);
+  const int s = rec->active[a];
+  PoseT<Dual<float>> x = initial_pose(F, I.seed, (uint64_t)s, p);
+  int nfb = 0;
+  const uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, nfb);
+  double acc = 0.0;
+  if (m & PURSE_MASK_FEASIBLE) {
+    for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
+    for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
+  }
+  contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
+}
+
+// Sum over active samples (fixed order) and scatter into the gradients.
+__global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstRec *__restrict__ inst,
+                                                        const BwdRec *recs, const float *__restrict__ contrib,
+                                                        int max_dirs, float *g_centres, float *g_shapes,
+                                                        float *g_bounds) {
+  const int j = blockIdx.x;
+  const int d = threadIdx.x;
+  const InstRec I = inst[j];
+  const int64_t ko = b.kp_off[j];
+  const int n = b.n_kp[j];
+  const bool kp_ok = ko >= 0 && n >= 0 && n <= PURSE_MAX_KP && ko + n <= b.total_kp && b.kp_off[j + 1] - ko == n;
+  if (!kp_ok) return;
+  const bool is2d = I.kind == PURSE_KIND_2D3D;
+  const int dpk = dirs_per_kp(I.kind);
+  if (d >= n * dpk) return;
+  const int i = d / dpk, c = d % dpk;
+  const BwdRec *rec = recs + j;
+  float g = 0.f;
+  if ((I.status & 0xFF) == PURSE_INST_OK && rec->status == 2) {
+    g = __int_as_float(0x7fc00000);  // active set beyond capacity: no gradient
+  } else if ((I.status & 0xFF) == PURSE_INST_OK) {
+    double acc = 0.0;
+    for (int a = 0; a < rec->n_act; ++a) acc += (double)contrib[((int64_t)j * kMaxActive + a) * max_dirs + d];
+    g = (float)acc;
+  }
+  const int64_t k = ko + i;
+  if (c == 0) {
+    if (is2d)
+      g_centres[3 * k + 2] = 0.f;
+    else
+      for (int q = 0; q < 4; ++q) g_shapes[4 * k + q] = 0.f;
+  }
+  if (is2d) {
+    if (c < 2)
+      g_centres[3 * k + c] = g;
+    else if (c == 2)
+      g_shapes[4 * k] = g;
+    else if (c == 3) {
+      g_shapes[4 * k + 1] = 0.5f * g;
+      g_shapes[4 * k + 2] = 0.5f * g;
+    } else if (c == 4)
+      g_shapes[4 * k + 3] = g;
+    else
+      g_bounds[k] = g;
+  } else {
+    if (c < 3)
+      g_centres[3 * k + c] = g;
+    else
+      g_bounds[k] = g;
+  }
+}
+
+void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
+                     const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
+                     const KpRec *kp, BwdRec *recs, double *ckpt, float *tan, float *contrib, float *g_centres,
+                     float *g_shapes, float *g_bounds, hipStream_t stream) {
+  const int n = b.n_inst;
+  const int ck = p.ckpt_every < kMaxCkpt ? p.ckpt_every : kMaxCkpt;
+  hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii, g_centre,
+                     recs, ckpt, ck);
+  const int max_dirs = 6 * b.max_kp;
+  hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, recs, tan, max_dirs);
+  dim3 grid(kMaxActive, n, (max_dirs + 63) / 64);
+  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_2D3D>, grid, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
+                     max_dirs);
+  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, grid, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
+                     max_dirs);
+  hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
+                     g_shapes, g_bounds);
+}
+
+}  // namespace purse

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "purse_dual.hpp"
 #include "purse_layout.hpp"
 
 namespace purse {
@@ -47,6 +48,34 @@ template <typename T> __device__ __forceinline__ T datan2(T y, T x);
 template <> __device__ __forceinline__ float datan2<float>(float y, float x) { return atan2f(y, x); }
 template <> __device__ __forceinline__ double datan2<double>(double y, double x) { return atan2(y, x); }
 
+// reciprocal: the hardware approximation (1 ulp) in float32, exact otherwise
+template <typename T> __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// the same functions on dual numbers (value, derivative)
+template <typename T> __device__ __forceinline__ Dual<T> drcp(Dual<T> x) {
+  T r = drcp<T>(x.v);
+  return {r, -x.d * r * r};
+}
+template <typename T> __device__ __forceinline__ Dual<T> dsqrt(Dual<T> x) {
+  T s = dsqrt<T>(x.v);
+  return {s, x.d / (T(2) * s)};
+}
+template <typename T> __device__ __forceinline__ Dual<T> drsqrt(Dual<T> x) {
+  T r = drsqrt<T>(x.v);
+  return {r, T(-0.5) * r * r * r * x.d};
+}
+template <typename T> __device__ __forceinline__ void dsincos(Dual<T> x, Dual<T> *s, Dual<T> *c) {
+  T sv, cv;
+  dsincos<T>(x.v, &sv, &cv);
+  *s = Dual<T>(sv, cv * x.d);
+  *c = Dual<T>(cv, -sv * x.d);
+}
+template <typename T> __device__ __forceinline__ Dual<T> datan2(Dual<T> y, Dual<T> x) {
+  T den = x.v * x.v + y.v * y.v;
+  return {datan2<T>(y.v, x.v), (x.v * y.d - y.v * x.d) / den};
+}
+
 // ---------------------------------------------------------------------------
 // 3x3 matrices, row-major arrays of 9.
 template <typename T>
@@ -82,11 +111,11 @@ __device__ __forceinline__ void exp_so3(const T w[3], T R[9]) {
     B = T(0.5) - th2 / T(24);
     C = T(1) - T(0.5) * th2;
   } else {
-    T th = dsqrt(th2);
+    T ith = drsqrt(th2);
     T s, c;
-    dsincos(T(0.5) * th, &s, &c);
-    A = T(2) * s * c / th;
-    B = T(2) * s * s / th2;
+    dsincos(T(0.5) * th2 * ith, &s, &c);
+    A = T(2) * s * c * ith;
+    B = T(2) * s * s * ith * ith;
     C = T(1) - T(2) * s * s;
   }
   R[0] = C + B * w[0] * w[0];
@@ -111,26 +140,30 @@ __device__ __forceinline__ void log_so3(const T R[9], T w[3]) {
   if (sn2 < T(1e-30)) {
     f = T(1);
   } else {
-    T sn = dsqrt(sn2);
-    f = datan2(sn, c) / sn;
+    T isn = drsqrt(sn2);
+    f = datan2(sn2 * isn, c) * isn;
   }
   w[0] = f * s0;
   w[1] = f * s1;
   w[2] = f * s2;
 }
 
-// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix S (row-major,
-// overwritten by its near-diagonal form); V accumulates the eigenvectors as
-// columns.
+template <typename T> __device__ __forceinline__ bool is_zero(T x) { return x == T(0); }
+template <typename T> __device__ __forceinline__ bool is_zero(Dual<T> x) { return x.v == T(0) && x.d == T(0); }
+
+// Rotation in the (p, q) plane that zeroes S[p][q]: t = tan(phi) is the root of
+// t^2 + 2 t theta - 1 = 0 of smaller magnitude, theta = (aqq - app) / (2 apq),
+// written as t = 2 apq / (dl + sgn(dl) sqrt(dl^2 + 4 apq^2)), dl = aqq - app.
+// This form has no 1/apq, so it stays finite (and so do its derivatives) as
+// apq -> 0 in the sweeps after convergence.
 template <typename T>
 __device__ __forceinline__ void jacobi_rotate(T S[9], T V[9], int p, int q) {
   T apq = S[3 * p + q];
-  if (apq == T(0)) return;
+  if (is_zero(apq)) return;
   T app = S[3 * p + p], aqq = S[3 * q + q];
-  T theta = (aqq - app) / (T(2) * apq);
-  T at = theta < T(0) ? -theta : theta;
-  T tt = T(1) / (at + dsqrt(theta * theta + T(1)));
-  if (theta < T(0)) tt = -tt;
+  T dl = aqq - app;
+  T rt = dsqrt(dl * dl + T(4) * apq * apq);
+  T tt = T(2) * apq * drcp(dl < T(0) ? dl - rt : dl + rt);
   T c = drsqrt(tt * tt + T(1));
   T s = tt * c;
   S[3 * p + p] = app - tt * apq;
@@ -152,6 +185,9 @@ __device__ __forceinline__ void jacobi_rotate(T S[9], T V[9], int p, int q) {
   }
 }
 
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix S (row-major,
+// overwritten by its near-diagonal form); V accumulates the eigenvectors as
+// columns.
 template <typename T>
 __device__ __forceinline__ void jacobi3(T S[9], T V[9], int sweeps) {
 #pragma unroll
@@ -320,16 +356,17 @@ __device__ __forceinline__ void gn_accumulate(const T P[3], const T pt[3], T iz,
   j1[3] = T(0);
   j1[4] = d1[1];
   j1[5] = d1[2];
+  // one multiply-add per nonzero product, chained into the accumulator
+  // (j1[3] is structurally zero)
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
 #pragma unroll
     for (int k = 0; k <= i; ++k) {
-      if (i == 3 || k == 3)
-        A[tri(i, k)] += j0[i] * j0[k];
-      else
-        A[tri(i, k)] += j0[i] * j0[k] + j1[i] * j1[k];
+      A[tri(i, k)] += j0[i] * j0[k];
+      if (i != 3 && k != 3) A[tri(i, k)] += j1[i] * j1[k];
     }
-    g[i] += j0[i] * rt0 + j1[i] * rt1;
+    g[i] += j0[i] * rt0;
+    if (i != 3) g[i] += j1[i] * rt1;
   }
 }
 

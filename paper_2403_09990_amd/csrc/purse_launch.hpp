@@ -19,4 +19,9 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
                  int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
                  int64_t total_samples, hipStream_t stream);
 
+void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
+                     const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
+                     const KpRec *kp, BwdRec *recs, double *ckpt, float *tan, float *contrib, float *g_centres,
+                     float *g_shapes, float *g_bounds, hipStream_t stream);
+
 }  // namespace purse

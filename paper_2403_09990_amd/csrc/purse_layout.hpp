@@ -49,16 +49,29 @@ struct MegbRec {
   float centre[12];       // R* row-major, t*
 };
 
+// Backward scratch.
+constexpr int kMaxActive = 256;  // distinct samples the descent may touch per instance
+constexpr int kMaxCkpt = 16;     // largest checkpoint spacing of the descent replay
+constexpr int kMaxDirs = 6 * PURSE_MAX_KP;
+
+struct BwdRec {
+  int32_t n_act;   // active samples (sorted ids in `active`)
+  int32_t status;  // 0 ok, 1 empty, 2 active set beyond capacity, 3 trace inconsistent with mask
+  int32_t s0, sD, sd, pad;
+  int32_t active[kMaxActive];
+  double cot[kMaxActive][12];  // cotangent of each active pose: R (row-major), t
+};
+
 constexpr size_t kAlign = 256;
 __host__ __device__ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t inst, kp, megb, quat, trans, dref, bwd, total;
+  size_t inst, kp, megb, quat, trans, dref, bwd, ckpt, tan, contrib, total;
 };
 
-// Byte offsets of the workspace regions.  The backward region is sized by
-// the caller of ws_layout (bwd_bytes).
-inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, size_t bwd_bytes) {
+// Byte offsets of the workspace regions.
+inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, int max_kp, int megb_iters,
+                          int ckpt_every) {
   WsLayout L;
   size_t o = 0;
   L.inst = o;
@@ -74,7 +87,15 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   L.dref = o;
   o += align_up(8 * (size_t)total_samples);  // one float per sample per chain
   L.bwd = o;
-  o += align_up(bwd_bytes);
+  o += align_up(sizeof(BwdRec) * (size_t)n_inst);
+  const int ck = ckpt_every < kMaxCkpt ? (ckpt_every > 0 ? ckpt_every : 1) : kMaxCkpt;
+  L.ckpt = o;
+  o += align_up(sizeof(double) * 9 * (size_t)n_inst * (size_t)((megb_iters + ck - 1) / ck));
+  const size_t dirs = 6 * (size_t)max_kp;
+  L.tan = o;
+  o += align_up(sizeof(float) * 27 * (size_t)n_inst * dirs);
+  L.contrib = o;
+  o += align_up(sizeof(float) * (size_t)n_inst * kMaxActive * dirs);
   L.total = o;
   return L;
 }

@@ -31,6 +31,7 @@ constexpr int kUnroll = 8;
 constexpr int kCap = 3072;
 constexpr int kMaxChunks = kCap / 64;
 constexpr int kEarlySteps = 32;
+constexpr int kGroup = 2;
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
   return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
@@ -74,18 +75,37 @@ __device__ __forceinline__ bool better(float k1, int i1, float k2, int i2) {
   return k1 > k2 || (k1 == k2 && i1 < i2);
 }
 
-__device__ __forceinline__ void wave_argmax(float &k, int &id, int &e) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    float k2 = __shfl_xor(k, off, 64);
-    int i2 = __shfl_xor(id, off, 64);
-    int e2 = __shfl_xor(e, off, 64);
-    if (better(k2, i2, k, id)) {
-      k = k2;
-      id = i2;
-      e = e2;
-    }
-  }
+// Wavefront reductions by DPP row permutes: within each row of 16 lanes
+// (quad swaps, half-row and row mirrors), then row broadcasts 15 and 31 carry
+// the partial results up, so lane 63 ends with the reduction of all 64 lanes.
+__device__ __forceinline__ int wave_max_i32(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x140, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xA, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Keys are squared distances (>= 0) or the sentinel -1: their float bit
+// patterns order like the values under signed integer comparison.
+__device__ __forceinline__ float wave_max_key(float k) { return __int_as_float(wave_max_i32(__float_as_int(k))); }
+
+// Wavefront argmax (key desc, id asc); every lane gets the winning key and id.
+__device__ __forceinline__ void wave_argmax(float k, int id, float &wk, int &wi) {
+  wk = wave_max_key(k);
+  wi = wave_min_i32(k == wk ? id : INT32_MAX);
 }
 
 // Running sum of the last iterates: rotation matrices (chain 0) or centres.
@@ -102,11 +122,7 @@ __device__ __forceinline__ void accumulate_iterate(float4 C, int chain, float ac
   }
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
-}
+__device__ __forceinline__ float wave_max(float v) { return wave_max_key(v); }
 
 }  // namespace
 
@@ -384,7 +400,7 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
       const int i_end = no_prune ? T : (early ? min(T, kEarlySteps) : min(T, i0 + kGlobalSteps - 1));
       while (i <= i_end) {
         float bk = -1.f;
-        int bi = INT32_MAX, be = 0;
+        int bi = INT32_MAX;
         for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
           float4 a[kUnroll];
 #pragma unroll
@@ -404,10 +420,12 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
             }
           }
         }
-        wave_argmax(bk, bi, be);
+        float wk;
+        int wi;
+        wave_argmax(bk, bi, wk, wi);
         if (lane == 0) {
-          red_k[par][wave] = bk;
-          red_i[par][wave] = bi;
+          red_k[par][wave] = wk;
+          red_i[par][wave] = wi;
         }
         __syncthreads();
         bk = red_k[par][0];
@@ -432,8 +450,10 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
       stalled = false;
     } else {
       // ---------------------------------------------------------- shell steps
-      // wave 0 alone; chunks of 64 entries in decreasing distance bins, cut
-      // off once no later entry can beat the best found
+      // wave 0 alone.  Entries sit in chunks of 64 in decreasing distance
+      // bins; each lane keeps its own best over a group of kGroup chunks, one
+      // wavefront reduction per group, and the scan stops once no later
+      // chunk can beat the best found.
       const int K = (int)sh_n;
       const float theta = st_theta;
       const float slack = 4e-6f * sqrtf(sqdist(Cref, sh_pt[0], chain)) + 1e-30f;
@@ -442,26 +462,36 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
         float4 C = Cref;
         int i = i0;
         while (i <= T) {
-          float dC = sqrtf(sqdist(C, Cref, chain));
+          const float dC = sqrtf(sqdist(C, Cref, chain));
           float bk = -1.f;
           int bi = INT32_MAX, be = 0;
-          for (int c = 0; c < nchunks; ++c) {
-            if (c > 0 && c < kMaxChunks && sqrtf(bk) > chunk_ub[c] + dC + slack) break;
-            int e = c * 64 + lane;
-            if (e < K) {
-              float k = sqdist(C, sh_pt[e], chain);
-              int id = sh_id[e];
-              if (better(k, id, bk, bi)) {
-                bk = k;
-                bi = id;
-                be = e;
+          float wk;
+          int wi;
+          int c = 0;
+          while (true) {
+            const int cend = min(nchunks, c + kGroup);
+            for (; c < cend; ++c) {
+              const int e = c * 64 + lane;
+              if (e < K) {
+                float k = sqdist(C, sh_pt[e], chain);
+                int id = sh_id[e];
+                if (better(k, id, bk, bi)) {
+                  bk = k;
+                  bi = id;
+                  be = e;
+                }
               }
             }
-            wave_argmax(bk, bi, be);
+            wk = wave_max_key(bk);
+            if (c >= nchunks || sqrtf(wk) > chunk_ub[c] + dC + slack) break;
           }
-          if (theta >= 0.f && !(sqrtf(bk) > theta + dC + slack)) break;  // the shell no longer suffices
-          const float4 pt = sh_pt[be];
+          wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
+          if (theta >= 0.f && !(sqrtf(wk) > theta + dC + slack)) break;  // the shell no longer suffices
+          const unsigned long long win = __ballot(bk == wk && bi == wi);
+          const int we = __builtin_amdgcn_readlane(be, (int)__ffsll((long long)win) - 1);
+          const float4 pt = sh_pt[we];
           C = geodesic_step(C, pt, i, chain);
+          bi = wi;
           if (lane == 0) tr[2 * (i - 1)] = bi;
           if (i > T - avg) accumulate_iterate(C, chain, acc);
           ++i;

@@ -24,9 +24,11 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
     mask[g] = 0;
     return;
   }
-  Pose x = initial_pose(I, (uint64_t)s, p);
+  const FrameT<float> F = frame_of<float>(I);
+  const KpPlain kpl{kprec + I.kp_off};
+  Pose x = initial_pose(F, I.seed, (uint64_t)s, p);
   int n_fb = 0;
-  uint8_t m = run_trajectory<KIND>(I, kprec + I.kp_off, x, p, true, n_fb);
+  uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, n_fb);
   out[0] = make_float4(x.R[0], x.R[1], x.R[2], x.R[3]);
   out[1] = make_float4(x.R[4], x.R[5], x.R[6], x.R[7]);
   out[2] = make_float4(x.R[8], x.t[0], x.t[1], x.t[2]);

@@ -1,0 +1,130 @@
+"""GPU backward (purse_megb_backward through the C ABI) against the oracle's
+float64 reverse pass on the same trace: relative error of the gradient
+vector at most 1e-3."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import backward as oracle_backward
+from oracle.adjoint import radius_argmax
+from paper_2403_09990_amd import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _gpu_backward(res, gp, g_radii, g_centre):
+    import paper_2403_09990_amd as P
+    db = res["db"]
+    dev = res["poses"].device
+    g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
+    g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
+    g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
+    P.purse_megb_backward(db, gp, res["poses"], res["mask"], res["trace"],
+                          torch.as_tensor(g_radii, dtype=torch.float64, device=dev).contiguous(),
+                          torch.as_tensor(g_centre, dtype=torch.float32, device=dev).contiguous(),
+                          g_c, g_L, g_b, res["ws"])
+    torch.cuda.synchronize()
+    return g_c.cpu().numpy(), g_L.cpu().numpy(), g_b.cpu().numpy()
+
+
+def _compare(batch, res, gp, j, g_radii, g_centre, gpu):
+    inst = batch.instances[j]
+    off, end = res["db"].sample_off_host[j], res["db"].sample_off_host[j + 1]
+    kof, kend = res["db"].kp_off_host[j], res["db"].kp_off_host[j + 1]
+    poses = res["poses"][off:end].cpu().numpy()
+    mask = res["mask"][off:end].cpu().numpy()
+    trace = res["trace"][j].cpu().numpy()
+    s0 = int(np.nonzero(mask & 1)[0][0])
+    C = res["centre"][j].cpu().numpy().astype(np.float64)
+    sD, sd = radius_argmax(poses, mask, C[:9].reshape(3, 3), C[9:])
+    ora = oracle_backward(PT.as_f32_instance(inst), PT.oracle_params(gp), trace, s0, sD, sd,
+                          g_radii[j], g_centre[j])
+    g = np.concatenate([x[kof:kend].ravel() for x in gpu])
+    o = np.concatenate([x.ravel() for x in ora])
+    rel = np.linalg.norm(g - o) / max(1e-12, np.linalg.norm(o))
+    _log("instance", j, "rel err", rel, "|g|", np.linalg.norm(o))
+    return rel
+
+
+@pytest.mark.parametrize("kind,iters", [("2d", 40), ("3d", 40), ("2d", 8), ("3d", 8)])
+def test_backward_matches_oracle(kind, iters):
+    _log("case: backward", kind, iters)
+    rng = np.random.default_rng(31 + iters)
+    if kind == "2d":
+        b = W.Batch([W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 1024)])
+    else:
+        b = W.Batch([W.make_3d3d(rng, 8, 0.01, 0.05, 1024)])
+    import paper_2403_09990_amd as P
+    gp = P.purse_default_params(n_iters=iters, megb_iters=512)
+    res = PT.run_gpu(b, gp)
+    g_radii = rng.normal(size=(1, 2))
+    g_centre = rng.normal(size=(1, 6))
+    gpu = _gpu_backward(res, gp, g_radii, g_centre)
+    assert _compare(b, res, gp, 0, g_radii, g_centre, gpu) <= 1e-3
+
+
+def test_backward_c4_full_size():
+    """The differentiation workload at its full size: 2D-3D, N = 24, 262,144
+    trajectories, 20 iterations, checkpoint every 5, T = 4096."""
+    _log("case: backward c4")
+    import paper_2403_09990_amd as P
+    b = W.config_c4(0)
+    gp = P.purse_default_params(n_iters=20, ckpt_every=5)
+    res = PT.run_gpu(b, gp)
+    rng = np.random.default_rng(4)
+    g_radii = rng.normal(size=(1, 2))
+    g_centre = rng.normal(size=(1, 6))
+    gpu = _gpu_backward(res, gp, g_radii, g_centre)
+    assert _compare(b, res, gp, 0, g_radii, g_centre, gpu) <= 1e-3
+
+
+def test_backward_batched_equals_single():
+    """Gradients of a batch equal the gradients of each instance alone."""
+    _log("case: backward batched")
+    import paper_2403_09990_amd as P
+    b = W.config_c3(1, n_inst=4, m_range=(300, 600), n_range=(6, 12))
+    gp = P.purse_default_params(n_iters=30, megb_iters=256)
+    res = PT.run_gpu(b, gp)
+    rng = np.random.default_rng(5)
+    g_radii = rng.normal(size=(4, 2))
+    g_centre = rng.normal(size=(4, 6))
+    full = _gpu_backward(res, gp, g_radii, g_centre)
+    for j in range(4):
+        single = PT.run_gpu(W.sub_batch(b, [j]), gp)
+        gs = _gpu_backward(single, gp, g_radii[j:j + 1], g_centre[j:j + 1])
+        k0, k1 = res["db"].kp_off_host[j], res["db"].kp_off_host[j + 1]
+        for a, s in zip(full, gs):
+            np.testing.assert_array_equal(a[k0:k1], s)
+
+
+def test_autograd_function():
+    """PurseMEGB inside torch.autograd: loss.backward() reproduces the ABI call."""
+    _log("case: autograd")
+    import paper_2403_09990_amd as P
+    from paper_2403_09990_amd.autograd import PurseMEGB, left_cotangent
+    rng = np.random.default_rng(6)
+    b = W.Batch([W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 512)])
+    gp = P.purse_default_params(n_iters=30, megb_iters=256)
+    db = P.DeviceBatch(b)
+    centres = db.centres.clone().requires_grad_(True)
+    shapes = db.shapes.clone().requires_grad_(True)
+    bounds = db.bounds.clone().requires_grad_(True)
+    centre, radii = PurseMEGB.apply(centres, shapes, bounds, db, gp)
+    loss = 0.7 * radii[0, 0] - 0.3 * radii[0, 1] + centre[0, 9:].sum()
+    loss.backward()
+    res = PT.run_gpu(b, gp)
+    g_centre = np.zeros((1, 6))
+    g_centre[0, 3:] = 1.0
+    gpu = _gpu_backward(res, gp, np.array([[0.7, -0.3]]), g_centre)
+    np.testing.assert_allclose(centres.grad.cpu().numpy(), gpu[0], rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(bounds.grad.cpu().numpy(), gpu[2], rtol=1e-5, atol=1e-7)
+    R = torch.eye(3, dtype=torch.float64)[None]
+    assert torch.allclose(left_cotangent(R, torch.zeros(1, 3, 3, dtype=torch.float64)), torch.zeros(1, 3,
+                                                                                                   dtype=torch.float64))
