@@ -8,13 +8,15 @@ through the C ABI, on inputs already resident in HBM.  The default workload is
 the 2D-3D single instance: N = 12 keypoints, 65,536 trajectories, 100
 alternating iterations.  Prints one JSON line.
 
-Also reported: the sampler and MEGB times separately, the roofline of the
-dominant kernel (the 2D-3D trajectory kernel; algorithmic float32 FLOPs per
-launch over its average duration, measured with HIP events on the launch
-stream) and the FP64 oracle timed on this host on a bounded sample.
+Also reported: the sampler and MEGB times separately, forward + backward
+(purse_megb_backward of random cotangents) time, the roofline of the dominant
+kernel (the trajectory kernel; algorithmic float32 FLOPs per launch over its
+average duration, measured with HIP events on the launch stream) and the
+FP64 oracle timed on this host on a bounded sample.  After the timed region
+one device copy of COPY_BYTES runs as the calibration kernel for HBM traffic
+counters read by rocprofv3 on this same command.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pose samples/sec (alt-projection iters) & per-instance MEGB ms, fwd vs fwd+bwd"
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed)
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 28              # calibration copy: reads and writes 256 MiB
 
 CONFIGS = {
     "c1": dict(desc="3D-3D single instance, N=8, M=1024, 50 iterations", iters=50),
@@ -45,20 +48,13 @@ def make_batch(cfg, seed=0):
             "c5": W.config_c5}[cfg](seed)
 
 
-def source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2403_09990_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(kernel, workload):
     """HBM traffic of the kernel from the committed rocprofv3 PMC summary, or
     None if the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
     if not os.path.exists(path):
         return None
+    from paper_2403_09990_amd.profile_summary import source_hash
     rec = json.load(open(path))
     if rec.get("source_hash") != source_hash():
         return None
@@ -116,6 +112,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-reps", type=int, default=10)
+    ap.add_argument("--no-backward", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -169,6 +166,31 @@ def main():
     flops = F.batch_flops(batch, cfg["iters"], gp.n_gn)
     achieved = flops / (ms_traj * 1e-3) / 1e12
     traffic = read_traffic("k_sample", args.config)
+    # forward + backward: the step followed by the gradients of random
+    # cotangents of the radii and the centre
+    ms_fwd_bwd = None
+    if not args.no_backward:
+        rng = np.random.default_rng(0)
+        g_radii = torch.as_tensor(rng.normal(size=(db.n_inst, 2)), dtype=torch.float64, device=dev)
+        g_centre = torch.as_tensor(rng.normal(size=(db.n_inst, 6)), dtype=torch.float32, device=dev)
+        g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
+        g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
+        g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
+
+        def fwd_bwd():
+            step()
+            P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream)
+
+        fwd_bwd()
+        ms_fwd_bwd = time_events(fwd_bwd, max(1, min(args.steps, 5)), stream)
+
+    # calibration kernel for the traffic counters: a copy of known size
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
     m = mask.cpu().numpy()
     st = status.cpu().numpy()
     rad = radii.cpu().numpy()
@@ -192,6 +214,8 @@ def main():
         "trajectory_kernel_ms": ms_traj,
         "megb_ms": ms_megb,
         "megb_ms_per_instance": ms_megb / db.n_inst,
+        "fwd_ms": ms_step,
+        "fwd_bwd_ms": ms_fwd_bwd,
         "sampler_samples_per_s": total_m / (ms_sample * 1e-3),
         "sample_iters_per_s": total_m * cfg["iters"] / (ms_sample * 1e-3),
         "feasible_fraction": float((m & 1).mean()),

@@ -67,13 +67,16 @@ typedef int32_t purse_status;
 
 #define PURSE_MAX_KP 64
 
-/* Debug flags (purse_params.flags). */
+/* Flags (purse_params.flags): debugging and schedule choices. */
 #define PURSE_FLAG_FORCE_FP64_POLAR 1 /* always take the float64 3x3 polar step */
 #define PURSE_FLAG_NO_PRUNING 2       /* MEGB: scan every feasible sample at every step */
 #define PURSE_FLAG_REUSE_PROLOGUE 4   /* purse_sample: keep the per-instance centre fit and anchor that a
                                          previous purse_sample call with the same batch and params left
                                          in this workspace (draws more trajectories without refitting;
                                          inst_status is left as that call wrote it) */
+#define PURSE_FLAG_INSTANCE_ORDER 8   /* purse_sample: run the tiles in instance order instead of the
+                                         default heaviest-first order (results are identical; this only
+                                         changes the schedule, for tuning) */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints
@@ -114,7 +117,7 @@ typedef struct purse_params {
   int32_t centre_gn;   /* cap on the Gauss-Newton steps of the 2D-3D centre fit, which
                           stops once the step is below 1e-13 (rotation, rad) and
                           1e-13 (1 + |t|_inf) (translation, m) */
-  int32_t tile;        /* samples per workgroup: 64, 128, 256 or 512; 0 = library choice */
+  int32_t tile;        /* samples per workgroup: 64, 128 or 256; 0 = library choice (256) */
   int32_t flags;       /* PURSE_FLAG_* */
 } purse_params;
 

@@ -1,0 +1,101 @@
+"""Autotuner of the sampler's launch schedule.
+
+The sampler's results do not depend on the schedule: only the workgroup size
+(params.tile: 64, 128 or 256 samples) and the tile order (heaviest instances
+first, or instance order with PURSE_FLAG_INSTANCE_ORDER) change its speed.
+tune() times every candidate with HIP events on the given batch and keeps the
+fastest; the choice is cached in a JSON file keyed by the workload's
+signature (kinds, keypoint counts, sample counts, iteration counts, device
+name), so later calls on the same shape skip the timing.
+"""
+import hashlib
+import json
+import os
+from typing import Optional
+
+from . import PURSE_FLAG_INSTANCE_ORDER, purse_default_params, purse_sample
+
+TILES = (64, 128, 256)
+ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
+
+
+def default_cache_path() -> str:
+    return os.environ.get("PURSE_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "purse_autotune.json"))
+
+
+def signature(db, params) -> str:
+    """Key of a workload: everything the schedule's speed depends on."""
+    import numpy as np
+    import torch
+    kinds = db.kind.cpu().numpy()
+    nkp = db.n_kp.cpu().numpy()
+    m = np.diff(db.sample_off_host)
+    h = hashlib.sha256()
+    for a in (kinds, nkp, m):
+        h.update(np.ascontiguousarray(a).tobytes())
+    dev = torch.cuda.get_device_name(db.kind.device)
+    return "%s|n%d|it%d|gn%d|bis%d|%s" % (dev, db.n_inst, params.n_iters, params.n_gn, params.n_bis,
+                                          h.hexdigest()[:16])
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, table):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _with(params, tile, order):
+    p = purse_default_params()
+    for name, _ in type(params)._fields_:
+        setattr(p, name, getattr(params, name))
+    p.tile = tile
+    p.flags = (params.flags & ~PURSE_FLAG_INSTANCE_ORDER) | order
+    return p
+
+
+def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
+         cache: Optional[str] = None, force: bool = False):
+    """Returns (params with the fastest tile and order, report dict).
+
+    The candidates run on the caller's buffers (poses, mask, inst_status and
+    the workspace are overwritten)."""
+    import torch
+    path = cache or default_cache_path()
+    key = signature(db, params)
+    table = _load(path)
+    if not force and key in table:
+        rec = table[key]
+        return _with(params, rec["tile"], rec["order"]), dict(rec, cached=True)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    times = {}
+    for tile in TILES:
+        for order in ORDERS:
+            p = _with(params, tile, order)
+            purse_sample(db, p, poses, mask, inst_status, ws, stream)  # warm-up
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            for _ in range(reps):
+                purse_sample(db, p, poses, mask, inst_status, ws, stream)
+            e.record(stream)
+            e.synchronize()
+            times["%d/%s" % (tile, "instance" if order else "heaviest-first")] = s.elapsed_time(e) / reps
+    best = min(times, key=times.get)
+    tile = int(best.split("/")[0])
+    order = PURSE_FLAG_INSTANCE_ORDER if best.endswith("instance") else 0
+    rec = {"tile": tile, "order": order, "ms": times[best], "candidates_ms": times}
+    table[key] = rec
+    _store(path, table)
+    return _with(params, tile, order), dict(rec, cached=False)

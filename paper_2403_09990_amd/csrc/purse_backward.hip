@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const 
   kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
              kpl.tk);
   const int s = rec->active[a];
-  PoseT<Dual<float>> x = initial_pose(F, I.seed, (uint64_t)s, p);
+  PoseT<Dual<float>> x = initial_pose<Dual<float>>(F, I.seed, (uint64_t)s, p);
   int nfb = 0;
   const uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, nfb);
   double acc = 0.0;

@@ -10,9 +10,13 @@ namespace purse {
 void launch_prologue(const DevBatch &b, const DevParams &p, InstRec *inst, KpRec *kp, int32_t *inst_status,
                      hipStream_t stream);
 
-// tile: samples per workgroup (64, 128 or 256); max_samples: host bound on M_j.
-void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, float *poses,
-                   uint8_t *mask, int tile, int64_t max_samples, hipStream_t stream);
+// Workgroups of one sampler launch (an upper bound on sum_j ceil(M_j / tile)).
+int64_t sample_grid(int64_t total_samples, int n_inst, int tile);
+
+// Builds the tile schedule (sched: sched_ints(n_inst) int32 per kind) and runs
+// both kinds' trajectories; tile: samples per workgroup (64, 128 or 256).
+void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
+                   float *poses, uint8_t *mask, int tile, hipStream_t stream);
 
 void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                  MegbRec *rec, float4 *quat, float4 *trans, float *dref, float *centre, double *radii,

@@ -47,6 +47,7 @@ struct MegbRec {
   unsigned long long max_rot;    // float64 bit pattern of max ||R* - R_s||_F^2
   unsigned long long max_trans;  // float64 bit pattern of max ||t* - t_s||^2
   float centre[12];       // R* row-major, t*
+  long long n_groups[2];  // diagnostics: chunk groups scanned in shell steps per chain
 };
 
 // Backward scratch.
@@ -66,8 +67,13 @@ constexpr size_t kAlign = 256;
 __host__ __device__ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t inst, kp, megb, quat, trans, dref, bwd, ckpt, tan, contrib, total;
+  size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, total;
 };
+
+// Tile schedule of the sampler, one per kind: order[n] lists the instances
+// (heaviest per trajectory first), tstart[n + 1] the first tile of each entry
+// of that order and, last, the kind's tile count.
+__host__ __device__ inline size_t sched_ints(int64_t n_inst) { return 2 * (size_t)n_inst + 1; }
 
 // Byte offsets of the workspace regions.
 inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, int max_kp, int megb_iters,
@@ -78,6 +84,8 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   o += align_up(sizeof(InstRec) * (size_t)n_inst);
   L.kp = o;
   o += align_up(sizeof(KpRec) * (size_t)total_kp);
+  L.sched = o;
+  o += align_up(sizeof(int32_t) * 2 * sched_ints(n_inst));
   L.megb = o;
   o += align_up(sizeof(MegbRec) * (size_t)n_inst);
   L.quat = o;

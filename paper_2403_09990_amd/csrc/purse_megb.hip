@@ -234,6 +234,7 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
   for (int k = 0; k < 9; ++k) acc[k] = 0.f;
   bool stalled = false;
   int n_rescan = 0, n_global = 0;
+  long long n_groups = 0;
 
   while (true) {
     const float4 Cref = st_C;
@@ -483,6 +484,7 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
               }
             }
             wk = wave_max_key(bk);
+            ++n_groups;
             if (c >= nchunks || sqrtf(wk) > chunk_ub[c] + dC + slack) break;
           }
           wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
@@ -509,6 +511,7 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
   if (tid == 0) {
     rec[j].n_rescan[chain] = n_rescan;
     rec[j].n_global[chain] = n_global;
+    rec[j].n_groups[chain] = n_groups;
     if (chain == 0) {
       double Md[9], Rd[9];
 #pragma unroll

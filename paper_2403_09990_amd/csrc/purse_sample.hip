@@ -1,20 +1,105 @@
-// The sampler: one trajectory per lane.  Workgroup (tile, instance) covers
-// samples [tile * blockDim, (tile + 1) * blockDim) of one instance, so every
-// wave reads the same keypoint records (wave-uniform loads) and runs one code
-// path; one launch per kind keeps each kind's register allocation separate.
+// The sampler: one trajectory per lane.  A workgroup covers one tile of
+// blockDim consecutive samples of one instance, so every wave reads the same
+// keypoint records (wave-uniform loads) and runs one code path; one launch
+// per kind keeps each kind's register allocation separate.
+//
+// Tiles of a ragged batch are dealt from a schedule built on the device after
+// the prologue: per kind, the instances in decreasing per-trajectory cost (the
+// keypoint count orders it within a kind), each contributing ceil(M_j / tile)
+// consecutive tiles.  The hardware dispatches workgroups in index order, so the
+// heaviest tiles start first and the tail of the launch is made of light ones
+// (longest-processing-time-first list scheduling).
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
 
 namespace purse {
 
+constexpr int kSchedBlock = 1024;
+
+// Launch an instance belongs to; an invalid kind goes with 3D-3D, which
+// writes its (flagged) outputs as zeros.
+__device__ __forceinline__ int launch_kind(const InstRec &I) {
+  return I.kind == PURSE_KIND_2D3D ? PURSE_KIND_2D3D : PURSE_KIND_3D3D;
+}
+constexpr int kMaxSorted = 8192;  // larger batches keep instance order
+
+// Builds both kinds' schedules in one workgroup: rank of instance j = number
+// of instances of the kind that come before it (larger keypoint count, or
+// equal count and lower index), then a prefix sum of tile counts in rank order.
+__global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restrict__ inst, int n, int tile,
+                                                          int flags, int32_t *__restrict__ sched) {
+  __shared__ int key[kMaxSorted];
+  __shared__ int part[kSchedBlock];
+  const int tid = threadIdx.x;
+  const bool sorted = n <= kMaxSorted && !(flags & PURSE_FLAG_INSTANCE_ORDER);
+  for (int kind = 0; kind < 2; ++kind) {
+    int32_t *order = sched + (size_t)kind * sched_ints(n);
+    int32_t *tstart = order + n;
+    if (sorted) {
+      for (int j = tid; j < n; j += kSchedBlock) key[j] = launch_kind(inst[j]) == kind ? inst[j].n_kp : -1;
+      __syncthreads();
+      for (int j = tid; j < n; j += kSchedBlock) {
+        const int kj = key[j];
+        int r = 0;
+        for (int i = 0; i < n; ++i) {
+          const int ki = key[i];
+          r += (ki > kj) || (ki == kj && i < j);
+        }
+        order[r] = j;
+      }
+    } else {
+      for (int j = tid; j < n; j += kSchedBlock) order[j] = j;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // tiles per entry of the order, summed over contiguous chunks per thread
+    const int per = (n + kSchedBlock - 1) / kSchedBlock;
+    const int b0 = tid * per, b1 = min(n, b0 + per);
+    int acc = 0;
+    for (int k = b0; k < b1; ++k) {
+      const InstRec &I = inst[order[k]];
+      acc += launch_kind(I) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
+    }
+    part[tid] = acc;
+    __syncthreads();
+    for (int off = 1; off < kSchedBlock; off <<= 1) {
+      const int v = tid >= off ? part[tid - off] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    int run = tid ? part[tid - 1] : 0;
+    for (int k = b0; k < b1; ++k) {
+      tstart[k] = run;
+      const InstRec &I = inst[order[k]];
+      run += launch_kind(I) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
+    }
+    if (tid == kSchedBlock - 1) tstart[n] = part[kSchedBlock - 1];
+    __syncthreads();
+  }
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
-                                                DevParams p, float *__restrict__ poses, uint8_t *__restrict__ mask) {
-  const int j = blockIdx.y;
-  const InstRec I = inst[j];
-  if (I.kind != KIND) return;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= I.n_samples) return;
+                                                const int32_t *__restrict__ sched, int n_inst, DevParams p,
+                                                float *__restrict__ poses, uint8_t *__restrict__ mask) {
+  const int32_t *order = sched + (size_t)KIND * sched_ints(n_inst);
+  const int32_t *tstart = order + n_inst;
+  const int b = blockIdx.x;
+  if (b >= tstart[n_inst]) return;
+  // the entry k of the order with tstart[k] <= b < tstart[k + 1]
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tstart[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int j = order[lo];
+  const InstRec &I = inst[j];
+  const int64_t s = (int64_t)(b - tstart[lo]) * blockDim.x + threadIdx.x;
+  if (launch_kind(I) != KIND || s >= I.n_samples) return;
   const int64_t g = I.sample_off + s;
   float4 *out = reinterpret_cast<float4 *>(poses + 12 * g);
   if ((I.status & 0xFF) != PURSE_INST_OK) {
@@ -24,9 +109,9 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
     mask[g] = 0;
     return;
   }
-  const FrameT<float> F = frame_of<float>(I);
+  const FrameRef F = frame_ref(I);
   const KpPlain kpl{kprec + I.kp_off};
-  Pose x = initial_pose(F, I.seed, (uint64_t)s, p);
+  Pose x = initial_pose<float>(F, I.seed, (uint64_t)s, p);
   int n_fb = 0;
   uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, n_fb);
   out[0] = make_float4(x.R[0], x.R[1], x.R[2], x.R[3]);
@@ -35,11 +120,19 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   mask[g] = m;
 }
 
-void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, float *poses,
-                   uint8_t *mask, int tile, int64_t max_samples, hipStream_t stream) {
-  dim3 grid((unsigned)((max_samples + tile - 1) / tile), (unsigned)b.n_inst);
-  hipLaunchKernelGGL(k_sample<PURSE_KIND_2D3D>, grid, dim3(tile), 0, stream, inst, kp, p, poses, mask);
-  hipLaunchKernelGGL(k_sample<PURSE_KIND_3D3D>, grid, dim3(tile), 0, stream, inst, kp, p, poses, mask);
+int64_t sample_grid(int64_t total_samples, int n_inst, int tile) {
+  // sum_j ceil(M_j / tile) <= total / tile + n_inst
+  return total_samples / tile + n_inst;
+}
+
+void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
+                   float *poses, uint8_t *mask, int tile, hipStream_t stream) {
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
+  const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
+  hipLaunchKernelGGL(k_sample<PURSE_KIND_2D3D>, grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
+                     mask);
+  hipLaunchKernelGGL(k_sample<PURSE_KIND_3D3D>, grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
+                     mask);
 }
 
 }  // namespace purse

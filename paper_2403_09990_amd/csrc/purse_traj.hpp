@@ -68,6 +68,15 @@ struct KpSeq {
 template <typename T> struct ClampBand { static constexpr float v = 1.0f; };
 template <typename T> struct ClampBand<Dual<T>> { static constexpr float v = (1.0f - 1e-5f) * (1.0f - 1e-5f); };
 
+// The frame read in place from the instance record (the sampler): each use
+// is a load next to it, so the record does not hold registers across the
+// whole trajectory.
+struct FrameRef {
+  const float *Rc, *tc, *oc, *Ra, *ta;
+};
+
+__device__ __forceinline__ FrameRef frame_ref(const InstRec &I) { return FrameRef{I.Rc, I.tc, I.oc, I.Ra, I.ta}; }
+
 template <typename T>
 __device__ __forceinline__ FrameT<T> frame_of(const InstRec &I) {
   FrameT<T> F;
@@ -102,9 +111,8 @@ __device__ __forceinline__ void trajectory_direction(uint64_t seed, uint64_t s, 
   d[2] = z;
 }
 
-template <typename T>
-__device__ __forceinline__ PoseT<T> initial_pose(const FrameT<T> &F, uint64_t seed, uint64_t s,
-                                                 const DevParams &p) {
+template <typename T, typename FR>
+__device__ __forceinline__ PoseT<T> initial_pose(const FR &F, uint64_t seed, uint64_t s, const DevParams &p) {
   float d[3];
   trajectory_direction(seed, s, d);
   PoseT<T> x;
@@ -112,16 +120,19 @@ __device__ __forceinline__ PoseT<T> initial_pose(const FrameT<T> &F, uint64_t se
     T w[3] = {T(p.omega0 * d[0]), T(p.omega0 * d[1]), T(p.omega0 * d[2])};
     T E[9];
     exp_so3(w, E);
-    matmul3(E, F.Rc, x.R);
-    T r[3] = {F.tc[0] - F.oc[0], F.tc[1] - F.oc[1], F.tc[2] - F.oc[2]}, e[3];
+    T Rc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = T(F.Rc[k]);
+    matmul3(E, Rc, x.R);
+    T r[3] = {T(F.tc[0]) - T(F.oc[0]), T(F.tc[1]) - T(F.oc[1]), T(F.tc[2]) - T(F.oc[2])}, e[3];
     matvec3(E, r, e);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) x.t[k] = e[k] + F.oc[k];
+    for (int k = 0; k < 3; ++k) x.t[k] = e[k] + T(F.oc[k]);
   } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) x.R[k] = F.Rc[k];
+    for (int k = 0; k < 9; ++k) x.R[k] = T(F.Rc[k]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) x.t[k] = F.tc[k] + T(p.v0 * d[k]);
+    for (int k = 0; k < 3; ++k) x.t[k] = T(F.tc[k]) + T(p.v0 * d[k]);
   }
   return x;
 }
@@ -242,52 +253,61 @@ __device__ __forceinline__ void project2d(const T R[9], const T t[3], const KK &
   v = K[1] * (P[1] * iz) + K[3];
 }
 
+// One Gauss-Newton step of the 2D-3D refit from x towards the targets of the
+// projection pose xk (FIRST: x == xk, so the residual is (s - 1) e).
+template <bool FIRST, typename T, typename KPL>
+__device__ __forceinline__ bool gn_pass2d(const KPL &kpl, int n, const float K[4], const T oc[3], float z_min,
+                                          float band, const PoseT<T> &xk, PoseT<T> &x) {
+  T A[21], g[6];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = T(0.f);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = T(0.f);
+  bool ok = true;
+  KpSeq<KPL> seq(kpl, n);
+  for (int i = 0; i < n; ++i) {
+    const auto k = seq(i);
+    T P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    ok = ok && (P[2] > z_min);
+    T rt0, rt1;
+    if (FIRST) {
+      T e0 = u - k.c[0], e1 = v - k.c[1];
+      T et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      T r2 = et0 * et0 + et1 * et1;
+      T s = (r2 <= k.kb2 * band) ? T(1.f) : k.kb * drsqrt(r2);
+      rt0 = (s - 1.f) * et0;
+      rt1 = (s - 1.f) * et1;
+    } else {
+      T Pk[3], izk, uk, vk;
+      project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
+      T e0 = uk - k.c[0], e1 = vk - k.c[1];
+      T et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      T r2 = et0 * et0 + et1 * et1;
+      T s = (r2 <= k.kb2 * band) ? T(1.f) : k.kb * drsqrt(r2);
+      T r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
+      rt0 = k.w[0] * r0 + k.w[1] * r1;
+      rt1 = k.w[2] * r1;
+    }
+    T pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+    gn_accumulate<T>(P, pt, iz, T(K[0]), T(K[1]), k.w, rt0, rt1, A, g);
+  }
+  T d[6];
+  ok = ok && chol6_solve<T>(A, g, d);
+  if (!ok) return false;
+  apply_update<T>(d, oc, x.R, x.t);
+  return true;
+}
+
 template <typename T, typename KPL>
 __device__ __forceinline__ bool traj2d(const KPL &kpl, int n, const float K[4], const T oc[3], int n_iters,
                                        int n_gn, float z_min, PoseT<T> &x) {
   const float band = ClampBand<T>::v;
   for (int it = 0; it < n_iters; ++it) {
     const PoseT<T> xk = x;
-    for (int gs = 0; gs < n_gn; ++gs) {
-      T A[21], g[6];
-#pragma unroll
-      for (int k = 0; k < 21; ++k) A[k] = T(0.f);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) g[k] = T(0.f);
-      bool ok = true;
-      KpSeq<KPL> seq(kpl, n);
-      for (int i = 0; i < n; ++i) {
-        const auto k = seq(i);
-        T P[3], iz, u, v;
-        project2d(x.R, x.t, k, K, P, iz, u, v);
-        ok = ok && (P[2] > z_min);
-        T rt0, rt1;
-        if (gs == 0) {
-          T e0 = u - k.c[0], e1 = v - k.c[1];
-          T et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
-          T r2 = et0 * et0 + et1 * et1;
-          T s = (r2 <= k.kb2 * band) ? T(1.f) : k.kb * drsqrt(r2);
-          rt0 = (s - 1.f) * et0;
-          rt1 = (s - 1.f) * et1;
-        } else {
-          T Pk[3], izk, uk, vk;
-          project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
-          T e0 = uk - k.c[0], e1 = vk - k.c[1];
-          T et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
-          T r2 = et0 * et0 + et1 * et1;
-          T s = (r2 <= k.kb2 * band) ? T(1.f) : k.kb * drsqrt(r2);
-          T r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
-          rt0 = k.w[0] * r0 + k.w[1] * r1;
-          rt1 = k.w[2] * r1;
-        }
-        T pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
-        gn_accumulate<T>(P, pt, iz, T(K[0]), T(K[1]), k.w, rt0, rt1, A, g);
-      }
-      T d[6];
-      ok = ok && chol6_solve<T>(A, g, d);
-      if (!ok) return false;
-      apply_update<T>(d, oc, x.R, x.t);
-    }
+    if (!gn_pass2d<true>(kpl, n, K, oc, z_min, band, xk, x)) return false;
+    for (int gs = 1; gs < n_gn; ++gs)
+      if (!gn_pass2d<false>(kpl, n, K, oc, z_min, band, xk, x)) return false;
   }
   return true;
 }
@@ -337,14 +357,18 @@ __device__ __forceinline__ bool feasible(const InstRec &I, const KPL &kpl, const
 
 // Bisection on x(l) = (R_a Exp(l Log(R_a^T R)), t_a + l (t - t_a)) between the
 // feasible anchor (l = 0) and the infeasible end (l = 1); keeps the feasible end.
-template <int KIND, typename T, typename KPL>
-__device__ __forceinline__ PoseT<T> pull_in(const InstRec &I, const FrameT<T> &F, const KPL &kpl,
-                                            const PoseT<T> &x, const DevParams &p) {
-  T RtR[9], RaT[9], w[3];
+template <int KIND, typename T, typename KPL, typename FR>
+__device__ __forceinline__ PoseT<T> pull_in(const InstRec &I, const FR &F, const KPL &kpl, const PoseT<T> &x,
+                                            const DevParams &p) {
+  T Ra[9], ta[3], RtR[9], RaT[9], w[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ra[k] = T(F.Ra[k]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) ta[r] = T(F.ta[r]);
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) RaT[3 * r + c] = F.Ra[3 * c + r];
+    for (int c = 0; c < 3; ++c) RaT[3 * r + c] = Ra[3 * c + r];
   matmul3(RaT, x.R, RtR);
   log_so3(RtR, w);
   float lo = 0.f, hi = 1.f;
@@ -353,9 +377,9 @@ __device__ __forceinline__ PoseT<T> pull_in(const InstRec &I, const FrameT<T> &F
     T wm[3] = {mid * w[0], mid * w[1], mid * w[2]}, E[9];
     PoseT<T> m;
     exp_so3(wm, E);
-    matmul3(F.Ra, E, m.R);
+    matmul3(Ra, E, m.R);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) m.t[r] = F.ta[r] + mid * (x.t[r] - F.ta[r]);
+    for (int r = 0; r < 3; ++r) m.t[r] = ta[r] + mid * (x.t[r] - ta[r]);
     if (feasible<KIND>(I, kpl, m, p, -1.f))
       lo = mid;
     else
@@ -364,29 +388,30 @@ __device__ __forceinline__ PoseT<T> pull_in(const InstRec &I, const FrameT<T> &F
   PoseT<T> out;
   if (lo == 0.f) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out.R[k] = F.Ra[k];
+    for (int k = 0; k < 9; ++k) out.R[k] = Ra[k];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) out.t[r] = F.ta[r];
+    for (int r = 0; r < 3; ++r) out.t[r] = ta[r];
   } else {
     T wl[3] = {lo * w[0], lo * w[1], lo * w[2]}, E[9];
     exp_so3(wl, E);
-    matmul3(F.Ra, E, out.R);
+    matmul3(Ra, E, out.R);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) out.t[r] = F.ta[r] + lo * (x.t[r] - F.ta[r]);
+    for (int r = 0; r < 3; ++r) out.t[r] = ta[r] + lo * (x.t[r] - ta[r]);
   }
   return out;
 }
 
 // Full trajectory from x; returns the mask bits and leaves the output pose in x.
-template <int KIND, typename T, typename KPL>
-__device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FrameT<T> &F, const KPL &kpl,
+template <int KIND, typename T, typename KPL, typename FR>
+__device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FR &F, const KPL &kpl,
                                                   PoseT<T> &x, const DevParams &p, bool with_pull_in,
                                                   int &n_fb) {
   bool ok = true;
   if (KIND == PURSE_KIND_3D3D) {
     traj3d(kpl, I.n_kp, I.abar, p.n_iters, (p.flags & PURSE_FLAG_FORCE_FP64_POLAR) != 0, x, n_fb);
   } else {
-    ok = traj2d(kpl, I.n_kp, I.K, F.oc, p.n_iters, p.n_gn, p.z_min, x);
+    T oc[3] = {T(F.oc[0]), T(F.oc[1]), T(F.oc[2])};
+    ok = traj2d(kpl, I.n_kp, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
     reorthonormalise(x.R);
   }
   if (!ok) return PURSE_MASK_FAILED;

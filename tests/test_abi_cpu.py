@@ -21,6 +21,23 @@ def test_header_declares_what_the_binding_wraps():
     assert _declared() == set(_native.EXPORTED)
 
 
+def test_header_constants_match_the_binding():
+    """Every PURSE_* integer constant of the header has the same value in the
+    Python binding."""
+    text = open(os.path.join(ROOT, "include", "purse.h")).read()
+    defs = dict(re.findall(r"^#define\s+(PURSE_\w+)\s+(\(?-?\d+(?:\s*<<\s*\d+)?\)?)", text, re.M))
+    enums = dict(re.findall(r"^\s+(PURSE_\w+)\s*=\s*(-?\d+)", text, re.M))
+    defs.update(enums)
+    assert len(defs) >= 20
+    for name, expr in defs.items():
+        if name.startswith("PURSE_MAX_KP") or not hasattr(_native, name):
+            continue
+        assert getattr(_native, name) == eval(expr), name
+    for name in dir(_native):
+        if name.startswith("PURSE_") and not name.startswith("PURSE_MAX"):
+            assert name in defs, name
+
+
 def test_library_exports_every_declared_symbol():
     lib = _native.load()
     for name in _declared():
