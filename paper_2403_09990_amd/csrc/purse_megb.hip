@@ -32,16 +32,22 @@ constexpr int kCap = 3072;
 constexpr int kMaxChunks = kCap / 64;
 constexpr int kEarlySteps = 32;
 constexpr int kGroup = 2;
+constexpr int kRecentreGroups = 2;   // a step scanning more groups than this ...
+constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
+static_assert(kCap % (64 * kGroup) == 0, "shell groups tile the shell");
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
   return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
 }
 
+// Squared distance: ||R_a - R_b||_F^2 = 2 |a - b|^2 |a + b|^2 for unit
+// quaternions a, b, where |a + b|^2 = 4 - |a - b|^2 (chain 0); |a - b|^2 for
+// translations (chain 1).
 __device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
   if (chain == 0) {
     float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
-    float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
-    return 2.f * (m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3) * (p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3);
+    float x = m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3;
+    return 2.f * x * (4.f - x);
   }
   float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
   return d0 * d0 + d1 * d1 + d2 * d2;
@@ -49,10 +55,8 @@ __device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
 
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
 __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
-  if (chain == 1) {
-    float fi = (float)i;
-    return make_float4(a.x + (b.x - a.x) / fi, a.y + (b.y - a.y) / fi, a.z + (b.z - a.z) / fi, 1.f);
-  }
+  const float inv = 1.f / (float)i;
+  if (chain == 1) return make_float4(a.x + (b.x - a.x) * inv, a.y + (b.y - a.y) * inv, a.z + (b.z - a.z) * inv, 1.f);
   float dt = a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
   if (dt < 0.f) b = make_float4(-b.x, -b.y, -b.z, -b.w);
   float4 ac = make_float4(a.x, -a.y, -a.z, -a.w);
@@ -60,7 +64,7 @@ __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int c
   float sn = sqrtf(r.y * r.y + r.z * r.z + r.w * r.w);
   if (!(sn > 0.f)) return a;
   float half = atan2f(sn, r.x);
-  float ph = half / (float)i;
+  float ph = half * inv;
   float s, c;
   sincosf(ph, &s, &c);
   float f = s / sn;
@@ -188,34 +192,42 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
   }
 }
 
-// One workgroup of kChainBlock threads per (instance, chain).
-__global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
-                                                            const float4 *__restrict__ quat,
-                                                            const float4 *__restrict__ trans, MegbRec *rec,
-                                                            float *dref_all, int64_t total_samples,
-                                                            int32_t *trace, int T, int avg, int cap,
-                                                            int no_prune) {
-  extern __shared__ float4 sh_pt[];
-  int *sh_id = reinterpret_cast<int *>(sh_pt + cap);
-  __shared__ unsigned int hist[kBins];
-  __shared__ unsigned int cursor[kBins];
-  __shared__ float chunk_ub[kMaxChunks];
-  __shared__ float red_k[2][kChainWaves];
-  __shared__ int red_i[2][kChainWaves];
+// Shared state of one chain's workgroup.
+struct ChainShared {
+  float4 *pt;             // shell points, [cap]
+  int *id;                // shell sample ids, [cap]
+  unsigned int *hist;     // [kBins]
+  unsigned int *cursor;   // [kBins]
+  float *chunk_ub;        // [kMaxChunks]
+  float (*red_k)[kChainWaves];
+  int (*red_i)[kChainWaves];
+};
+
+// Bin of distance d in a histogram of kBins bins of width w from lo.
+__device__ __forceinline__ int bin_of(float d, float lo, float w) {
+  int b = (int)((d - lo) / w);
+  return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+}
+
+template <int CHAIN>
+__device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *__restrict__ sample_off,
+                                          int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
+                                          float *dref_all, int64_t total_samples, int32_t *trace, int T, int avg,
+                                          int cap, int no_prune) {
   __shared__ float4 st_C;
   __shared__ int st_i;
-  __shared__ float st_theta, st_lo, st_w;
+  __shared__ float st_theta, st_lo, st_w, st_rref;
   __shared__ int st_bstar;
   __shared__ int st_mode;  // 0 shell in LDS, 1 scan of every sample
   __shared__ unsigned int sh_n;
 
+  constexpr int chain = CHAIN;
   const int j = blockIdx.x >> 1;
-  const int chain = blockIdx.x & 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
   sample_range(sample_off, j, total_samples, max_m, off, M64);
   const int M = (int)M64;
-  const float4 *D = (chain == 0 ? quat : trans) + off;
+  const float4 *D = pts + off;
   float *dref = dref_all + chain * total_samples + off;
   int32_t *tr = trace + (int64_t)j * T * 2 + chain;
   const int first = rec[j].first;
@@ -267,29 +279,80 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
         }
       }
       mx = wave_max(mx);
-      if (lane == 0) red_k[0][wave] = mx;
+      if (lane == 0) S.red_k[0][wave] = mx;
       __syncthreads();
       float rref = 0.f;
 #pragma unroll
-      for (int k = 0; k < kChainWaves; ++k) rref = fmaxf(rref, red_k[0][k]);
-      // histogram of d over [lo, rref]; the shell is every bin from bstar up,
-      // theta = lower edge of bin bstar (-1: every feasible sample fits)
+      for (int k = 0; k < kChainWaves; ++k) rref = fmaxf(rref, S.red_k[0][k]);
+      // Shell membership: d >= theta and (coarse) bin >= bstar of the
+      // histogram (lo, w); theta = -1 when every feasible sample fits.
       if (tid == 0) {
         st_mode = 0;
         st_theta = -1.f;
         st_lo = 0.f;
         st_w = rref / (float)kBins;
         st_bstar = 0;
+        st_rref = rref;
       }
       __syncthreads();
-      for (int level = 0; level < 2; ++level) {
-        const float lo = st_lo, wdt = st_w;
-        if (!(wdt > 0.f)) {
-          if (tid == 0) st_mode = 1;
+      if (n_feas > cap) {
+        for (int level = 0; level < 2; ++level) {
+          const float lo = st_lo, wdt = st_w;
+          if (!(wdt > 0.f)) {
+            if (tid == 0) st_mode = 1;
+            __syncthreads();
+            break;
+          }
+          for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
           __syncthreads();
-          break;
+          for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
+            float dd[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+              int s = s0 + u * kChainBlock + tid;
+              dd[u] = s < M ? dref[s] : -1.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+              if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, wdt)], 1u);
+          }
+          __syncthreads();
+          if (tid == 0) {
+            int cum = 0, bb = kBins - 1;
+            for (; bb >= 0; --bb) {
+              if (cum + (int)S.hist[bb] > cap) break;
+              cum += (int)S.hist[bb];
+            }
+            if (bb < 0) {  // everything at or above lo fits
+              st_bstar = 0;
+              st_theta = level == 0 ? -1.f : lo;
+            } else if (bb < kBins - 1) {
+              st_bstar = bb + 1;
+              st_theta = lo + (float)(bb + 1) * wdt;
+            } else if (level == 0) {  // the top bin alone overflows: refine inside it
+              st_lo = lo + (float)(kBins - 1) * wdt;
+              st_w = wdt / (float)kBins;
+              st_theta = -2.f;
+            } else {
+              st_mode = 1;
+            }
+          }
+          __syncthreads();
+          if (st_theta != -2.f || st_mode == 1) break;
         }
-        for (int k = tid; k < kBins; k += kChainBlock) hist[k] = 0u;
+      }
+      // ---------------- collect, ordered by fine bins over [max(theta,0), rref]
+      if (st_mode == 0) {
+        const float lo = st_lo, wdt = st_w, theta = st_theta;
+        const int bstar = st_bstar;
+        const float flo = fmaxf(theta, 0.f);
+        const float fw = (rref - flo) / (float)kBins;
+        const bool fine = fw > 0.f;
+        auto member = [&](float d) {
+          return d >= 0.f && d >= theta && (theta < 0.f || (d >= lo && bin_of(d, lo, wdt) >= bstar));
+        };
+        auto fbin = [&](float d) { return fine ? bin_of(d, flo, fw) : kBins - 1; };
+        for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
         __syncthreads();
         for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
           float dd[kUnroll];
@@ -300,53 +363,21 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
           }
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u)
-            if (dd[u] >= lo) {
-              int bb = (int)((dd[u] - lo) / wdt);
-              bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
-              atomicAdd(&hist[bb], 1u);
-            }
+            if (member(dd[u])) atomicAdd(&S.hist[fbin(dd[u])], 1u);
         }
         __syncthreads();
         if (tid == 0) {
-          int cum = 0, bb = kBins - 1;
-          for (; bb >= 0; --bb) {
-            if (cum + (int)hist[bb] > cap) break;
-            cum += (int)hist[bb];
-          }
-          if (bb < 0) {  // everything at or above lo fits
-            st_bstar = 0;
-            st_theta = level == 0 ? -1.f : lo;
-          } else if (bb < kBins - 1) {
-            st_bstar = bb + 1;
-            st_theta = lo + (float)(bb + 1) * wdt;
-          } else if (level == 0) {  // the top bin alone overflows: refine inside it
-            st_lo = lo + (float)(kBins - 1) * wdt;
-            st_w = wdt / (float)kBins;
-            st_theta = -2.f;
-          } else {
-            st_mode = 1;
-          }
-        }
-        __syncthreads();
-        if (st_theta != -2.f || st_mode == 1) break;
-      }
-      // -------------------------------------------- collect, sorted by bin
-      if (st_mode == 0) {
-        const float lo = st_lo, wdt = st_w, theta = st_theta;
-        const int bstar = st_bstar;
-        if (tid == 0) {
-          // entries in decreasing bin order: cursor[b] = first slot of bin b
+          // entries in decreasing fine-bin order: cursor[b] = first slot of bin b
           unsigned int c = 0;
-          for (int bb = kBins - 1; bb >= bstar; --bb) {
-            cursor[bb] = c;
-            c += hist[bb];
+          for (int bb = kBins - 1; bb >= 0; --bb) {
+            S.cursor[bb] = c;
+            c += S.hist[bb];
           }
           sh_n = c;
+          if (c > (unsigned)cap) st_mode = 1;
         }
         __syncthreads();
-        if (sh_n > (unsigned)cap) {
-          if (tid == 0) st_mode = 1;
-        } else {
+        if (st_mode == 0) {
           for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
             float dd[kUnroll];
 #pragma unroll
@@ -357,35 +388,28 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
               int s = s0 + u * kChainBlock + tid;
-              if (dd[u] >= 0.f && dd[u] >= theta) {
-                int bb = dd[u] >= lo ? (int)((dd[u] - lo) / wdt) : 0;
-                bb = bb < 0 ? 0 : (bb >= kBins ? kBins - 1 : bb);
-                if (bb >= bstar) {
-                  unsigned int pos = atomicAdd(&cursor[bb], 1u);
-                  if (pos < (unsigned)cap) {
-                    sh_pt[pos] = D[s];
-                    sh_id[pos] = s;
-                  }
+              if (member(dd[u])) {
+                unsigned int pos = atomicAdd(&S.cursor[fbin(dd[u])], 1u);
+                if (pos < (unsigned)cap) {
+                  S.pt[pos] = D[s];
+                  S.id[pos] = s;
                 }
               }
             }
           }
-        }
-        __syncthreads();
-        // upper bound of d_ref over each chunk of 64 entries: the upper edge
-        // of the bin holding its first entry (entries are in decreasing bins)
-        if (st_mode == 0) {
+          __syncthreads();
+          // upper bound of d_ref over each chunk of 64 entries: the upper edge
+          // of the fine bin holding its first entry (the top bin's is rref)
           const int K = (int)sh_n;
           for (int c = tid; c * 64 < K && c < kMaxChunks; c += kChainBlock) {
-            int e = c * 64;
-            // bin of entry e: the bb with cursor_end... recount from hist
+            const unsigned int e = (unsigned)c * 64u;
             unsigned int acc_n = 0;
             int bb = kBins - 1;
-            for (; bb >= bstar; --bb) {
-              if ((unsigned)e < acc_n + hist[bb]) break;
-              acc_n += hist[bb];
+            for (; bb > 0; --bb) {
+              if (e < acc_n + S.hist[bb]) break;
+              acc_n += S.hist[bb];
             }
-            chunk_ub[c] = (bb >= kBins - 1) ? 3.0e38f : lo + (float)(bb + 1) * wdt;
+            S.chunk_ub[c] = (bb >= kBins - 1 || !fine) ? rref : flo + (float)(bb + 1) * fw;
           }
         }
         __syncthreads();
@@ -425,17 +449,17 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
         int wi;
         wave_argmax(bk, bi, wk, wi);
         if (lane == 0) {
-          red_k[par][wave] = wk;
-          red_i[par][wave] = wi;
+          S.red_k[par][wave] = wk;
+          S.red_i[par][wave] = wi;
         }
         __syncthreads();
-        bk = red_k[par][0];
-        bi = red_i[par][0];
+        bk = S.red_k[par][0];
+        bi = S.red_i[par][0];
 #pragma unroll
         for (int w = 1; w < kChainWaves; ++w)
-          if (better(red_k[par][w], red_i[par][w], bk, bi)) {
-            bk = red_k[par][w];
-            bi = red_i[par][w];
+          if (better(S.red_k[par][w], S.red_i[par][w], bk, bi)) {
+            bk = S.red_k[par][w];
+            bi = S.red_i[par][w];
           }
         par ^= 1;
         C = geodesic_step(C, D[bi], i, chain);
@@ -451,14 +475,17 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
       stalled = false;
     } else {
       // ---------------------------------------------------------- shell steps
-      // wave 0 alone.  Entries sit in chunks of 64 in decreasing distance
-      // bins; each lane keeps its own best over a group of kGroup chunks, one
-      // wavefront reduction per group, and the scan stops once no later
-      // chunk can beat the best found.
+      // Wave 0 alone.  Entries sit in chunks of 64 in decreasing fine bins of
+      // d_ref; each lane keeps its own best over a group of kGroup chunks (the
+      // next group's entries are loaded while this one is reduced), one
+      // wavefront reduction per group, and the scan stops once no later chunk
+      // can beat the best found.  When a step needs many groups the centre has
+      // drifted from C_ref: the stage ends and the next one rescans there.
       const int K = (int)sh_n;
       const float theta = st_theta;
-      const float slack = 4e-6f * sqrtf(sqdist(Cref, sh_pt[0], chain)) + 1e-30f;
+      const float slack = 4e-6f * st_rref + 1e-30f;
       const int nchunks = (K + 63) / 64;
+      const int ngroups = (nchunks + kGroup - 1) / kGroup;
       if (wave == 0) {
         float4 C = Cref;
         int i = i0;
@@ -466,37 +493,59 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
           const float dC = sqrtf(sqdist(C, Cref, chain));
           float bk = -1.f;
           int bi = INT32_MAX, be = 0;
+          float4 p[kGroup];
+          int q[kGroup];
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u) {
+            const int e = u * 64 + lane;
+            p[u] = S.pt[e];
+            q[u] = S.id[e];
+          }
           float wk;
-          int wi;
-          int c = 0;
+          int g = 0;
           while (true) {
-            const int cend = min(nchunks, c + kGroup);
-            for (; c < cend; ++c) {
-              const int e = c * 64 + lane;
+            float4 np[kGroup];
+            int nq[kGroup];
+            const bool more = g + 1 < ngroups;
+            if (more) {
+#pragma unroll
+              for (int u = 0; u < kGroup; ++u) {
+                const int e = ((g + 1) * kGroup + u) * 64 + lane;
+                np[u] = S.pt[e];
+                nq[u] = S.id[e];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+              const int e = (g * kGroup + u) * 64 + lane;
               if (e < K) {
-                float k = sqdist(C, sh_pt[e], chain);
-                int id = sh_id[e];
-                if (better(k, id, bk, bi)) {
+                const float k = sqdist(C, p[u], chain);
+                if (better(k, q[u], bk, bi)) {
                   bk = k;
-                  bi = id;
+                  bi = q[u];
                   be = e;
                 }
               }
             }
             wk = wave_max_key(bk);
-            ++n_groups;
-            if (c >= nchunks || sqrtf(wk) > chunk_ub[c] + dC + slack) break;
+            ++g;
+            if (!more || sqrtf(wk) > S.chunk_ub[g * kGroup] + dC + slack) break;
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+              p[u] = np[u];
+              q[u] = nq[u];
+            }
           }
-          wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
+          n_groups += g;
           if (theta >= 0.f && !(sqrtf(wk) > theta + dC + slack)) break;  // the shell no longer suffices
+          const int wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
           const unsigned long long win = __ballot(bk == wk && bi == wi);
           const int we = __builtin_amdgcn_readlane(be, (int)__ffsll((long long)win) - 1);
-          const float4 pt = sh_pt[we];
-          C = geodesic_step(C, pt, i, chain);
-          bi = wi;
-          if (lane == 0) tr[2 * (i - 1)] = bi;
+          C = geodesic_step(C, S.pt[we], i, chain);
+          if (lane == 0) tr[2 * (i - 1)] = wi;
           if (i > T - avg) accumulate_iterate(C, chain, acc);
           ++i;
+          if (g > kRecentreGroups && i - i0 > kMinShellSteps) break;  // re-centre the shell
         }
         if (lane == 0) {
           st_C = C;
@@ -525,6 +574,27 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
       for (int k = 0; k < 3; ++k) rec[j].centre[9 + k] = acc[k] / (float)na;
     }
   }
+}
+
+// One workgroup of kChainBlock threads per (instance, chain): even blocks
+// run the rotation chain, odd blocks the translation chain.
+__global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+                                                            const float4 *__restrict__ quat,
+                                                            const float4 *__restrict__ trans, MegbRec *rec,
+                                                            float *dref_all, int64_t total_samples,
+                                                            int32_t *trace, int T, int avg, int cap,
+                                                            int no_prune) {
+  extern __shared__ float4 sh_pt[];
+  __shared__ unsigned int hist[kBins];
+  __shared__ unsigned int cursor[kBins];
+  __shared__ float chunk_ub[kMaxChunks];
+  __shared__ float red_k[2][kChainWaves];
+  __shared__ int red_i[2][kChainWaves];
+  const ChainShared S{sh_pt, reinterpret_cast<int *>(sh_pt + cap), hist, cursor, chunk_ub, red_k, red_i};
+  if (blockIdx.x & 1)
+    chain_run<1>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
+  else
+    chain_run<0>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
 }
 
 // float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.

@@ -4,6 +4,9 @@
         Markdown table of the per-kernel statistics (--kernel-trace --stats)
         found under DIR.
 
+    python -m paper_2403_09990_amd.profile_summary counters DIR --kernel NAME
+        Mean per dispatch of every counter of a --pmc run for one kernel.
+
     python -m paper_2403_09990_amd.profile_summary traffic FETCH_DIR WRITE_DIR
             --kernel k_sample --copy-bytes B --out FILE.json [--cmd-fetch C] [--cmd-write C]
         HBM bytes per dispatch of a kernel from two --pmc runs (FETCH_SIZE, then
@@ -18,6 +21,7 @@ import glob
 import hashlib
 import json
 import os
+import sqlite3
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -31,11 +35,25 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _find(dirname, suffix):
+def _find(dirname, suffix, required=True):
     hits = sorted(glob.glob(os.path.join(dirname, "**", "*" + suffix), recursive=True))
-    if not hits:
+    if not hits and required:
         raise FileNotFoundError("no *%s under %s" % (suffix, dirname))
     return hits
+
+
+def _db_rows(dirname, query):
+    """Rows of a query over every rocpd database (*_results.db) under dirname."""
+    rows = []
+    for path in _find(dirname, "results.db"):
+        con = sqlite3.connect(path)
+        try:
+            cur = con.execute(query)
+            names = [d[0] for d in cur.description]
+            rows += [dict(zip(names, r), _path=path) for r in cur.fetchall()]
+        finally:
+            con.close()
+    return rows
 
 
 def _short(name: str) -> str:
@@ -43,11 +61,28 @@ def _short(name: str) -> str:
     return name if len(name) <= 90 else name[:87] + "..."
 
 
-def stats(dirname, title=None, cmd=None):
+def _kernel_rows(dirname):
+    """Per-kernel statistics, from the CSV output or the rocpd database."""
     rows = []
-    for path in _find(dirname, "kernel_stats.csv"):
+    for path in _find(dirname, "kernel_stats.csv", required=False):
         with open(path) as f:
             rows += list(csv.DictReader(f))
+    if rows:
+        return rows
+    disp = _db_rows(dirname, "select name, duration from kernels")
+    by = {}
+    for r in disp:
+        by.setdefault(r["name"], []).append(float(r["duration"]))
+    total = sum(sum(v) for v in by.values()) or 1.0
+    for name, v in by.items():
+        rows.append({"Name": name, "Calls": str(len(v)), "TotalDurationNs": sum(v),
+                     "AverageNs": sum(v) / len(v), "MinNs": min(v), "MaxNs": max(v),
+                     "Percentage": 100.0 * sum(v) / total})
+    return rows
+
+
+def stats(dirname, title=None, cmd=None):
+    rows = _kernel_rows(dirname)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = []
     if title:
@@ -66,19 +101,38 @@ def stats(dirname, title=None, cmd=None):
 
 
 def _per_dispatch(dirname, counter):
-    """{dispatch id: (kernel name, value)} of one counter."""
+    """[(kernel name, value)] of one counter, one entry per dispatch (values
+    of the counter's instances summed)."""
     vals = {}
-    for path in _find(dirname, "counter_collection.csv"):
+    for path in _find(dirname, "counter_collection.csv", required=False):
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r.get("Counter_Name") != counter:
                     continue
                 key = (path, r["Dispatch_Id"])
-                name = r["Kernel_Name"]
-                v = float(r["Counter_Value"])
-                prev = vals.get(key, (name, 0.0))[1]
-                vals[key] = (name, prev + v)
+                prev = vals.get(key, (r["Kernel_Name"], 0.0))[1]
+                vals[key] = (r["Kernel_Name"], prev + float(r["Counter_Value"]))
+    if not vals:
+        q = ("select dispatch_id, kernel_name, value from counters_collection where counter_name = '%s'"
+             % counter)
+        for r in _db_rows(dirname, q):
+            key = (r["_path"], r["dispatch_id"])
+            prev = vals.get(key, (r["kernel_name"], 0.0))[1]
+            vals[key] = (r["kernel_name"], prev + float(r["value"]))
     return list(vals.values())
+
+
+def counters(dirname, kernel):
+    """Mean per dispatch of every counter collected for dispatches of kernel."""
+    q = "select dispatch_id, kernel_name, counter_name, value from counters_collection"
+    acc = {}
+    for r in _db_rows(dirname, q):
+        if kernel not in r["kernel_name"]:
+            continue
+        d = acc.setdefault(r["counter_name"], {})
+        key = (r["_path"], r["dispatch_id"])
+        d[key] = d.get(key, 0.0) + float(r["value"])
+    return {c: sum(v.values()) / len(v) for c, v in acc.items()}
 
 
 def _mean_for(disp, pred):
@@ -93,7 +147,7 @@ def traffic(fetch_dir, write_dir, kernel, copy_bytes, out, cmd_fetch=None, cmd_w
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         disp = _per_dispatch(d, counter)
         k_kib, nk = _mean_for(disp, lambda n: kernel in n)
-        copies = [x for n, x in disp if "copy" in n.lower()]
+        copies = [x for n, x in disp if "copy" in n.lower() or "elementwise" in n.lower()]
         if k_kib is None or not copies:
             raise RuntimeError("%s: kernel or calibration copy not found in %s" % (counter, d))
         c_kib = max(copies)
@@ -115,6 +169,9 @@ def main(argv=None):
     a.add_argument("--title")
     a.add_argument("--cmd")
     a.add_argument("--out")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernel", required=True)
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -124,6 +181,9 @@ def main(argv=None):
     b.add_argument("--cmd-fetch")
     b.add_argument("--cmd-write")
     args = ap.parse_args(argv)
+    if args.mode == "counters":
+        print(json.dumps(counters(args.dir, args.kernel), indent=1))
+        return
     if args.mode == "stats":
         text = stats(args.dir, args.title, args.cmd)
         if args.out:
