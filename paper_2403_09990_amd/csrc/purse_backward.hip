@@ -22,8 +22,10 @@ namespace purse {
 
 namespace {
 
-constexpr int kBwdBlock = 1024;
+constexpr int kBwdBlock = 256;
 constexpr int kBwdWaves = kBwdBlock / 64;
+constexpr int kLdsTrace = 8192;  // descents up to this length are replayed from LDS
+static_assert(kMaxActive <= 256, "active-set slots are bytes");
 
 using D = double;
 
@@ -177,6 +179,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __shared__ int act[kMaxActive];
   __shared__ int n_act_s, overflow_s;
   __shared__ double cot[kMaxActive][12];
+  __shared__ float pact[kMaxActive][12];       // poses of the active samples
+  __shared__ uint8_t tslot[2 * kLdsTrace];     // trace as active-set slots
+  __shared__ double seg[kMaxCkpt][9];          // one recomputed checkpoint segment
   __shared__ double Rstar[9], tstar[3], Ssum[9];
   __shared__ double red_v[kBwdWaves];
   __shared__ int red_i[kBwdWaves];
@@ -256,17 +261,30 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     last = mn;
   }
   __syncthreads();
+  // ---- stage the active samples' poses and the trace (as slots) in LDS: the
+  // serial sweeps below then read nothing from global memory per step
+  const bool lds_trace = T <= kLdsTrace && !overflow_s;
+  if (!overflow_s) {
+    for (int k = tid; k < n_act_s * 12; k += kBwdBlock) pact[k / 12][k % 12] = poses[12 * (off + act[k / 12]) + k % 12];
+    if (lds_trace)
+      for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act_s, tr[k]);
+  }
+  __syncthreads();
+  auto slot_of = [&](int k) { return lds_trace ? (int)tslot[k] : find_active(act, n_act_s, tr[k]); };
+  auto load_act = [&](int a, D R[9]) {
+    for (int q = 0; q < 9; ++q) R[q] = (D)pact[a][q];
+  };
   // ---- replay the descent in float64 (thread 0: rotation, thread 64: translation)
   double *ckpt = ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9;
-  if (tid == 0) {
+  if (tid == 0 && !overflow_s) {
     D C[9], S[9];
-    load_R(poses, off + s0, C);
+    load_act(find_active(act, n_act_s, s0), C);
     for (int k = 0; k < 9; ++k) S[k] = 0;
     for (int i = 1; i <= T; ++i) {
       if ((i - 1) % ck == 0)
         for (int k = 0; k < 9; ++k) ckpt[((i - 1) / ck) * 9 + k] = C[k];
       D R[9], Y[9], phi[3], Cn[9];
-      load_R(poses, off + tr[2 * (i - 1)], R);
+      load_act(slot_of(2 * (i - 1)), R);
       step_rot(C, R, i, Cn, Y, phi);
       for (int k = 0; k < 9; ++k) C[k] = Cn[k];
       if (i > T - avg)
@@ -278,11 +296,11 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       Rstar[k] = Rs[k];
       Ssum[k] = S[k];
     }
-  } else if (tid == 64) {
+  } else if (tid == 64 && !overflow_s) {
     D c[3], acc[3] = {0, 0, 0};
     for (int r = 0; r < 3; ++r) c[r] = poses[12 * (off + s0) + 9 + r];
     for (int i = 1; i <= T; ++i) {
-      const float *P = poses + 12 * (off + tr[2 * (i - 1) + 1]);
+      const float *P = pact[slot_of(2 * (i - 1) + 1)];
       for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) / i;
       if (i > T - avg)
         for (int r = 0; r < 3; ++r) acc[r] += c[r];
@@ -427,23 +445,25 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     D Cb[9];
     for (int k = 0; k < 9; ++k) Cb[k] = 0;
     const int nseg = (T + ck - 1) / ck;
-    D seg[kMaxCkpt][9];
     for (int sg = nseg - 1; sg >= 0; --sg) {
       const int i_lo = sg * ck + 1, i_hi = min(T, (sg + 1) * ck);
       // seg[q] = C_{i_lo - 1 + q}
       for (int k = 0; k < 9; ++k) seg[0][k] = ckpt[sg * 9 + k];
       for (int i = i_lo; i < i_hi; ++i) {
-        D R[9], Y[9], phi[3];
-        load_R(poses, off + tr[2 * (i - 1)], R);
-        step_rot(seg[i - i_lo], R, i, seg[i - i_lo + 1], Y, phi);
+        D R[9], Y[9], phi[3], Cq[9], Cn[9];
+        load_act(slot_of(2 * (i - 1)), R);
+        for (int k = 0; k < 9; ++k) Cq[k] = seg[i - i_lo][k];
+        step_rot(Cq, R, i, Cn, Y, phi);
+        for (int k = 0; k < 9; ++k) seg[i - i_lo + 1][k] = Cn[k];
       }
       for (int i = i_hi; i >= i_lo; --i) {
         if (i > T - avg)
           for (int k = 0; k < 9; ++k) Cb[k] += Sbar[k];
-        const D *Cp = seg[i - i_lo];
-        const int s = tr[2 * (i - 1)];
+        D Cp[9];
+        for (int k = 0; k < 9; ++k) Cp[k] = seg[i - i_lo][k];
+        const int pa = slot_of(2 * (i - 1));
         D R[9], Y[9], phi[3], Cn[9];
-        load_R(poses, off + s, R);
+        load_act(pa, R);
         step_rot(Cp, R, i, Cn, Y, phi);
         D E[9];
         exp_so3<D>(phi, E);
@@ -456,7 +476,6 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         D t1[9], t2[9];
         matmul_nt(R, Yb, t1);        // C_bar_prev += R Y_bar^T
         matmul3<D>(Cp, Yb, t2);      // R_bar += C Y_bar
-        const int pa = find_active(act, n_act, s);
         for (int k = 0; k < 9; ++k) {
           Cb[k] = Cbp[k] + t1[k];
           if (pa >= 0) cot[pa][k] += t2[k];
@@ -483,7 +502,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     for (int i = T; i >= 1; --i) {
       if (i > T - avg)
         for (int r = 0; r < 3; ++r) cb[r] += tb[r] / avg;
-      const int pa = find_active(act, n_act, tr[2 * (i - 1) + 1]);
+      const int pa = slot_of(2 * (i - 1) + 1);
       for (int r = 0; r < 3; ++r) {
         if (pa >= 0) cot[pa][9 + r] += cb[r] / i;
         cb[r] *= (1.0 - 1.0 / i);

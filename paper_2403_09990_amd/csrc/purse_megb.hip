@@ -25,7 +25,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBins = 256;
 constexpr int kGlobalSteps = 64;
-constexpr int kChainBlock = 1024;
+constexpr int kChainBlock = 512;
 constexpr int kChainWaves = kChainBlock / 64;
 constexpr int kUnroll = 8;
 constexpr int kCap = 3072;
@@ -53,7 +53,30 @@ __device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
   return d0 * d0 + d1 * d1 + d2 * d2;
 }
 
+// sin and cos on [0, pi/2] by their Taylor series through x^13 and x^14
+// (truncation below 7e-10 there), evaluated in x^2 by Horner's rule.
+__device__ __forceinline__ void sincos_quadrant(float x, float &s, float &c) {
+  const float z = x * x;
+  float ps = 1.f / 6227020800.f;       // 1/13!
+  ps = ps * z - 1.f / 39916800.f;      // 1/11!
+  ps = ps * z + 1.f / 362880.f;        // 1/9!
+  ps = ps * z - 1.f / 5040.f;          // 1/7!
+  ps = ps * z + 1.f / 120.f;
+  ps = ps * z - 1.f / 6.f;
+  s = x + x * (ps * z);
+  float pc = 1.f / 87178291200.f;      // 1/14!
+  pc = pc * z - 1.f / 479001600.f;     // 1/12!
+  pc = pc * z + 1.f / 3628800.f;       // 1/10!
+  pc = pc * z - 1.f / 40320.f;         // 1/8!
+  pc = pc * z + 1.f / 720.f;
+  pc = pc * z - 1.f / 24.f;
+  pc = pc * z + 0.5f;
+  c = 1.f - pc * z;
+}
+
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
+// With r = conj(a) b = (cos h, sin h u) (sign of b chosen so that h <= pi/2),
+// the step is a (cos(h / i), sin(h / i) u).
 __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
   const float inv = 1.f / (float)i;
   if (chain == 1) return make_float4(a.x + (b.x - a.x) * inv, a.y + (b.y - a.y) * inv, a.z + (b.z - a.z) * inv, 1.f);
@@ -61,13 +84,13 @@ __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int c
   if (dt < 0.f) b = make_float4(-b.x, -b.y, -b.z, -b.w);
   float4 ac = make_float4(a.x, -a.y, -a.z, -a.w);
   float4 r = quat_mul(ac, b);
-  float sn = sqrtf(r.y * r.y + r.z * r.z + r.w * r.w);
-  if (!(sn > 0.f)) return a;
-  float half = atan2f(sn, r.x);
-  float ph = half * inv;
+  float sn2 = r.y * r.y + r.z * r.z + r.w * r.w;
+  if (!(sn2 > 0.f)) return a;
+  float isn = rsqrtf(sn2);
+  float half = atan2f(sn2 * isn, fmaxf(r.x, 0.f));
   float s, c;
-  sincosf(ph, &s, &c);
-  float f = s / sn;
+  sincos_quadrant(half * inv, s, c);
+  float f = s * isn;
   float4 e = make_float4(c, f * r.y, f * r.z, f * r.w);
   float4 q = quat_mul(a, e);
   float nn = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
@@ -100,6 +123,10 @@ __device__ __forceinline__ int wave_min_i32(int v) {
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xA, 0xF, false));
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xC, 0xF, false));
   return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 // Keys are squared distances (>= 0) or the sentinel -1: their float bit
@@ -476,72 +503,97 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
     } else {
       // ---------------------------------------------------------- shell steps
       // Wave 0 alone.  Entries sit in chunks of 64 in decreasing fine bins of
-      // d_ref; each lane keeps its own best over a group of kGroup chunks (the
-      // next group's entries are loaded while this one is reduced), one
-      // wavefront reduction per group, and the scan stops once no later chunk
-      // can beat the best found.  When a step needs many groups the centre has
-      // drifted from C_ref: the stage ends and the next one rescans there.
+      // d_ref.  Each lane keeps its own best (key, id, point) over a group of
+      // kGroup chunks, one wavefront reduction per group, and the scan stops
+      // once no later chunk can beat the best found.  The first two groups,
+      // which almost every step needs, stay in registers for the whole stage;
+      // later groups are read from LDS, the next one while this one is
+      // reduced.  When a step needs many groups the centre has drifted from
+      // C_ref: the stage ends and the next one rescans there.
       const int K = (int)sh_n;
       const float theta = st_theta;
       const float slack = 4e-6f * st_rref + 1e-30f;
       const int nchunks = (K + 63) / 64;
       const int ngroups = (nchunks + kGroup - 1) / kGroup;
       if (wave == 0) {
+        float4 p0[kGroup], p1[kGroup];
+        int q0[kGroup], q1[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          p0[u] = S.pt[u * 64 + lane];
+          q0[u] = S.id[u * 64 + lane];
+          p1[u] = S.pt[(kGroup + u) * 64 + lane];
+          q1[u] = S.id[(kGroup + u) * 64 + lane];
+        }
+        const float ub1 = ngroups > 1 ? S.chunk_ub[kGroup] : 0.f;
+        const float ub2 = ngroups > 2 ? S.chunk_ub[2 * kGroup] : 0.f;
         float4 C = Cref;
         int i = i0;
         while (i <= T) {
           const float dC = sqrtf(sqdist(C, Cref, chain));
           float bk = -1.f;
-          int bi = INT32_MAX, be = 0;
-          float4 p[kGroup];
-          int q[kGroup];
-#pragma unroll
-          for (int u = 0; u < kGroup; ++u) {
-            const int e = u * 64 + lane;
-            p[u] = S.pt[e];
-            q[u] = S.id[e];
-          }
-          float wk;
-          int g = 0;
-          while (true) {
-            float4 np[kGroup];
-            int nq[kGroup];
-            const bool more = g + 1 < ngroups;
-            if (more) {
-#pragma unroll
-              for (int u = 0; u < kGroup; ++u) {
-                const int e = ((g + 1) * kGroup + u) * 64 + lane;
-                np[u] = S.pt[e];
-                nq[u] = S.id[e];
-              }
-            }
+          int bi = INT32_MAX;
+          float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
+          auto scan = [&](const float4 *pp, const int *qq, int g) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-              const int e = (g * kGroup + u) * 64 + lane;
-              if (e < K) {
-                const float k = sqdist(C, p[u], chain);
-                if (better(k, q[u], bk, bi)) {
+              if ((g * kGroup + u) * 64 + lane < K) {
+                const float k = sqdist(C, pp[u], chain);
+                if (better(k, qq[u], bk, bi)) {
                   bk = k;
-                  bi = q[u];
-                  be = e;
+                  bi = qq[u];
+                  bp = pp[u];
                 }
               }
             }
+          };
+          scan(p0, q0, 0);
+          float wk = wave_max_key(bk);
+          int g = 1;
+          if (ngroups > 1 && !(sqrtf(wk) > ub1 + dC + slack)) {
+            scan(p1, q1, 1);
             wk = wave_max_key(bk);
-            ++g;
-            if (!more || sqrtf(wk) > S.chunk_ub[g * kGroup] + dC + slack) break;
+            g = 2;
+            if (ngroups > 2 && !(sqrtf(wk) > ub2 + dC + slack)) {
+              float4 p[kGroup];
+              int q[kGroup];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-              p[u] = np[u];
-              q[u] = nq[u];
+              for (int u = 0; u < kGroup; ++u) {
+                p[u] = S.pt[(2 * kGroup + u) * 64 + lane];
+                q[u] = S.id[(2 * kGroup + u) * 64 + lane];
+              }
+              while (true) {
+                float4 np[kGroup];
+                int nq[kGroup];
+                const bool more = g + 1 < ngroups;
+                if (more) {
+#pragma unroll
+                  for (int u = 0; u < kGroup; ++u) {
+                    const int e = ((g + 1) * kGroup + u) * 64 + lane;
+                    np[u] = S.pt[e];
+                    nq[u] = S.id[e];
+                  }
+                }
+                scan(p, q, g);
+                wk = wave_max_key(bk);
+                ++g;
+                if (!more || sqrtf(wk) > S.chunk_ub[g * kGroup] + dC + slack) break;
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u) {
+                  p[u] = np[u];
+                  q[u] = nq[u];
+                }
+              }
             }
           }
           n_groups += g;
           if (theta >= 0.f && !(sqrtf(wk) > theta + dC + slack)) break;  // the shell no longer suffices
           const int wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
           const unsigned long long win = __ballot(bk == wk && bi == wi);
-          const int we = __builtin_amdgcn_readlane(be, (int)__ffsll((long long)win) - 1);
-          C = geodesic_step(C, S.pt[we], i, chain);
+          const int wl = (int)__ffsll((long long)win) - 1;
+          const float4 pt = make_float4(readlane_f(bp.x, wl), readlane_f(bp.y, wl), readlane_f(bp.z, wl),
+                                        readlane_f(bp.w, wl));
+          C = geodesic_step(C, pt, i, chain);
           if (lane == 0) tr[2 * (i - 1)] = wi;
           if (i > T - avg) accumulate_iterate(C, chain, acc);
           ++i;
