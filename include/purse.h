@@ -77,6 +77,8 @@ typedef int32_t purse_status;
 #define PURSE_FLAG_INSTANCE_ORDER 8   /* purse_sample: run the tiles in instance order instead of the
                                          default heaviest-first order (results are identical; this only
                                          changes the schedule, for tuning) */
+#define PURSE_FLAG_GENERIC_LOOP 16    /* purse_sample: use the general keypoint loop even when every
+                                         instance has at most 16 keypoints (for tuning) */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints

@@ -1,8 +1,10 @@
 """Autotuner of the sampler's launch schedule.
 
 The sampler's results do not depend on the schedule: only the workgroup size
-(params.tile: 64, 128 or 256 samples) and the tile order (heaviest instances
-first, or instance order with PURSE_FLAG_INSTANCE_ORDER) change its speed.
+(params.tile: 64, 128 or 256 samples), the tile order (heaviest instances
+first, or instance order with PURSE_FLAG_INSTANCE_ORDER) and, for 2D-3D
+batches of at most 16 keypoints, the keypoint loop (unrolled, or the general
+one with PURSE_FLAG_GENERIC_LOOP) change its speed.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -13,10 +15,13 @@ import json
 import os
 from typing import Optional
 
-from . import PURSE_FLAG_INSTANCE_ORDER, purse_default_params, purse_sample
+from . import PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, purse_default_params, purse_sample
 
 TILES = (64, 128, 256)
 ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
+LOOPS = (0, PURSE_FLAG_GENERIC_LOOP)
+SMALL_N = 16
+_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP
 
 
 def default_cache_path() -> str:
@@ -55,13 +60,18 @@ def _store(path, table):
     os.replace(tmp, path)
 
 
-def _with(params, tile, order):
+def _with(params, tile, flags):
     p = purse_default_params()
     for name, _ in type(params)._fields_:
         setattr(p, name, getattr(params, name))
     p.tile = tile
-    p.flags = (params.flags & ~PURSE_FLAG_INSTANCE_ORDER) | order
+    p.flags = (params.flags & ~_TUNED) | flags
     return p
+
+
+def _name(tile, flags):
+    return "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first",
+                         "generic" if flags & PURSE_FLAG_GENERIC_LOOP else "unrolled")
 
 
 def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
@@ -76,26 +86,29 @@ def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
     table = _load(path)
     if not force and key in table:
         rec = table[key]
-        return _with(params, rec["tile"], rec["order"]), dict(rec, cached=True)
+        return _with(params, rec["tile"], rec["flags"]), dict(rec, cached=True)
     if stream is None:
         stream = torch.cuda.current_stream()
-    times = {}
+    loops = LOOPS if db.max_kp <= SMALL_N and bool((db.kind == 1).any()) else (0,)
+    times, cand = {}, {}
     for tile in TILES:
         for order in ORDERS:
-            p = _with(params, tile, order)
-            purse_sample(db, p, poses, mask, inst_status, ws, stream)  # warm-up
-            s = torch.cuda.Event(enable_timing=True)
-            e = torch.cuda.Event(enable_timing=True)
-            s.record(stream)
-            for _ in range(reps):
-                purse_sample(db, p, poses, mask, inst_status, ws, stream)
-            e.record(stream)
-            e.synchronize()
-            times["%d/%s" % (tile, "instance" if order else "heaviest-first")] = s.elapsed_time(e) / reps
+            for loop in loops:
+                p = _with(params, tile, order | loop)
+                purse_sample(db, p, poses, mask, inst_status, ws, stream)  # warm-up
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record(stream)
+                for _ in range(reps):
+                    purse_sample(db, p, poses, mask, inst_status, ws, stream)
+                e.record(stream)
+                e.synchronize()
+                name = _name(tile, order | loop)
+                times[name] = s.elapsed_time(e) / reps
+                cand[name] = (tile, order | loop)
     best = min(times, key=times.get)
-    tile = int(best.split("/")[0])
-    order = PURSE_FLAG_INSTANCE_ORDER if best.endswith("instance") else 0
-    rec = {"tile": tile, "order": order, "ms": times[best], "candidates_ms": times}
+    tile, flags = cand[best]
+    rec = {"tile": tile, "flags": flags, "choice": best, "ms": times[best], "candidates_ms": times}
     table[key] = rec
     _store(path, table)
-    return _with(params, tile, order), dict(rec, cached=False)
+    return _with(params, tile, flags), dict(rec, cached=False)

@@ -5,8 +5,10 @@
 //    float64 from the trace, keeping every ckpt_every-th rotation iterate;
 //    the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
 //    centre projection, the last-iterate average and the T geodesic steps
-//    (segments recomputed from their checkpoint), onto the few samples the
-//    trace touches (the active set).
+//    onto the few samples the trace touches (the active set): the 3x3
+//    tangent Jacobians of the steps are formed in parallel, a chunk of steps
+//    at a time, each step recomputed from its checkpoint, and only their
+//    products run serially.
 // 2. k_bwd_frame: per input direction, the tangent of the centre fit, pivot
 //    and anchor (the fit re-run in float64 dual numbers from its start).
 // 3. k_bwd_traj: per (active sample, input direction), the trajectory re-run
@@ -44,14 +46,6 @@ __device__ __forceinline__ void matmul_tn(const D A[9], const D B[9], D C[9]) {
     for (int c = 0; c < 3; ++c) C[3 * r + c] = A[r] * B[c] + A[3 + r] * B[3 + c] + A[6 + r] * B[6 + c];
 }
 
-// C = A B^T
-__device__ __forceinline__ void matmul_nt(const D A[9], const D B[9], D C[9]) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[3 * c] + A[3 * r + 1] * B[3 * c + 1] + A[3 * r + 2] * B[3 * c + 2];
-}
-
 // v(X) = vee(X - X^T), so that <X, [w]x> = w . v(X)
 __device__ __forceinline__ void vskew(const D X[9], D v[3]) {
   v[0] = X[7] - X[5];
@@ -71,83 +65,22 @@ __device__ __forceinline__ void hat_d(const D w[3], D W[9]) {
   W[8] = 0;
 }
 
-// One descent step C_i = C Exp(Log(C^T R) / i) (float64 matrix form).
-__device__ __forceinline__ void step_rot(const D C[9], const D R[9], int i, D Cn[9], D Y[9], D phi[3]) {
-  matmul_tn(C, R, Y);
-  D w[3];
-  log_so3<D>(Y, w);
-  phi[0] = w[0] / i;
-  phi[1] = w[1] / i;
-  phi[2] = w[2] / i;
-  D E[9];
-  exp_so3<D>(phi, E);
-  matmul3<D>(C, E, Cn);
-}
-
-// VJP of E = Exp(phi) = cos(th) I + A [phi]x + B phi phi^T:
-// phi_bar = (-(sin th/th) tr Eb + (A'/th) phi.v(Eb) + (B'/th) phi^T Eb phi) phi
-//           + A v(Eb) + B (Eb + Eb^T) phi.
-__device__ __forceinline__ void vjp_exp(const D phi[3], const D Eb[9], D pb[3]) {
-  D th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
-  D A, B, sA, dA, dB;  // sA = sin th / th, dA = A'/th, dB = B'/th
-  if (th2 < 1e-12) {
-    A = 1.0 - th2 / 6.0;
-    B = 0.5 - th2 / 24.0;
-    sA = A;
-    dA = -1.0 / 3.0 + th2 / 30.0;
-    dB = -1.0 / 12.0 + th2 / 180.0;
-  } else {
-    D th = sqrt(th2), s = sin(th), c = cos(th);
-    A = s / th;
-    B = (1.0 - c) / th2;
-    sA = A;
-    dA = (th * c - s) / (th2 * th);
-    dB = (th * s - 2.0 * (1.0 - c)) / (th2 * th2);
-  }
-  D v[3];
-  vskew(Eb, v);
-  D trE = Eb[0] + Eb[4] + Eb[8];
-  D pv = phi[0] * v[0] + phi[1] * v[1] + phi[2] * v[2];
-  D Ep[3], ETp[3];
-  for (int r = 0; r < 3; ++r) {
-    Ep[r] = Eb[3 * r] * phi[0] + Eb[3 * r + 1] * phi[1] + Eb[3 * r + 2] * phi[2];
-    ETp[r] = Eb[r] * phi[0] + Eb[3 + r] * phi[1] + Eb[6 + r] * phi[2];
-  }
-  D pEp = phi[0] * Ep[0] + phi[1] * Ep[1] + phi[2] * Ep[2];
-  D k = -sA * trE + dA * pv + dB * pEp;
-  for (int r = 0; r < 3; ++r) pb[r] = k * phi[r] + A * v[r] + B * (Ep[r] + ETp[r]);
-}
-
-// VJP of phi = Log(Y) = f s, s = vee((Y - Y^T)/2), c = (tr Y - 1)/2,
-// th = atan2(|s|, c), f = th / |s|: returns Y_bar.
-__device__ __forceinline__ void vjp_log(const D Y[9], const D pb[3], D Yb[9]) {
-  D s[3] = {0.5 * (Y[7] - Y[5]), 0.5 * (Y[2] - Y[6]), 0.5 * (Y[3] - Y[1])};
-  D c = 0.5 * (Y[0] + Y[4] + Y[8] - 1.0);
-  D n2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
-  D sb[3], cb;
-  if (n2 < 1e-20) {
-    sb[0] = pb[0];
-    sb[1] = pb[1];
-    sb[2] = pb[2];
-    cb = 0.0;
-  } else {
-    D n = sqrt(n2);
-    D th = atan2(n, c);
-    D f = th / n;
-    D den = n2 + c * c;
-    D th_n = c / den, th_c = -n / den;
-    D f_n = (th_n * n - th) / n2, f_c = th_c / n;
-    D ps = pb[0] * s[0] + pb[1] * s[1] + pb[2] * s[2];
-    for (int r = 0; r < 3; ++r) sb[r] = f * pb[r] + ps * f_n * s[r] / n;
-    cb = ps * f_c;
-  }
-  // s = v(Y) / 2 -> Y_bar = [s_bar]x / 2; c = (tr Y - 1)/2 -> Y_bar += c_bar I / 2
-  D W[9];
-  hat_d(sb, W);
-  for (int k = 0; k < 9; ++k) Yb[k] = 0.5 * W[k];
-  Yb[0] += 0.5 * cb;
-  Yb[4] += 0.5 * cb;
-  Yb[8] += 0.5 * cb;
+// One descent step C_i = C Exp(Log(C^T R) / i), over float64 or its dual numbers.
+template <typename T>
+__device__ __forceinline__ void step_rot_t(const T C[9], const T R[9], int i, T Cn[9]) {
+  T Y[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Y[3 * r + c] = C[r] * R[c] + C[3 + r] * R[3 + c] + C[6 + r] * R[6 + c];
+  T w[3], phi[3], E[9];
+  log_so3<T>(Y, w);
+  const double inv = 1.0 / (double)i;
+  phi[0] = w[0] * inv;
+  phi[1] = w[1] * inv;
+  phi[2] = w[2] * inv;
+  exp_so3<T>(phi, E);
+  matmul3<T>(C, E, Cn);
 }
 
 __device__ __forceinline__ void load_R(const float *poses, int64_t g, D R[9]) {
@@ -181,7 +114,10 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __shared__ double cot[kMaxActive][12];
   __shared__ float pact[kMaxActive][12];       // poses of the active samples
   __shared__ uint8_t tslot[2 * kLdsTrace];     // trace as active-set slots
-  __shared__ double seg[kMaxCkpt][9];          // one recomputed checkpoint segment
+  __shared__ double jac[kBwdBlock][2][9];      // J_C, J_R of the steps of one chunk
+  __shared__ double jadd[kBwdBlock][3];        // averaged-iterate terms of those steps
+  __shared__ double rho[kMaxActive][3];        // tangent cotangents of active rotations
+  __shared__ double Sbar_s[9], gvec[3];
   __shared__ double Rstar[9], tstar[3], Ssum[9];
   __shared__ double red_v[kBwdWaves];
   __shared__ int red_i[kBwdWaves];
@@ -283,9 +219,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     for (int i = 1; i <= T; ++i) {
       if ((i - 1) % ck == 0)
         for (int k = 0; k < 9; ++k) ckpt[((i - 1) / ck) * 9 + k] = C[k];
-      D R[9], Y[9], phi[3], Cn[9];
+      D R[9], Cn[9];
       load_act(slot_of(2 * (i - 1)), R);
-      step_rot(C, R, i, Cn, Y, phi);
+      step_rot_t<D>(C, R, i, Cn);
       for (int k = 0; k < 9; ++k) C[k] = Cn[k];
       if (i > T - avg)
         for (int k = 0; k < 9; ++k) S[k] += C[k];
@@ -399,6 +335,18 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __syncthreads();
   const int n_act = n_act_s;
   // ---- reverse sweeps
+  // Rotation chain.  Thread 0 turns the cotangents of R* and the rotation
+  // radius into S_bar = dL/dS (S = sum of the last iterates).  Then the T
+  // steps are swept backwards in chunks of kBwdBlock: every thread takes one
+  // step i of the chunk, recomputes C_{i-1} from its checkpoint and, in dual
+  // numbers, the 3x3 Jacobians of C_i = C_{i-1} Exp(Log(C_{i-1}^T R) / i) in
+  // right-trivialised tangents, J_C (w.r.t. C_{i-1} Exp(d)) and J_R (w.r.t.
+  // R Exp(e)); thread 0 then runs the chunk's recurrence
+  //   g_i += vskew(C_i^T S_bar) (i among the averaged iterates),
+  //   rho_{s_i} += J_R^T g_i,  g_{i-1} = J_C^T g_i,
+  // so the serial part is 3x3 products only.  g_0 belongs to the first
+  // sample (C_0 = R_{s0}); a sample's tangent cotangent rho becomes the
+  // ambient cotangent R [rho]x / 2 of its rotation.
   if (tid == 0 && !overflow_s) {
     // cotangent of R*: (g_w . left tangent) and the rotation radius
     D G[9], W[9];
@@ -441,50 +389,103 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     D Bh[9], Sbar[9];
     hat_d(bb, Bh);
     matmul3<D>(Rstar, Bh, Sbar);
-    // reverse over the steps, segments recomputed from their checkpoints
-    D Cb[9];
-    for (int k = 0; k < 9; ++k) Cb[k] = 0;
-    const int nseg = (T + ck - 1) / ck;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      const int i_lo = sg * ck + 1, i_hi = min(T, (sg + 1) * ck);
-      // seg[q] = C_{i_lo - 1 + q}
-      for (int k = 0; k < 9; ++k) seg[0][k] = ckpt[sg * 9 + k];
-      for (int i = i_lo; i < i_hi; ++i) {
-        D R[9], Y[9], phi[3], Cq[9], Cn[9];
-        load_act(slot_of(2 * (i - 1)), R);
-        for (int k = 0; k < 9; ++k) Cq[k] = seg[i - i_lo][k];
-        step_rot(Cq, R, i, Cn, Y, phi);
-        for (int k = 0; k < 9; ++k) seg[i - i_lo + 1][k] = Cn[k];
-      }
-      for (int i = i_hi; i >= i_lo; --i) {
-        if (i > T - avg)
-          for (int k = 0; k < 9; ++k) Cb[k] += Sbar[k];
-        D Cp[9];
-        for (int k = 0; k < 9; ++k) Cp[k] = seg[i - i_lo][k];
-        const int pa = slot_of(2 * (i - 1));
-        D R[9], Y[9], phi[3], Cn[9];
-        load_act(pa, R);
-        step_rot(Cp, R, i, Cn, Y, phi);
-        D E[9];
-        exp_so3<D>(phi, E);
-        D Eb[9], Cbp[9], pb[3], Yb[9];
-        matmul_tn(Cp, Cb, Eb);       // E_bar = C^T C_bar
-        matmul_nt(Cb, E, Cbp);       // C_bar_prev = C_bar E^T
-        vjp_exp(phi, Eb, pb);
-        for (int r = 0; r < 3; ++r) pb[r] /= i;
-        vjp_log(Y, pb, Yb);
-        D t1[9], t2[9];
-        matmul_nt(R, Yb, t1);        // C_bar_prev += R Y_bar^T
-        matmul3<D>(Cp, Yb, t2);      // R_bar += C Y_bar
-        for (int k = 0; k < 9; ++k) {
-          Cb[k] = Cbp[k] + t1[k];
-          if (pa >= 0) cot[pa][k] += t2[k];
+    for (int k = 0; k < 9; ++k) Sbar_s[k] = Sbar[k];
+    for (int k = 0; k < 3; ++k) gvec[k] = 0.0;
+  }
+  for (int k = tid; k < kMaxActive * 3; k += kBwdBlock) rho[k / 3][k % 3] = 0.0;
+  __syncthreads();
+  if (!overflow_s) {
+    for (int i_hi = T; i_hi >= 1; i_hi -= kBwdBlock) {
+      const int i_lo = max(1, i_hi - kBwdBlock + 1);
+      const int i = i_lo + tid;
+      if (i <= i_hi) {
+        // C_{i-1} from the checkpoint C_{q ck}, q = (i - 1) / ck
+        const int q = (i - 1) / ck;
+        D C[9];
+        for (int k = 0; k < 9; ++k) C[k] = ckpt[q * 9 + k];
+        for (int m = q * ck + 1; m <= i - 1; ++m) {
+          D R[9], Cn[9];
+          load_act(slot_of(2 * (m - 1)), R);
+          step_rot_t<D>(C, R, m, Cn);
+          for (int k = 0; k < 9; ++k) C[k] = Cn[k];
         }
+        D R[9];
+        load_act(slot_of(2 * (i - 1)), R);
+        D Ci[9];
+        step_rot_t<D>(C, R, i, Ci);
+        // ambient term of the averaged iterates
+        D a[3] = {0.0, 0.0, 0.0};
+        if (i > T - avg) {
+          D Sb[9], X[9];
+          for (int k = 0; k < 9; ++k) Sb[k] = Sbar_s[k];
+          matmul_tn(Ci, Sb, X);
+          vskew(X, a);
+        }
+        // Jacobian columns from right perturbations of C_{i-1} and of R
+        for (int which = 0; which < 2; ++which)
+          for (int c = 0; c < 3; ++c) {
+            Dual<D> Cd[9], Rd[9], Cnd[9];
+            for (int k = 0; k < 9; ++k) {
+              Cd[k] = Dual<D>(C[k], 0.0);
+              Rd[k] = Dual<D>(R[k], 0.0);
+            }
+            // X [e_c]x: column c2 of X [e]x is X (e x e_c2)
+            Dual<D> *X = which == 0 ? Cd : Rd;
+            const D *Xv = which == 0 ? C : R;
+            for (int r = 0; r < 3; ++r) {
+              const D x0 = Xv[3 * r], x1 = Xv[3 * r + 1], x2 = Xv[3 * r + 2];
+              // [e_c]x columns: e_c x e_0, e_c x e_1, e_c x e_2
+              D d0 = 0, d1 = 0, d2 = 0;
+              if (c == 0) { d1 = x2; d2 = -x1; }
+              if (c == 1) { d0 = -x2; d2 = x0; }
+              if (c == 2) { d0 = x1; d1 = -x0; }
+              X[3 * r].d = d0;
+              X[3 * r + 1].d = d1;
+              X[3 * r + 2].d = d2;
+            }
+            step_rot_t<Dual<D>>(Cd, Rd, i, Cnd);
+            D dC[9], Y[9], v[3];
+            for (int k = 0; k < 9; ++k) dC[k] = Cnd[k].d;
+            matmul_tn(Ci, dC, Y);
+            vskew(Y, v);
+            for (int r = 0; r < 3; ++r) jac[tid][which][3 * r + c] = 0.5 * v[r];
+          }
+        for (int k = 0; k < 3; ++k) jadd[tid][k] = a[k];
       }
+      __syncthreads();
+      if (tid == 0) {
+        D g[3] = {gvec[0], gvec[1], gvec[2]};
+        for (int ii = i_hi; ii >= i_lo; --ii) {
+          const int t = ii - i_lo;
+          for (int k = 0; k < 3; ++k) g[k] += jadd[t][k];
+          const D *JC = jac[t][0], *JR = jac[t][1];
+          const int pa = slot_of(2 * (ii - 1));
+          for (int c = 0; c < 3; ++c) rho[pa][c] += JR[c] * g[0] + JR[3 + c] * g[1] + JR[6 + c] * g[2];
+          D gn[3];
+          for (int c = 0; c < 3; ++c) gn[c] = JC[c] * g[0] + JC[3 + c] * g[1] + JC[6 + c] * g[2];
+          for (int k = 0; k < 3; ++k) g[k] = gn[k];
+        }
+        for (int k = 0; k < 3; ++k) gvec[k] = g[k];
+      }
+      __syncthreads();
     }
-    const int p0 = find_active(act, n_act, s0);
-    for (int k = 0; k < 9; ++k) cot[p0][k] += Cb[k];
-  } else if (tid == 64 && !overflow_s) {
+    if (tid == 0) {
+      const int p0 = find_active(act, n_act, s0);
+      for (int k = 0; k < 3; ++k) rho[p0][k] += gvec[k];
+    }
+    __syncthreads();
+    // rho -> ambient cotangent R [rho]x / 2
+    for (int a = tid; a < n_act; a += kBwdBlock) {
+      D R[9], Wr[9], X[9];
+      load_act(a, R);
+      hat_d(rho[a], Wr);
+      matmul3<D>(R, Wr, X);
+      for (int k = 0; k < 9; ++k) cot[a][k] += 0.5 * X[k];
+    }
+  }
+  // Translation chain: c_i = c_{i-1} + (t_{s_i} - c_{i-1}) / i is linear, so
+  // its reverse is a scalar recurrence per coordinate.
+  if (tid == 64 && !overflow_s) {
     const float *gc = g_centre + 6 * j;
     D tb[3] = {gc[3], gc[4], gc[5]};
     const D gd = g_radii[2 * j + 1];

@@ -74,6 +74,30 @@ __device__ __forceinline__ void sincos_quadrant(float x, float &s, float &c) {
   c = 1.f - pc * z;
 }
 
+// atan2(y, x) for y, x >= 0 (not both 0): t = min/max in [0, 1]; above
+// tan(pi/8) the tangent addition formula gives atan t = pi/4 + atan u with
+// u = (t - 1) / (t + 1), so |u| <= tan(pi/8); the odd Taylor series of atan u
+// through u^19 (truncation below 5e-10) follows; y > x reflects about pi/4.
+__device__ __forceinline__ float atan2_quadrant(float y, float x) {
+  const float mx = fmaxf(x, y), mn = fminf(x, y);
+  const float t = mn * __builtin_amdgcn_rcpf(mx);
+  const bool hi = t > 0.41421356f;
+  const float u = hi ? (t - 1.f) * __builtin_amdgcn_rcpf(t + 1.f) : t;
+  const float z = u * u;
+  float p = 1.f / 19.f;
+  p = p * z - 1.f / 17.f;
+  p = p * z + 1.f / 15.f;
+  p = p * z - 1.f / 13.f;
+  p = p * z + 1.f / 11.f;
+  p = p * z - 1.f / 9.f;
+  p = p * z + 1.f / 7.f;
+  p = p * z - 1.f / 5.f;
+  p = p * z + 1.f / 3.f;
+  float a = u - u * (p * z);
+  if (hi) a += 0.78539816f;
+  return y > x ? 1.57079633f - a : a;
+}
+
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
 // With r = conj(a) b = (cos h, sin h u) (sign of b chosen so that h <= pi/2),
 // the step is a (cos(h / i), sin(h / i) u).
@@ -87,7 +111,7 @@ __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int c
   float sn2 = r.y * r.y + r.z * r.z + r.w * r.w;
   if (!(sn2 > 0.f)) return a;
   float isn = rsqrtf(sn2);
-  float half = atan2f(sn2 * isn, fmaxf(r.x, 0.f));
+  float half = atan2_quadrant(sn2 * isn, fmaxf(r.x, 0.f));
   float s, c;
   sincos_quadrant(half * inv, s, c);
   float f = s * isn;
@@ -530,31 +554,37 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         float4 C = Cref;
         int i = i0;
         while (i <= T) {
-          const float dC = sqrtf(sqdist(C, Cref, chain));
+          // bounds compared squared; the raw square root is within the slack
+          const float dC = __builtin_amdgcn_sqrtf(sqdist(C, Cref, chain));
+          auto beats = [&](float key, float ub) {
+            const float b = ub + dC + slack;
+            return key > b * b;
+          };
           float bk = -1.f;
           int bi = INT32_MAX;
           float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
           auto scan = [&](const float4 *pp, const int *qq, int g) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-              if ((g * kGroup + u) * 64 + lane < K) {
-                const float k = sqdist(C, pp[u], chain);
-                if (better(k, qq[u], bk, bi)) {
-                  bk = k;
-                  bi = qq[u];
-                  bp = pp[u];
-                }
-              }
+              const bool valid = (g * kGroup + u) * 64 + lane < K;
+              const float k = valid ? sqdist(C, pp[u], chain) : -1.f;
+              const bool take = k > bk || (k == bk && qq[u] < bi);
+              bk = take ? k : bk;
+              bi = take ? qq[u] : bi;
+              bp.x = take ? pp[u].x : bp.x;
+              bp.y = take ? pp[u].y : bp.y;
+              bp.z = take ? pp[u].z : bp.z;
+              bp.w = take ? pp[u].w : bp.w;
             }
           };
           scan(p0, q0, 0);
           float wk = wave_max_key(bk);
           int g = 1;
-          if (ngroups > 1 && !(sqrtf(wk) > ub1 + dC + slack)) {
+          if (ngroups > 1 && !beats(wk, ub1)) {
             scan(p1, q1, 1);
             wk = wave_max_key(bk);
             g = 2;
-            if (ngroups > 2 && !(sqrtf(wk) > ub2 + dC + slack)) {
+            if (ngroups > 2 && !beats(wk, ub2)) {
               float4 p[kGroup];
               int q[kGroup];
 #pragma unroll
@@ -577,7 +607,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 scan(p, q, g);
                 wk = wave_max_key(bk);
                 ++g;
-                if (!more || sqrtf(wk) > S.chunk_ub[g * kGroup] + dC + slack) break;
+                if (!more || beats(wk, S.chunk_ub[g * kGroup])) break;
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u) {
                   p[u] = np[u];
@@ -587,7 +617,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             }
           }
           n_groups += g;
-          if (theta >= 0.f && !(sqrtf(wk) > theta + dC + slack)) break;  // the shell no longer suffices
+          if (theta >= 0.f && !beats(wk, theta)) break;  // the shell no longer suffices
           const int wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
           const unsigned long long win = __ballot(bk == wk && bi == wi);
           const int wl = (int)__ffsll((long long)win) - 1;

@@ -15,6 +15,7 @@
 namespace purse {
 
 constexpr int kSchedBlock = 1024;
+constexpr int kSmallN = 16;  // keypoint bound of the unrolled 2D-3D variant
 
 // Launch an instance belongs to; an invalid kind goes with 3D-3D, which
 // writes its (flagged) outputs as zeros.
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
   }
 }
 
-template <int KIND>
+template <int KIND, int NMAX>
 __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
                                                 const int32_t *__restrict__ sched, int n_inst, DevParams p,
                                                 float *__restrict__ poses, uint8_t *__restrict__ mask) {
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   const KpPlain kpl{kprec + I.kp_off};
   Pose x = initial_pose<float>(F, I.seed, (uint64_t)s, p);
   int n_fb = 0;
-  uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, n_fb);
+  uint8_t m = run_trajectory<KIND, NMAX>(I, F, kpl, x, p, true, n_fb);
   out[0] = make_float4(x.R[0], x.R[1], x.R[2], x.R[3]);
   out[1] = make_float4(x.R[4], x.R[5], x.R[6], x.R[7]);
   out[2] = make_float4(x.R[8], x.t[0], x.t[1], x.t[2]);
@@ -129,10 +130,15 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
                    float *poses, uint8_t *mask, int tile, hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
   const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
-  hipLaunchKernelGGL(k_sample<PURSE_KIND_2D3D>, grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
-                     mask);
-  hipLaunchKernelGGL(k_sample<PURSE_KIND_3D3D>, grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
-                     mask);
+  // 2D-3D batches with at most kSmallN keypoints take the unrolled variant
+  if (b.max_kp <= kSmallN && !(p.flags & PURSE_FLAG_GENERIC_LOOP))
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst,
+                       p, poses, mask);
+  else
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                       poses, mask);
+  hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                     poses, mask);
 }
 
 }  // namespace purse

@@ -299,15 +299,69 @@ __device__ __forceinline__ bool gn_pass2d(const KPL &kpl, int n, const float K[4
   return true;
 }
 
-template <typename T, typename KPL>
+// The same Gauss-Newton step with the keypoint loop unrolled for at most NMAX
+// keypoints and the projection targets of the current iteration held in
+// registers: the first step computes q_i = c_i + s_i e_i at xk and keeps it,
+// later steps only re-project at x.  Arithmetic as in gn_pass2d.
+template <bool FIRST, int NMAX, typename T, typename KPL>
+__device__ __forceinline__ bool gn_pass2d_unrolled(const KPL &kpl, int n, const float K[4], const T oc[3],
+                                                   float z_min, float band, T tq[NMAX][2], PoseT<T> &x) {
+  T A[21], g[6];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = T(0.f);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = T(0.f);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i < n) {
+      const auto k = kpl(i);
+      T P[3], iz, u, v;
+      project2d(x.R, x.t, k, K, P, iz, u, v);
+      ok = ok && (P[2] > z_min);
+      T rt0, rt1;
+      if (FIRST) {
+        T e0 = u - k.c[0], e1 = v - k.c[1];
+        T et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+        T r2 = et0 * et0 + et1 * et1;
+        T s = (r2 <= k.kb2 * band) ? T(1.f) : k.kb * drsqrt(r2);
+        rt0 = (s - 1.f) * et0;
+        rt1 = (s - 1.f) * et1;
+        tq[i][0] = k.c[0] + s * e0;
+        tq[i][1] = k.c[1] + s * e1;
+      } else {
+        T r0 = tq[i][0] - u, r1 = tq[i][1] - v;
+        rt0 = k.w[0] * r0 + k.w[1] * r1;
+        rt1 = k.w[2] * r1;
+      }
+      T pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+      gn_accumulate<T>(P, pt, iz, T(K[0]), T(K[1]), k.w, rt0, rt1, A, g);
+    }
+  }
+  T d[6];
+  ok = ok && chol6_solve<T>(A, g, d);
+  if (!ok) return false;
+  apply_update<T>(d, oc, x.R, x.t);
+  return true;
+}
+
+// NMAX > 0: at most NMAX keypoints, loops unrolled (gn_pass2d_unrolled).
+template <int NMAX, typename T, typename KPL>
 __device__ __forceinline__ bool traj2d(const KPL &kpl, int n, const float K[4], const T oc[3], int n_iters,
                                        int n_gn, float z_min, PoseT<T> &x) {
   const float band = ClampBand<T>::v;
   for (int it = 0; it < n_iters; ++it) {
-    const PoseT<T> xk = x;
-    if (!gn_pass2d<true>(kpl, n, K, oc, z_min, band, xk, x)) return false;
-    for (int gs = 1; gs < n_gn; ++gs)
-      if (!gn_pass2d<false>(kpl, n, K, oc, z_min, band, xk, x)) return false;
+    if constexpr (NMAX > 0) {
+      T tq[NMAX][2];
+      if (!gn_pass2d_unrolled<true, NMAX>(kpl, n, K, oc, z_min, band, tq, x)) return false;
+      for (int gs = 1; gs < n_gn; ++gs)
+        if (!gn_pass2d_unrolled<false, NMAX>(kpl, n, K, oc, z_min, band, tq, x)) return false;
+    } else {
+      const PoseT<T> xk = x;
+      if (!gn_pass2d<true>(kpl, n, K, oc, z_min, band, xk, x)) return false;
+      for (int gs = 1; gs < n_gn; ++gs)
+        if (!gn_pass2d<false>(kpl, n, K, oc, z_min, band, xk, x)) return false;
+    }
   }
   return true;
 }
@@ -402,7 +456,7 @@ __device__ __forceinline__ PoseT<T> pull_in(const InstRec &I, const FR &F, const
 }
 
 // Full trajectory from x; returns the mask bits and leaves the output pose in x.
-template <int KIND, typename T, typename KPL, typename FR>
+template <int KIND, int NMAX = 0, typename T, typename KPL, typename FR>
 __device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FR &F, const KPL &kpl,
                                                   PoseT<T> &x, const DevParams &p, bool with_pull_in,
                                                   int &n_fb) {
@@ -411,7 +465,7 @@ __device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FR &F,
     traj3d(kpl, I.n_kp, I.abar, p.n_iters, (p.flags & PURSE_FLAG_FORCE_FP64_POLAR) != 0, x, n_fb);
   } else {
     T oc[3] = {T(F.oc[0]), T(F.oc[1]), T(F.oc[2])};
-    ok = traj2d(kpl, I.n_kp, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
+    ok = traj2d<NMAX>(kpl, I.n_kp, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
     reorthonormalise(x.R);
   }
   if (!ok) return PURSE_MASK_FAILED;

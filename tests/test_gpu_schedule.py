@@ -64,6 +64,23 @@ def test_every_schedule_writes_every_sample_identically():
                 assert torch.equal(poses, ref[0]) and torch.equal(mask, ref[1]) and torch.equal(status, ref[2])
 
 
+def test_unrolled_and_generic_keypoint_loops_agree():
+    """2D-3D batches of at most 16 keypoints run an unrolled keypoint loop
+    that keeps the iteration's projection targets in registers; the general
+    loop recomputes them.  Both compute the same values."""
+    import paper_2403_09990_amd as P
+    _log("case: unrolled vs generic loop")
+    rng = np.random.default_rng(8)
+    b = W.Batch([W.make_2d3d(rng, n, 2.0, (5.0, 20.0), m) for n, m in ((6, 300), (12, 1000), (16, 257))])
+    db = P.DeviceBatch(b)
+    a = _run(P, db, P.purse_default_params(n_iters=40))
+    g = _run(P, db, P.purse_default_params(n_iters=40, flags=P.PURSE_FLAG_GENERIC_LOOP))
+    assert torch.equal(a[1], g[1]) and torch.equal(a[2], g[2])
+    diff = (a[0] - g[0]).abs().max().item()
+    _log("max pose difference", diff)
+    assert diff <= 1e-5
+
+
 def test_autotune_picks_and_caches(tmp_path):
     import paper_2403_09990_amd as P
     from paper_2403_09990_amd import autotune
@@ -76,7 +93,7 @@ def test_autotune_picks_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     best, rep = autotune.tune(db, gp, ws, out["poses"], out["mask"], out["inst_status"], cache=cache, reps=1)
     assert not rep["cached"] and best.tile in autotune.TILES
-    assert len(rep["candidates_ms"]) == len(autotune.TILES) * len(autotune.ORDERS)
+    assert len(rep["candidates_ms"]) >= len(autotune.TILES) * len(autotune.ORDERS)
     best2, rep2 = autotune.tune(db, gp, ws, out["poses"], out["mask"], out["inst_status"], cache=cache)
     assert rep2["cached"] and best2.tile == best.tile and best2.flags == best.flags
     # the tuned schedule gives the default schedule's results
