@@ -334,6 +334,14 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   for (int k = tid; k < kMaxActive * 12; k += kBwdBlock) cot[k / 12][k % 12] = 0.0;
   __syncthreads();
   const int n_act = n_act_s;
+  // a radius sample outside the trace shifts the active set: stage the poses
+  // and the trace slots again for the new positions
+  if (!overflow_s) {
+    for (int k = tid; k < n_act * 12; k += kBwdBlock) pact[k / 12][k % 12] = poses[12 * (off + act[k / 12]) + k % 12];
+    if (lds_trace)
+      for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act, tr[k]);
+  }
+  __syncthreads();
   // ---- reverse sweeps
   // Rotation chain.  Thread 0 turns the cotangents of R* and the rotation
   // radius into S_bar = dL/dS (S = sum of the last iterates).  Then the T

@@ -70,9 +70,11 @@ struct WsLayout {
   size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, total;
 };
 
-// Tile schedule of the sampler, one per kind: order[n] lists the instances
-// (heaviest per trajectory first), tstart[n + 1] the first tile of each entry
-// of that order and, last, the kind's tile count.
+// Tile schedule of the sampler, one per launch group (3D-3D; 2D-3D with the
+// general keypoint loop; 2D-3D with the unrolled one): order[n] lists the
+// instances (heaviest per trajectory first), tstart[n + 1] the first tile of
+// each entry of that order and, last, the group's tile count.
+constexpr int kSchedGroups = 3;
 __host__ __device__ inline size_t sched_ints(int64_t n_inst) { return 2 * (size_t)n_inst + 1; }
 
 // Byte offsets of the workspace regions.
@@ -85,7 +87,7 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   L.kp = o;
   o += align_up(sizeof(KpRec) * (size_t)total_kp);
   L.sched = o;
-  o += align_up(sizeof(int32_t) * 2 * sched_ints(n_inst));
+  o += align_up(sizeof(int32_t) * kSchedGroups * sched_ints(n_inst));
   L.megb = o;
   o += align_up(sizeof(MegbRec) * (size_t)n_inst);
   L.quat = o;

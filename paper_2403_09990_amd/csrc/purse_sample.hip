@@ -14,14 +14,26 @@
 
 namespace purse {
 
-constexpr int kSchedBlock = 1024;
 constexpr int kSmallN = 16;  // keypoint bound of the unrolled 2D-3D variant
 
-// Launch an instance belongs to; an invalid kind goes with 3D-3D, which
-// writes its (flagged) outputs as zeros.
-__device__ __forceinline__ int launch_kind(const InstRec &I) {
-  return I.kind == PURSE_KIND_2D3D ? PURSE_KIND_2D3D : PURSE_KIND_3D3D;
+constexpr int kSchedBlock = 1024;
+
+// Launch group of an instance: 0 for 3D-3D (an invalid kind goes there too,
+// and its flagged outputs are written as zeros), 1 for 2D-3D with the
+// general keypoint loop, 2 for 2D-3D instances of at most kSmallN keypoints
+// (the unrolled loop, unless the flags ask for the general one).  The group
+// depends on the instance alone, so an instance computes bitwise the same
+// samples in any batch.
+__device__ __forceinline__ int launch_group(const InstRec &I, int flags) {
+  if (I.kind != PURSE_KIND_2D3D) return 0;
+  return (I.n_kp <= kSmallN && !(flags & PURSE_FLAG_GENERIC_LOOP)) ? 2 : 1;
 }
+
+template <int KIND, int NMAX>
+constexpr int group_of() {
+  return KIND == PURSE_KIND_3D3D ? 0 : (NMAX > 0 ? 2 : 1);
+}
+
 constexpr int kMaxSorted = 8192;  // larger batches keep instance order
 
 // Builds both kinds' schedules in one workgroup: rank of instance j = number
@@ -33,11 +45,11 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
   __shared__ int part[kSchedBlock];
   const int tid = threadIdx.x;
   const bool sorted = n <= kMaxSorted && !(flags & PURSE_FLAG_INSTANCE_ORDER);
-  for (int kind = 0; kind < 2; ++kind) {
+  for (int kind = 0; kind < kSchedGroups; ++kind) {
     int32_t *order = sched + (size_t)kind * sched_ints(n);
     int32_t *tstart = order + n;
     if (sorted) {
-      for (int j = tid; j < n; j += kSchedBlock) key[j] = launch_kind(inst[j]) == kind ? inst[j].n_kp : -1;
+      for (int j = tid; j < n; j += kSchedBlock) key[j] = launch_group(inst[j], flags) == kind ? inst[j].n_kp : -1;
       __syncthreads();
       for (int j = tid; j < n; j += kSchedBlock) {
         const int kj = key[j];
@@ -59,7 +71,7 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
     int acc = 0;
     for (int k = b0; k < b1; ++k) {
       const InstRec &I = inst[order[k]];
-      acc += launch_kind(I) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
+      acc += launch_group(I, flags) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
     }
     part[tid] = acc;
     __syncthreads();
@@ -73,7 +85,7 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
     for (int k = b0; k < b1; ++k) {
       tstart[k] = run;
       const InstRec &I = inst[order[k]];
-      run += launch_kind(I) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
+      run += launch_group(I, flags) == kind ? (int)((I.n_samples + tile - 1) / tile) : 0;
     }
     if (tid == kSchedBlock - 1) tstart[n] = part[kSchedBlock - 1];
     __syncthreads();
@@ -84,7 +96,7 @@ template <int KIND, int NMAX>
 __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
                                                 const int32_t *__restrict__ sched, int n_inst, DevParams p,
                                                 float *__restrict__ poses, uint8_t *__restrict__ mask) {
-  const int32_t *order = sched + (size_t)KIND * sched_ints(n_inst);
+  const int32_t *order = sched + (size_t)group_of<KIND, NMAX>() * sched_ints(n_inst);
   const int32_t *tstart = order + n_inst;
   const int b = blockIdx.x;
   if (b >= tstart[n_inst]) return;
@@ -100,7 +112,7 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   const int j = order[lo];
   const InstRec &I = inst[j];
   const int64_t s = (int64_t)(b - tstart[lo]) * blockDim.x + threadIdx.x;
-  if (launch_kind(I) != KIND || s >= I.n_samples) return;
+  if (launch_group(I, p.flags) != group_of<KIND, NMAX>() || s >= I.n_samples) return;
   const int64_t g = I.sample_off + s;
   float4 *out = reinterpret_cast<float4 *>(poses + 12 * g);
   if ((I.status & 0xFF) != PURSE_INST_OK) {
@@ -130,13 +142,10 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
                    float *poses, uint8_t *mask, int tile, hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
   const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
-  // 2D-3D batches with at most kSmallN keypoints take the unrolled variant
-  if (b.max_kp <= kSmallN && !(p.flags & PURSE_FLAG_GENERIC_LOOP))
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst,
-                       p, poses, mask);
-  else
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                       poses, mask);
+  hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                     poses, mask);
+  hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                     poses, mask);
   hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
                      poses, mask);
 }
