@@ -41,13 +41,13 @@ __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
 }
 
 // Squared distance: ||R_a - R_b||_F^2 = 2 |a - b|^2 |a + b|^2 for unit
-// quaternions a, b, where |a + b|^2 = 4 - |a - b|^2 (chain 0); |a - b|^2 for
-// translations (chain 1).
+// quaternions a, b (chain 0; both chords are formed directly, so the key stays
+// accurate whichever sign b carries); |a - b|^2 for translations (chain 1).
 __device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
   if (chain == 0) {
     float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
-    float x = m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3;
-    return 2.f * x * (4.f - x);
+    float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
+    return 2.f * (m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3) * (p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3);
   }
   float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
   return d0 * d0 + d1 * d1 + d2 * d2;
@@ -99,25 +99,32 @@ __device__ __forceinline__ float atan2_quadrant(float y, float x) {
 }
 
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
-// With r = conj(a) b = (cos h, sin h u) (sign of b chosen so that h <= pi/2),
-// the step is a (cos(h / i), sin(h / i) u).
+// For unit quaternions a (centre) and b (sample, sign chosen so that a.b >= 0)
+// at quaternion angle h, the step is the spherical interpolation at 1/i:
+//   sin((1 - 1/i) h) / sin h a + sin(h / i) / sin h b.
+// h comes from the chords, sin(h/2) = |a - b'| / 2 and cos(h/2) = |a + b'| / 2,
+// both formed directly, which stay accurate for small angles.
 __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
   const float inv = 1.f / (float)i;
   if (chain == 1) return make_float4(a.x + (b.x - a.x) * inv, a.y + (b.y - a.y) * inv, a.z + (b.z - a.z) * inv, 1.f);
-  float dt = a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
-  if (dt < 0.f) b = make_float4(-b.x, -b.y, -b.z, -b.w);
-  float4 ac = make_float4(a.x, -a.y, -a.z, -a.w);
-  float4 r = quat_mul(ac, b);
-  float sn2 = r.y * r.y + r.z * r.z + r.w * r.w;
-  if (!(sn2 > 0.f)) return a;
-  float isn = rsqrtf(sn2);
-  float half = atan2_quadrant(sn2 * isn, fmaxf(r.x, 0.f));
-  float s, c;
-  sincos_quadrant(half * inv, s, c);
-  float f = s * isn;
-  float4 e = make_float4(c, f * r.y, f * r.z, f * r.w);
-  float4 q = quat_mul(a, e);
-  float nn = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
+  const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
+  const float x = m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3;  // |a - b|^2
+  const float y = p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3;  // |a + b|^2
+  const bool flip = x > y;                                // a . b < 0: use b' = -b
+  const float xs = flip ? y : x;                          // |a - b'|^2
+  const float ys = flip ? x : y;                          // |a + b'|^2
+  if (!(xs > 0.f)) return a;
+  const float half = atan2_quadrant(__builtin_amdgcn_sqrtf(xs), __builtin_amdgcn_sqrtf(ys));  // h / 2
+  float st, ct;
+  sincos_quadrant(2.f * half * inv, st, ct);              // sin, cos of h / i
+  const float sh = 0.5f * __builtin_amdgcn_sqrtf(xs * ys);  // sin h
+  const float chh = 1.f - 0.5f * xs;                      // cos h
+  const float cb = st * __builtin_amdgcn_rcpf(sh);
+  const float ca = ct - chh * cb;
+  const float cbs = flip ? -cb : cb;
+  float4 q = make_float4(ca * a.x + cbs * b.x, ca * a.y + cbs * b.y, ca * a.z + cbs * b.z, ca * a.w + cbs * b.w);
+  const float nn = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
   return make_float4(q.x * nn, q.y * nn, q.z * nn, q.w * nn);
 }
 
@@ -566,9 +573,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           auto scan = [&](const float4 *pp, const int *qq, int g) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
+              // selects only (no control flow): every lane evaluates every entry
               const bool valid = (g * kGroup + u) * 64 + lane < K;
-              const float k = valid ? sqdist(C, pp[u], chain) : -1.f;
-              const bool take = k > bk || (k == bk && qq[u] < bi);
+              const float kk = sqdist(C, pp[u], chain);
+              const float k = valid ? kk : -1.f;
+              const bool take = (k > bk) | ((k == bk) & (qq[u] < bi));
               bk = take ? k : bk;
               bi = take ? qq[u] : bi;
               bp.x = take ? pp[u].x : bp.x;
@@ -618,9 +627,15 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           }
           n_groups += g;
           if (theta >= 0.f && !beats(wk, theta)) break;  // the shell no longer suffices
-          const int wi = wave_min_i32(bk == wk ? bi : INT32_MAX);
-          const unsigned long long win = __ballot(bk == wk && bi == wi);
+          // winner: the one lane holding the maximum key, else (a tie) the
+          // lowest sample id among the lanes that hold it
+          unsigned long long win = __ballot(bk == wk);
+          if (__popcll(win) > 1) {
+            const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
+            win = __ballot(bk == wk && bi == wmin);
+          }
           const int wl = (int)__ffsll((long long)win) - 1;
+          const int wi = __builtin_amdgcn_readlane(bi, wl);
           const float4 pt = make_float4(readlane_f(bp.x, wl), readlane_f(bp.y, wl), readlane_f(bp.z, wl),
                                         readlane_f(bp.w, wl));
           C = geodesic_step(C, pt, i, chain);
