@@ -79,6 +79,10 @@ typedef int32_t purse_status;
                                          changes the schedule, for tuning) */
 #define PURSE_FLAG_GENERIC_LOOP 16    /* purse_sample: use the general keypoint loop even when every
                                          instance has at most 16 keypoints (for tuning) */
+#define PURSE_FLAG_PAIR_LANES 32      /* purse_sample: 2D-3D instances of at most 16 keypoints run each
+                                         trajectory on two lanes (twice the wavefronts, for batches too
+                                         small to fill the GPU); results agree with one lane per
+                                         trajectory to float32 rounding */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints

@@ -3,8 +3,10 @@
 The sampler's results do not depend on the schedule: only the workgroup size
 (params.tile: 64, 128 or 256 samples), the tile order (heaviest instances
 first, or instance order with PURSE_FLAG_INSTANCE_ORDER) and, for 2D-3D
-batches of at most 16 keypoints, the keypoint loop (unrolled, or the general
-one with PURSE_FLAG_GENERIC_LOOP) change its speed.
+instances of at most 16 keypoints, the keypoint loop (unrolled; the general
+one with PURSE_FLAG_GENERIC_LOOP; two lanes per trajectory with
+PURSE_FLAG_PAIR_LANES) change its speed; the last two change float32 rounding
+only.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -15,13 +17,14 @@ import json
 import os
 from typing import Optional
 
-from . import PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, purse_default_params, purse_sample
+from . import (PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, purse_default_params,
+               purse_sample)
 
 TILES = (64, 128, 256)
 ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
-LOOPS = (0, PURSE_FLAG_GENERIC_LOOP)
+LOOPS = (0, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_PAIR_LANES)
 SMALL_N = 16
-_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP
+_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES
 
 
 def default_cache_path() -> str:
@@ -53,11 +56,15 @@ def _load(path):
 
 
 def _store(path, table):
-    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    tmp = path + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(table, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    """Writes the cache; an unwritable location only costs the caching."""
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
 
 
 def _with(params, tile, flags):
@@ -70,8 +77,9 @@ def _with(params, tile, flags):
 
 
 def _name(tile, flags):
-    return "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first",
-                         "generic" if flags & PURSE_FLAG_GENERIC_LOOP else "unrolled")
+    loop = ("generic" if flags & PURSE_FLAG_GENERIC_LOOP else
+            "pair-lanes" if flags & PURSE_FLAG_PAIR_LANES else "unrolled")
+    return "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first", loop)
 
 
 def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
@@ -84,8 +92,8 @@ def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
     path = cache or default_cache_path()
     key = signature(db, params)
     table = _load(path)
-    if not force and key in table:
-        rec = table[key]
+    rec = table.get(key)
+    if not force and isinstance(rec, dict) and "tile" in rec and "flags" in rec:
         return _with(params, rec["tile"], rec["flags"]), dict(rec, cached=True)
     if stream is None:
         stream = torch.cuda.current_stream()

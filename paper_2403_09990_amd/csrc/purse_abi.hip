@@ -174,7 +174,7 @@ purse_status purse_sample(const purse_batch *b, const purse_params *p, float *po
     if ((s = hip_check(hipGetLastError(), "prologue launch"))) return s;
   }
   const int tile = p->tile ? p->tile : 256;
-  if (purse::sample_grid(b->total_samples, b->n_inst, tile) > INT32_MAX)
+  if (purse::sample_grid(b->total_samples, b->n_inst, tile / 2) > INT32_MAX)
     return fail(PURSE_E_BAD_ARG, "too many sample tiles for one launch");
   purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, st);
   return hip_check(hipGetLastError(), "sampler launch");

@@ -100,12 +100,14 @@ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T c[3]) {
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// Exp of so(3): (cos th) I + (sin th / th) [w]x + ((1 - cos th)/th^2) w w^T,
-// with 1 - cos th written as 2 sin^2(th/2) so small angles keep full precision.
+// Coefficients of Exp on so(3): A = sin th / th, B = (1 - cos th) / th^2,
+// C = cos th, from th^2.  In general 1 - cos th is written as 2 sin^2(th/2) so
+// small angles keep full precision.  In float32 (and its dual numbers), angles
+// up to pi/2 use the Taylor series of A, B and C in th^2 instead (through
+// th^12, th^12 and th^14: truncation below 5e-10 there), which needs no square
+// root or trigonometric call.
 template <typename T>
-__device__ __forceinline__ void exp_so3(const T w[3], T R[9]) {
-  T th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-  T A, B, C;
+__device__ __forceinline__ void exp_coeffs(T th2, T &A, T &B, T &C) {
   if (th2 < T(1e-12)) {
     A = T(1) - th2 / T(6);
     B = T(0.5) - th2 / T(24);
@@ -118,6 +120,66 @@ __device__ __forceinline__ void exp_so3(const T w[3], T R[9]) {
     B = T(2) * s * s * ith * ith;
     C = T(1) - T(2) * s * s;
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void exp_coeffs_series(T z, T &A, T &B, T &C) {
+  A = T(1.f / 6227020800.f);
+  A = A * z - 1.f / 39916800.f;
+  A = A * z + 1.f / 362880.f;
+  A = A * z - 1.f / 5040.f;
+  A = A * z + 1.f / 120.f;
+  A = A * z - 1.f / 6.f;
+  A = A * z + 1.f;
+  B = T(1.f / 87178291200.f);
+  B = B * z - 1.f / 479001600.f;
+  B = B * z + 1.f / 3628800.f;
+  B = B * z - 1.f / 40320.f;
+  B = B * z + 1.f / 720.f;
+  B = B * z - 1.f / 24.f;
+  B = B * z + 0.5f;
+  C = T(-1.f / 87178291200.f);
+  C = C * z + 1.f / 479001600.f;
+  C = C * z - 1.f / 3628800.f;
+  C = C * z + 1.f / 40320.f;
+  C = C * z - 1.f / 720.f;
+  C = C * z + 1.f / 24.f;
+  C = C * z - 0.5f;
+  C = C * z + 1.f;
+}
+
+constexpr float kExpSeriesMax = 2.4674011f;  // (pi/2)^2
+
+__device__ __forceinline__ void exp_coeffs(float th2, float &A, float &B, float &C) {
+  if (th2 <= kExpSeriesMax) {
+    exp_coeffs_series<float>(th2, A, B, C);
+  } else {
+    float ith = rsqrtf(th2), s, c;
+    sincosf(0.5f * th2 * ith, &s, &c);
+    A = 2.f * s * c * ith;
+    B = 2.f * s * s * ith * ith;
+    C = 1.f - 2.f * s * s;
+  }
+}
+
+__device__ __forceinline__ void exp_coeffs(Dual<float> th2, Dual<float> &A, Dual<float> &B, Dual<float> &C) {
+  if (th2.v <= kExpSeriesMax) {
+    exp_coeffs_series<Dual<float>>(th2, A, B, C);
+  } else {
+    Dual<float> ith = drsqrt(th2), s, c;
+    dsincos(Dual<float>(0.5f) * th2 * ith, &s, &c);
+    A = Dual<float>(2.f) * s * c * ith;
+    B = Dual<float>(2.f) * s * s * ith * ith;
+    C = Dual<float>(1.f) - Dual<float>(2.f) * s * s;
+  }
+}
+
+// Exp of so(3): (cos th) I + (sin th / th) [w]x + ((1 - cos th)/th^2) w w^T.
+template <typename T>
+__device__ __forceinline__ void exp_so3(const T w[3], T R[9]) {
+  T th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  T A, B, C;
+  exp_coeffs(th2, A, B, C);
   R[0] = C + B * w[0] * w[0];
   R[4] = C + B * w[1] * w[1];
   R[8] = C + B * w[2] * w[2];

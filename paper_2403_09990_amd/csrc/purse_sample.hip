@@ -39,13 +39,15 @@ constexpr int kMaxSorted = 8192;  // larger batches keep instance order
 // Builds both kinds' schedules in one workgroup: rank of instance j = number
 // of instances of the kind that come before it (larger keypoint count, or
 // equal count and lower index), then a prefix sum of tile counts in rank order.
-__global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restrict__ inst, int n, int tile,
+__global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restrict__ inst, int n, int tile_lanes,
                                                           int flags, int32_t *__restrict__ sched) {
   __shared__ int key[kMaxSorted];
   __shared__ int part[kSchedBlock];
   const int tid = threadIdx.x;
   const bool sorted = n <= kMaxSorted && !(flags & PURSE_FLAG_INSTANCE_ORDER);
   for (int kind = 0; kind < kSchedGroups; ++kind) {
+    // samples per tile: one per lane, or one per lane pair in pair mode
+    const int tile = (kind == 2 && (flags & PURSE_FLAG_PAIR_LANES)) ? tile_lanes / 2 : tile_lanes;
     int32_t *order = sched + (size_t)kind * sched_ints(n);
     int32_t *tstart = order + n;
     if (sorted) {
@@ -133,6 +135,58 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   mask[g] = m;
 }
 
+// Pair mode of the unrolled 2D-3D group (PURSE_FLAG_PAIR_LANES): a workgroup
+// of blockDim lanes runs blockDim / 2 trajectories, two lanes each; the
+// instance's keypoint records are staged in LDS first.
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_sample2d_pair(const InstRec *__restrict__ inst,
+                                                       const KpRec *__restrict__ kprec,
+                                                       const int32_t *__restrict__ sched, int n_inst, DevParams p,
+                                                       float *__restrict__ poses, uint8_t *__restrict__ mask) {
+  __shared__ KpRec kp_s[NMAX];
+  const int32_t *order = sched + (size_t)2 * sched_ints(n_inst);
+  const int32_t *tstart = order + n_inst;
+  const int b = blockIdx.x;
+  if (b >= tstart[n_inst]) return;
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tstart[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int j = order[lo];
+  const InstRec &I = inst[j];
+  if (launch_group(I, p.flags) != 2) return;  // (whole workgroup)
+  const bool valid = (I.status & 0xFF) == PURSE_INST_OK;
+  if (valid && (int)threadIdx.x < I.n_kp) kp_s[threadIdx.x] = kprec[I.kp_off + threadIdx.x];
+  __syncthreads();
+  const int64_t s = (int64_t)(b - tstart[lo]) * (blockDim.x / 2) + (threadIdx.x >> 1);
+  const int q = threadIdx.x & 1;
+  if (s >= I.n_samples) return;  // both lanes of a pair leave together
+  const int64_t g = I.sample_off + s;
+  float4 *out = reinterpret_cast<float4 *>(poses + 12 * g);
+  if (!valid) {
+    if (q == 0) {
+      out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+      mask[g] = 0;
+    }
+    return;
+  }
+  const FrameRef F = frame_ref(I);
+  Pose x = initial_pose<float>(F, I.seed, (uint64_t)s, p);
+  const uint8_t m = run_trajectory_pair<NMAX>(I, F, kp_s, q, x, p);
+  if (q == 0) {
+    out[0] = make_float4(x.R[0], x.R[1], x.R[2], x.R[3]);
+    out[1] = make_float4(x.R[4], x.R[5], x.R[6], x.R[7]);
+    out[2] = make_float4(x.R[8], x.t[0], x.t[1], x.t[2]);
+    mask[g] = m;
+  }
+}
+
 int64_t sample_grid(int64_t total_samples, int n_inst, int tile) {
   // sum_j ceil(M_j / tile) <= total / tile + n_inst
   return total_samples / tile + n_inst;
@@ -142,8 +196,14 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
                    float *poses, uint8_t *mask, int tile, hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
   const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
-  hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                     poses, mask);
+  if (p.flags & PURSE_FLAG_PAIR_LANES) {
+    const dim3 grid2((unsigned)sample_grid(b.total_samples, b.n_inst, tile / 2));
+    hipLaunchKernelGGL((k_sample2d_pair<kSmallN>), grid2, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
+                       mask);
+  } else {
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst,
+                       p, poses, mask);
+  }
   hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
                      poses, mask);
   hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,

@@ -477,4 +477,150 @@ __device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FR &F,
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Pair mode (2D-3D, at most NMAX keypoints): the two lanes 2k and 2k + 1 of a
+// wavefront run one trajectory together.  Lane parity q takes the keypoints
+// i = q, q + 2, ...; the normal equations (and the feasibility and depth
+// tests) are combined across the pair by a DPP quad permutation, so both lanes
+// then hold the same sums (addition commutes) and compute the same step.  This
+// halves the keypoint work per lane and doubles the wavefronts of a batch.
+// Keypoint records come from LDS, where each lane reads its own.
+__device__ __forceinline__ float pair_sum(float x) {
+  return x + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ bool pair_and(bool b) {
+  const int v = b ? 1 : 0;
+  return (v & __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false)) != 0;
+}
+
+template <bool FIRST, int NMAX>
+__device__ __forceinline__ bool gn_pass2d_pair(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
+                                               float z_min, float tq[NMAX / 2][2], Pose &x) {
+  float A[21], g[6];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = 0.f;
+  bool ok = true;
+#pragma unroll
+  for (int ii = 0; ii < NMAX / 2; ++ii) {
+    const int i = 2 * ii + q;
+    if (i < n) {
+      const KpRec k = kp[i];
+      float P[3], iz, u, v;
+      project2d(x.R, x.t, k, K, P, iz, u, v);
+      ok = ok && (P[2] > z_min);
+      float rt0, rt1;
+      if (FIRST) {
+        float e0 = u - k.c[0], e1 = v - k.c[1];
+        float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+        float r2 = et0 * et0 + et1 * et1;
+        float sc = (r2 <= k.kb2) ? 1.f : k.kb * drsqrt(r2);
+        rt0 = (sc - 1.f) * et0;
+        rt1 = (sc - 1.f) * et1;
+        tq[ii][0] = k.c[0] + sc * e0;
+        tq[ii][1] = k.c[1] + sc * e1;
+      } else {
+        float r0 = tq[ii][0] - u, r1 = tq[ii][1] - v;
+        rt0 = k.w[0] * r0 + k.w[1] * r1;
+        rt1 = k.w[2] * r1;
+      }
+      float pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+      gn_accumulate<float>(P, pt, iz, K[0], K[1], k.w, rt0, rt1, A, g);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = pair_sum(A[k]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = pair_sum(g[k]);
+  ok = pair_and(ok);
+  float d[6];
+  ok = ok && chol6_solve<float>(A, g, d);
+  if (!ok) return false;
+  apply_update<float>(d, oc, x.R, x.t);
+  return true;
+}
+
+template <int NMAX>
+__device__ __forceinline__ bool traj2d_pair(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
+                                            int n_iters, int n_gn, float z_min, Pose &x) {
+  for (int it = 0; it < n_iters; ++it) {
+    float tq[NMAX / 2][2];
+    if (!gn_pass2d_pair<true, NMAX>(kp, n, q, K, oc, z_min, tq, x)) return false;
+    for (int gs = 1; gs < n_gn; ++gs)
+      if (!gn_pass2d_pair<false, NMAX>(kp, n, q, K, oc, z_min, tq, x)) return false;
+  }
+  return true;
+}
+
+template <int NMAX>
+__device__ __forceinline__ bool feasible2d_pair(const KpRec *kp, int n, int q, const float K[4], const Pose &x,
+                                                float z_min) {
+  bool ok = true;
+#pragma unroll
+  for (int ii = 0; ii < NMAX / 2; ++ii) {
+    const int i = 2 * ii + q;
+    if (i < n) {
+      const KpRec k = kp[i];
+      float P[3], iz, u, v;
+      project2d(x.R, x.t, k, K, P, iz, u, v);
+      float e0 = u - k.c[0], e1 = v - k.c[1];
+      float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      ok = ok && (P[2] > z_min) && (sqrtf(et0 * et0 + et1 * et1) <= k.bt);
+    }
+  }
+  return pair_and(ok);
+}
+
+// Pair-mode trajectory: iterations, feasibility test, bisection pull-in.
+template <int NMAX>
+__device__ __forceinline__ uint8_t run_trajectory_pair(const InstRec &I, const FrameRef &F, const KpRec *kp, int q,
+                                                       Pose &x, const DevParams &p) {
+  const float oc[3] = {F.oc[0], F.oc[1], F.oc[2]};
+  const bool ok = traj2d_pair<NMAX>(kp, I.n_kp, q, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
+  reorthonormalise(x.R);
+  if (!ok) return PURSE_MASK_FAILED;
+  if (feasible2d_pair<NMAX>(kp, I.n_kp, q, I.K, x, p.z_min)) return PURSE_MASK_FEASIBLE;
+  if (!I.has_anchor) return 0;
+  float Ra[9], ta[3], RtR[9], RaT[9], w[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Ra[k] = F.Ra[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) ta[r] = F.ta[r];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) RaT[3 * r + c] = Ra[3 * c + r];
+  matmul3(RaT, x.R, RtR);
+  log_so3(RtR, w);
+  float lo = 0.f, hi = 1.f;
+  for (int b = 0; b < p.n_bis; ++b) {
+    float mid = 0.5f * (lo + hi);
+    float wm[3] = {mid * w[0], mid * w[1], mid * w[2]}, E[9];
+    Pose m;
+    exp_so3(wm, E);
+    matmul3(Ra, E, m.R);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) m.t[r] = ta[r] + mid * (x.t[r] - ta[r]);
+    if (feasible2d_pair<NMAX>(kp, I.n_kp, q, I.K, m, p.z_min))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  if (lo == 0.f) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x.R[k] = Ra[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x.t[r] = ta[r];
+  } else {
+    float wl[3] = {lo * w[0], lo * w[1], lo * w[2]}, E[9];
+    exp_so3(wl, E);
+    matmul3(Ra, E, x.R);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) x.t[r] = ta[r] + lo * (x.t[r] - ta[r]);
+  }
+  return PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
+}
+
 }  // namespace purse

@@ -121,7 +121,7 @@ def test_adjoint_matches_fd_of_the_real_forward(kind):
     gc, gL, gb = backward(inst, p, mg["trace"].numpy(), s0, sD, sd, g_radii, g_centre)
     Rref = mg["R"].numpy()
     n_ok = 0
-    for _ in range(10):
+    for _ in range(40):
         dc, dL, db = _direction(rng, inst, kind)
         h = 1e-6
         plus = _full(_perturbed(inst, h * dc, h * dL, h * db), p, M)
