@@ -17,6 +17,7 @@
 // 4. k_bwd_reduce: per direction, the sum over active samples in a fixed
 //    order, scattered into the gradient arrays.
 #include "purse_fit.hpp"
+#include "purse_geodesic.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
 
@@ -83,6 +84,25 @@ __device__ __forceinline__ void step_rot_t(const T C[9], const T R[9], int i, T 
   matmul3<T>(C, E, Cn);
 }
 
+// Rotation matrix of a (renormalised) float quaternion (w, x, y, z), in float64.
+__device__ __forceinline__ void rot_of_quat_d(float4 qf, D R[9]) {
+  D w = qf.x, x = qf.y, y = qf.z, z = qf.w;
+  const D n = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  w *= n;
+  x *= n;
+  y *= n;
+  z *= n;
+  R[0] = 1 - 2 * (y * y + z * z);
+  R[1] = 2 * (x * y - w * z);
+  R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);
+  R[4] = 1 - 2 * (x * x + z * z);
+  R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);
+  R[7] = 2 * (y * z + w * x);
+  R[8] = 1 - 2 * (x * x + y * y);
+}
+
 __device__ __forceinline__ void load_R(const float *poses, int64_t g, D R[9]) {
   const float *P = poses + 12 * g;
   for (int k = 0; k < 9; ++k) R[k] = (D)P[k];
@@ -113,6 +133,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __shared__ int n_act_s, overflow_s;
   __shared__ double cot[kMaxActive][12];
   __shared__ float pact[kMaxActive][12];       // poses of the active samples
+  __shared__ float4 qact[kMaxActive];          // their rotations as quaternions
   __shared__ uint8_t tslot[2 * kLdsTrace];     // trace as active-set slots
   __shared__ double jac[kBwdBlock][2][9];      // J_C, J_R of the steps of one chunk
   __shared__ double jadd[kBwdBlock][3];        // averaged-iterate terms of those steps
@@ -206,25 +227,35 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act_s, tr[k]);
   }
   __syncthreads();
+  for (int a = tid; a < n_act_s && !overflow_s; a += kBwdBlock) qact[a] = quat_from_rot(pact[a]);
+  __syncthreads();
   auto slot_of = [&](int k) { return lds_trace ? (int)tslot[k] : find_active(act, n_act_s, tr[k]); };
   auto load_act = [&](int a, D R[9]) {
     for (int q = 0; q < 9; ++q) R[q] = (D)pact[a][q];
   };
-  // ---- replay the descent in float64 (thread 0: rotation, thread 64: translation)
-  double *ckpt = ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9;
+  // ---- replay the descent (thread 0: rotation, thread 64: translation).
+  // The rotation chain repeats the forward's float32 quaternion steps, so the
+  // backward linearises at the iterates the forward computed; every ck-th
+  // iterate is kept as a checkpoint.
+  float *ckq = reinterpret_cast<float *>(ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9);
   if (tid == 0 && !overflow_s) {
-    D C[9], S[9];
-    load_act(find_active(act, n_act_s, s0), C);
+    float4 C = qact[find_active(act, n_act_s, s0)];
+    D S[9];
     for (int k = 0; k < 9; ++k) S[k] = 0;
     for (int i = 1; i <= T; ++i) {
-      if ((i - 1) % ck == 0)
-        for (int k = 0; k < 9; ++k) ckpt[((i - 1) / ck) * 9 + k] = C[k];
-      D R[9], Cn[9];
-      load_act(slot_of(2 * (i - 1)), R);
-      step_rot_t<D>(C, R, i, Cn);
-      for (int k = 0; k < 9; ++k) C[k] = Cn[k];
-      if (i > T - avg)
-        for (int k = 0; k < 9; ++k) S[k] += C[k];
+      if ((i - 1) % ck == 0) {
+        float *c = ckq + 4 * ((i - 1) / ck);
+        c[0] = C.x;
+        c[1] = C.y;
+        c[2] = C.z;
+        c[3] = C.w;
+      }
+      C = geodesic_step(C, qact[slot_of(2 * (i - 1))], i, 0);
+      if (i > T - avg) {
+        D Cm[9];
+        rot_of_quat_d(C, Cm);
+        for (int k = 0; k < 9; ++k) S[k] += Cm[k];
+      }
     }
     D Rs[9];
     polar_so3<D>(S, Rs, 12);
@@ -342,6 +373,8 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act, tr[k]);
   }
   __syncthreads();
+  for (int a = tid; a < n_act && !overflow_s; a += kBwdBlock) qact[a] = quat_from_rot(pact[a]);
+  __syncthreads();
   // ---- reverse sweeps
   // Rotation chain.  Thread 0 turns the cotangents of R* and the rotation
   // radius into S_bar = dL/dS (S = sum of the last iterates).  Then the T
@@ -407,16 +440,13 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       const int i_lo = max(1, i_hi - kBwdBlock + 1);
       const int i = i_lo + tid;
       if (i <= i_hi) {
-        // C_{i-1} from the checkpoint C_{q ck}, q = (i - 1) / ck
+        // C_{i-1}: the forward's float32 steps from the checkpoint C_{q ck}, q = (i - 1) / ck
         const int q = (i - 1) / ck;
+        const float *cq = ckq + 4 * q;
+        float4 Cf = make_float4(cq[0], cq[1], cq[2], cq[3]);
+        for (int m = q * ck + 1; m <= i - 1; ++m) Cf = geodesic_step(Cf, qact[slot_of(2 * (m - 1))], m, 0);
         D C[9];
-        for (int k = 0; k < 9; ++k) C[k] = ckpt[q * 9 + k];
-        for (int m = q * ck + 1; m <= i - 1; ++m) {
-          D R[9], Cn[9];
-          load_act(slot_of(2 * (m - 1)), R);
-          step_rot_t<D>(C, R, m, Cn);
-          for (int k = 0; k < 9; ++k) C[k] = Cn[k];
-        }
+        rot_of_quat_d(Cf, C);
         D R[9];
         load_act(slot_of(2 * (i - 1)), R);
         D Ci[9];
