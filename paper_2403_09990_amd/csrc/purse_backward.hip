@@ -240,9 +240,12 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   float *ckq = reinterpret_cast<float *>(ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9);
   if (tid == 0 && !overflow_s) {
     float4 C = qact[find_active(act, n_act_s, s0)];
+    float4 Bn = qact[slot_of(0)];  // sample of the next step, read one step ahead
     D S[9];
     for (int k = 0; k < 9; ++k) S[k] = 0;
     for (int i = 1; i <= T; ++i) {
+      const float4 B = Bn;
+      if (i < T) Bn = qact[slot_of(2 * i)];
       if ((i - 1) % ck == 0) {
         float *c = ckq + 4 * ((i - 1) / ck);
         c[0] = C.x;
@@ -250,7 +253,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         c[2] = C.z;
         c[3] = C.w;
       }
-      C = geodesic_step(C, qact[slot_of(2 * (i - 1))], i, 0);
+      C = geodesic_step(C, B, i, 0);
       if (i > T - avg) {
         D Cm[9];
         rot_of_quat_d(C, Cm);
@@ -268,7 +271,8 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     for (int r = 0; r < 3; ++r) c[r] = poses[12 * (off + s0) + 9 + r];
     for (int i = 1; i <= T; ++i) {
       const float *P = pact[slot_of(2 * (i - 1) + 1)];
-      for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) / i;
+      const D inv = 1.0 / (D)i;
+      for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) * inv;
       if (i > T - avg)
         for (int r = 0; r < 3; ++r) acc[r] += c[r];
     }
@@ -435,6 +439,27 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   }
   for (int k = tid; k < kMaxActive * 3; k += kBwdBlock) rho[k / 3][k % 3] = 0.0;
   __syncthreads();
+  // Translation chain: c_i = c_{i-1} + (t_{s_i} - c_{i-1}) / i is linear, so
+  // its reverse is a scalar recurrence per coordinate, swept by thread 64 over
+  // each chunk while thread 0 sweeps the rotation chain.
+  D cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  if (tid == 64 && !overflow_s) {
+    const float *gc = g_centre + 6 * j;
+    tb[0] = gc[3];
+    tb[1] = gc[4];
+    tb[2] = gc[5];
+    const D gd = g_radii[2 * j + 1];
+    const float *Pd = poses + 12 * (off + sd_s);
+    D dv[3] = {tstar[0] - Pd[9], tstar[1] - Pd[10], tstar[2] - Pd[11]};
+    D dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (dn > 0 && gd != 0) {
+      const int pd = find_active(act, n_act, sd_s);
+      for (int r = 0; r < 3; ++r) {
+        tb[r] += gd * dv[r] / dn;
+        cot[pd][9 + r] -= gd * dv[r] / dn;
+      }
+    }
+  }
   if (!overflow_s) {
     for (int i_hi = T; i_hi >= 1; i_hi -= kBwdBlock) {
       const int i_lo = max(1, i_hi - kBwdBlock + 1);
@@ -504,12 +529,26 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
           for (int k = 0; k < 3; ++k) g[k] = gn[k];
         }
         for (int k = 0; k < 3; ++k) gvec[k] = g[k];
+      } else if (tid == 64) {
+        for (int ii = i_hi; ii >= i_lo; --ii) {
+          if (ii > T - avg)
+            for (int r = 0; r < 3; ++r) cb[r] += tb[r] / avg;
+          const int pa = slot_of(2 * (ii - 1) + 1);
+          const D inv = 1.0 / (D)ii;
+          for (int r = 0; r < 3; ++r) {
+            cot[pa][9 + r] += cb[r] * inv;
+            cb[r] *= (1.0 - inv);
+          }
+        }
       }
       __syncthreads();
     }
     if (tid == 0) {
       const int p0 = find_active(act, n_act, s0);
       for (int k = 0; k < 3; ++k) rho[p0][k] += gvec[k];
+    } else if (tid == 64) {
+      const int p0 = find_active(act, n_act, s0);
+      for (int r = 0; r < 3; ++r) cot[p0][9 + r] += cb[r];
     }
     __syncthreads();
     // rho -> ambient cotangent R [rho]x / 2
@@ -520,35 +559,6 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       matmul3<D>(R, Wr, X);
       for (int k = 0; k < 9; ++k) cot[a][k] += 0.5 * X[k];
     }
-  }
-  // Translation chain: c_i = c_{i-1} + (t_{s_i} - c_{i-1}) / i is linear, so
-  // its reverse is a scalar recurrence per coordinate.
-  if (tid == 64 && !overflow_s) {
-    const float *gc = g_centre + 6 * j;
-    D tb[3] = {gc[3], gc[4], gc[5]};
-    const D gd = g_radii[2 * j + 1];
-    const float *Pd = poses + 12 * (off + sd_s);
-    D dv[3] = {tstar[0] - Pd[9], tstar[1] - Pd[10], tstar[2] - Pd[11]};
-    D dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
-    if (dn > 0 && gd != 0) {
-      const int pd = find_active(act, n_act, sd_s);
-      for (int r = 0; r < 3; ++r) {
-        tb[r] += gd * dv[r] / dn;
-        cot[pd][9 + r] -= gd * dv[r] / dn;
-      }
-    }
-    D cb[3] = {0, 0, 0};
-    for (int i = T; i >= 1; --i) {
-      if (i > T - avg)
-        for (int r = 0; r < 3; ++r) cb[r] += tb[r] / avg;
-      const int pa = slot_of(2 * (i - 1) + 1);
-      for (int r = 0; r < 3; ++r) {
-        if (pa >= 0) cot[pa][9 + r] += cb[r] / i;
-        cb[r] *= (1.0 - 1.0 / i);
-      }
-    }
-    const int p0 = find_active(act, n_act, s0);
-    for (int r = 0; r < 3; ++r) cot[p0][9 + r] += cb[r];
   }
   __syncthreads();
   if (tid == 0) {
