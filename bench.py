@@ -173,7 +173,10 @@ def main():
     ms_traj = time_events(lambda: do_sample(gp_reuse), args.roofline_reps, stream)
     flops = F.batch_flops(batch, cfg["iters"], gp.n_gn)
     achieved = flops / (ms_traj * 1e-3) / 1e12
-    traffic = read_traffic("k_sample", args.config)
+    # the trajectory kernel that carries the workload: the pair-lane variant
+    # when the schedule runs 2D-3D trajectories on two lanes each
+    traj_kernel = "k_sample2d_pair" if gp.flags & P.PURSE_FLAG_PAIR_LANES else "k_sample"
+    traffic = read_traffic(traj_kernel, args.config)
     # forward + backward: the step followed by the gradients of random
     # cotangents of the radii and the centre
     ms_fwd_bwd = None
@@ -233,7 +236,7 @@ def main():
         "radii_first_instance": [float(rad[0, 0]), float(rad[0, 1])],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "k_sample (2D-3D and 3D-3D trajectory kernels)",
+                     "traffic": traffic, "kernel": traj_kernel + " (trajectory kernels of the launch)",
                      "flops_per_launch": flops},
         "hbm_write_gbs": total_m * 13 / (ms_traj * 1e-3) / 1e9,
     }

@@ -1,11 +1,16 @@
 // One step of the MEGB geodesic descent on unit quaternions (rotation chain)
-// or points (translation chain), with the float32 sin/cos and atan2 it uses.
-// Shared by the descent and by its replay in the backward.
+// or points (translation chain), with the float32 sin/cos and arctangent it
+// uses.  Shared by the descent and by its replay in the backward, so both
+// take bitwise the same steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace purse {
+
+// From this step on the descent moves by at most (pi/2)/16 in quaternion
+// angle, where the short sin/cos series below are exact to float32.
+constexpr int kShortSeriesStep = 16;
 
 // sin and cos on [0, pi/2] by their Taylor series through x^13 and x^14
 // (truncation below 7e-10 there), evaluated in x^2 by Horner's rule.
@@ -28,16 +33,24 @@ __device__ __forceinline__ void sincos_quadrant(float x, float &s, float &c) {
   c = 1.f - pc * z;
 }
 
-// atan2(y, x) for y, x >= 0 (not both 0): t = min/max in [0, 1]; above
-// tan(pi/8) the tangent addition formula gives atan t = pi/4 + atan u with
-// u = (t - 1) / (t + 1), so |u| <= tan(pi/8); the odd Taylor series of atan u
-// through u^19 (truncation below 5e-10) follows; y > x reflects about pi/4.
-__device__ __forceinline__ float atan2_quadrant(float y, float x) {
-  const float mx = fmaxf(x, y), mn = fminf(x, y);
-  const float t = mn * __builtin_amdgcn_rcpf(mx);
-  const bool hi = t > 0.41421356f;
-  const float u = hi ? (t - 1.f) * __builtin_amdgcn_rcpf(t + 1.f) : t;
-  const float z = u * u;
+// sin and cos on [0, pi/32] by their Taylor series through x^7 and x^6
+// (truncation below 3e-13 there).
+__device__ __forceinline__ void sincos_small(float x, float &s, float &c) {
+  const float z = x * x;
+  float ps = -1.f / 5040.f;
+  ps = ps * z + 1.f / 120.f;
+  ps = ps * z - 1.f / 6.f;
+  s = x + x * (ps * z);
+  float pc = -1.f / 720.f;
+  pc = pc * z + 1.f / 24.f;
+  pc = pc * z - 0.5f;
+  c = 1.f + pc * z;
+}
+
+// atan w for 0 <= w <= tan(pi/8): the odd Taylor series through w^19
+// (truncation below 5e-10 there).
+__device__ __forceinline__ float atan_eighth(float w) {
+  const float z = w * w;
   float p = 1.f / 19.f;
   p = p * z - 1.f / 17.f;
   p = p * z + 1.f / 15.f;
@@ -47,19 +60,22 @@ __device__ __forceinline__ float atan2_quadrant(float y, float x) {
   p = p * z + 1.f / 7.f;
   p = p * z - 1.f / 5.f;
   p = p * z + 1.f / 3.f;
-  float a = u - u * (p * z);
-  if (hi) a += 0.78539816f;
-  return y > x ? 1.57079633f - a : a;
+  return w - w * (p * z);
 }
 
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
 // For unit quaternions a (centre) and b (sample, sign chosen so that a.b >= 0)
 // at quaternion angle h, the step is the spherical interpolation at 1/i:
-//   sin((1 - 1/i) h) / sin h a + sin(h / i) / sin h b.
-// h comes from the chords, sin(h/2) = |a - b'| / 2 and cos(h/2) = |a + b'| / 2,
-// both formed directly, which stay accurate for small angles.
-__device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
-  const float inv = 1.f / (float)i;
+//   sin((1 - 1/i) h) / sin h a + sin(h / i) / sin h b
+//   = (cos(h/i) - cos h sin(h/i) / sin h) a + sin(h/i) / sin h b.
+// The chords |a - b'| = 2 sin(h/2) and |a + b'| = 2 cos(h/2), both formed
+// directly, stay accurate for small angles; h/4 = atan(|a - b'| / (2 + |a + b'|))
+// (half-angle tangent of h/2), its argument at most tan(pi/8).  b' = a gives
+// sin(h/i) = 0 and no move (sin h is clamped away from 0 for that case).
+// inv is 1/i, correctly rounded; SMALL (i >= kShortSeriesStep) selects the
+// short sin/cos series.
+template <bool SMALL>
+__device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int chain) {
   if (chain == 1) return make_float4(a.x + (b.x - a.x) * inv, a.y + (b.y - a.y) * inv, a.z + (b.z - a.z) * inv, 1.f);
   const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
   const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
@@ -68,18 +84,29 @@ __device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int c
   const bool flip = x > y;                                // a . b < 0: use b' = -b
   const float xs = flip ? y : x;                          // |a - b'|^2
   const float ys = flip ? x : y;                          // |a + b'|^2
-  if (!(xs > 0.f)) return a;
-  const float half = atan2_quadrant(__builtin_amdgcn_sqrtf(xs), __builtin_amdgcn_sqrtf(ys));  // h / 2
+  const float rx = __builtin_amdgcn_sqrtf(xs), ry = __builtin_amdgcn_sqrtf(ys);
+  const float quarter = atan_eighth(rx * __builtin_amdgcn_rcpf(2.f + ry));  // h / 4
   float st, ct;
-  sincos_quadrant(2.f * half * inv, st, ct);              // sin, cos of h / i
-  const float sh = 0.5f * __builtin_amdgcn_sqrtf(xs * ys);  // sin h
+  if (SMALL)
+    sincos_small(4.f * quarter * inv, st, ct);            // sin, cos of h / i
+  else
+    sincos_quadrant(4.f * quarter * inv, st, ct);
+  const float sh = 0.5f * rx * ry;                        // sin h
   const float chh = 1.f - 0.5f * xs;                      // cos h
-  const float cb = st * __builtin_amdgcn_rcpf(sh);
+  const float cb = st * __builtin_amdgcn_rcpf(fmaxf(sh, 1e-30f));
   const float ca = ct - chh * cb;
   const float cbs = flip ? -cb : cb;
   float4 q = make_float4(ca * a.x + cbs * b.x, ca * a.y + cbs * b.y, ca * a.z + cbs * b.z, ca * a.w + cbs * b.w);
-  const float nn = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  const float nn = __builtin_amdgcn_rsqf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);  // |q| ~ 1
   return make_float4(q.x * nn, q.y * nn, q.z * nn, q.w * nn);
+}
+
+__device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int i, int chain) {
+  return i >= kShortSeriesStep ? geodesic_step_inv<true>(a, b, inv, chain) : geodesic_step_inv<false>(a, b, inv, chain);
+}
+
+__device__ __forceinline__ float4 geodesic_step(float4 a, float4 b, int i, int chain) {
+  return geodesic_step_inv(a, b, 1.f / (float)i, i, chain);
 }
 
 }  // namespace purse

@@ -112,6 +112,35 @@ __device__ __forceinline__ void accumulate_iterate(float4 C, int chain, float ac
 
 __device__ __forceinline__ float wave_max(float v) { return wave_max_key(v); }
 
+// Streams elements [0, M) of src to the workgroup in rounds of
+// kChainBlock * kUnroll elements (element s0 + u * kChainBlock + tid to thread
+// tid, past M the pad value).  The loads of the next round are issued before
+// the current round is handed to f(vals, s0), so two rounds are in flight.
+// Loads are unconditional at an index clamped to M - 1 (vector loads, and no
+// branch that would make the wait counts conservative); the pad is selected
+// afterwards.
+template <typename T, typename F>
+__device__ __forceinline__ void stream_rounds(const T *__restrict__ src, int M, T pad, F &&f) {
+  constexpr int R = kChainBlock * kUnroll;
+  if (M <= 0) return;
+  const int tid = threadIdx.x;
+  const int last = M - 1;
+  T cur[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) cur[u] = src[min(u * kChainBlock + tid, last)];
+  for (int s0 = 0; s0 < M; s0 += R) {
+    T nxt[kUnroll];  // (the last round reloads in-range elements it does not use)
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) nxt[u] = src[min(s0 + R + u * kChainBlock + tid, last)];
+    T v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = s0 + u * kChainBlock + tid < M ? cur[u] : pad;
+    f(v, s0);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
+  }
+}
+
 }  // namespace
 
 __global__ void k_megb_init(int n_inst, MegbRec *rec) {
@@ -242,26 +271,20 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       // -------------------------------------------------------------- rescan
       ++n_rescan;
       float mx = 0.f;
-      for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
-        float4 a[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          int s = s0 + u * kChainBlock + tid;
-          a[u] = s < M ? D[s] : make_float4(-2.f, 0.f, 0.f, 0.f);
-        }
+      stream_rounds(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           int s = s0 + u * kChainBlock + tid;
           if (s < M) {
             float d = -1.f;
             if (feasible_pt(a[u], chain)) {
-              d = sqrtf(sqdist(Cref, a[u], chain));
+              d = __builtin_amdgcn_sqrtf(sqdist(Cref, a[u], chain));  // within the slack
               mx = fmaxf(mx, d);
             }
             dref[s] = d;
           }
         }
-      }
+      });
       mx = wave_max(mx);
       if (lane == 0) S.red_k[0][wave] = mx;
       __syncthreads();
@@ -289,17 +312,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           }
           for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
           __syncthreads();
-          for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
-            float dd[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-              int s = s0 + u * kChainBlock + tid;
-              dd[u] = s < M ? dref[s] : -1.f;
-            }
+          stream_rounds(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
               if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, wdt)], 1u);
-          }
+          });
           __syncthreads();
           if (tid == 0) {
             int cum = 0, bb = kBins - 1;
@@ -338,17 +355,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         auto fbin = [&](float d) { return fine ? bin_of(d, flo, fw) : kBins - 1; };
         for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
         __syncthreads();
-        for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
-          float dd[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            int s = s0 + u * kChainBlock + tid;
-            dd[u] = s < M ? dref[s] : -1.f;
-          }
+        stream_rounds(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u)
             if (member(dd[u])) atomicAdd(&S.hist[fbin(dd[u])], 1u);
-        }
+        });
         __syncthreads();
         if (tid == 0) {
           // entries in decreasing fine-bin order: cursor[b] = first slot of bin b
@@ -362,13 +373,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         }
         __syncthreads();
         if (st_mode == 0) {
-          for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
-            float dd[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-              int s = s0 + u * kChainBlock + tid;
-              dd[u] = s < M ? dref[s] : -1.f;
-            }
+          stream_rounds(dref, M, -1.f, [&](const float *dd, int s0) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
               int s = s0 + u * kChainBlock + tid;
@@ -380,7 +385,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 }
               }
             }
-          }
+          });
           __syncthreads();
           // upper bound of d_ref over each chunk of 64 entries: the upper edge
           // of the fine bin holding its first entry (the top bin's is rref)
@@ -410,13 +415,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       while (i <= i_end) {
         float bk = -1.f;
         int bi = INT32_MAX;
-        for (int s0 = 0; s0 < M; s0 += kChainBlock * kUnroll) {
-          float4 a[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            int s = s0 + u * kChainBlock + tid;
-            a[u] = s < M ? D[s] : make_float4(-2.f, 0.f, 0.f, 0.f);
-          }
+        stream_rounds(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             int s = s0 + u * kChainBlock + tid;
@@ -428,7 +427,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               }
             }
           }
-        }
+        });
         float wk;
         int wi;
         wave_argmax(bk, bi, wk, wi);
@@ -463,10 +462,17 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       // d_ref.  Each lane keeps its own best (key, id, point) over a group of
       // kGroup chunks, one wavefront reduction per group, and the scan stops
       // once no later chunk can beat the best found.  The first two groups,
-      // which almost every step needs, stay in registers for the whole stage;
-      // later groups are read from LDS, the next one while this one is
-      // reduced.  When a step needs many groups the centre has drifted from
+      // which almost every step needs, stay in registers for the whole stage
+      // (lanes past the shell's end hold copies of entry 0, which change no
+      // argmax); later groups are read from LDS, the next one while this one
+      // is reduced.  When a step needs many groups the centre has drifted from
       // C_ref: the stage ends and the next one rescans there.
+      //
+      // A single wavefront issues about one instruction every few cycles
+      // whatever the dependences, so the common step (the first group
+      // suffices, one lane holds the maximum) is one straight path: 1/i comes
+      // from a per-lane table of the next 64 values, and the winners' ids are
+      // collected one per lane and written 64 at a time.
       const int K = (int)sh_n;
       const float theta = st_theta;
       const float slack = 4e-6f * st_rref + 1e-30f;
@@ -477,99 +483,132 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         int q0[kGroup], q1[kGroup];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
-          p0[u] = S.pt[u * 64 + lane];
-          q0[u] = S.id[u * 64 + lane];
-          p1[u] = S.pt[(kGroup + u) * 64 + lane];
-          q1[u] = S.id[(kGroup + u) * 64 + lane];
+          const int e0 = u * 64 + lane, e1 = (kGroup + u) * 64 + lane;
+          p0[u] = S.pt[e0 < K ? e0 : 0];
+          q0[u] = S.id[e0 < K ? e0 : 0];
+          p1[u] = S.pt[e1 < K ? e1 : 0];
+          q1[u] = S.id[e1 < K ? e1 : 0];
         }
         const float ub1 = ngroups > 1 ? S.chunk_ub[kGroup] : 0.f;
         const float ub2 = ngroups > 2 ? S.chunk_ub[2 * kGroup] : 0.f;
+        // the one bound the common step checks: entries past the first group,
+        // else (one group) samples outside the shell, else none
+        const bool need_ub = ngroups > 1 || theta >= 0.f;
+        const float ubf = ngroups > 1 ? ub1 : theta;
         float4 C = Cref;
         int i = i0;
+        int ib = i;                                 // first step of the block of 64
+        float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
+        int trv = 0;                                // winner of step ib + lane
         while (i <= T) {
+          if (i - ib == 64) {
+            tr[2 * (ib - 1 + lane)] = trv;
+            ib = i;
+            inv_tab = 1.f / (float)(ib + lane);
+          }
+          const float inv = readlane_f(inv_tab, i - ib);
           // bounds compared squared; the raw square root is within the slack
           const float dC = __builtin_amdgcn_sqrtf(sqdist(C, Cref, chain));
           auto beats = [&](float key, float ub) {
             const float b = ub + dC + slack;
             return key > b * b;
           };
-          float bk = -1.f;
-          int bi = INT32_MAX;
-          float4 bp = make_float4(0.f, 0.f, 0.f, 0.f);
-          auto scan = [&](const float4 *pp, const int *qq, int g) {
+          float bk, bp_x, bp_y, bp_z, bp_w;
+          int bi;
+          auto take_if = [&](bool take, float k, int q, float4 pp) {
+            bk = take ? k : bk;
+            bi = take ? q : bi;
+            bp_x = take ? pp.x : bp_x;
+            bp_y = take ? pp.y : bp_y;
+            bp_z = take ? pp.z : bp_z;
+            bp_w = take ? pp.w : bp_w;
+          };
+          auto scan = [&](const float4 *pp, const int *qq, int g, bool check) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
               // selects only (no control flow): every lane evaluates every entry
-              const bool valid = (g * kGroup + u) * 64 + lane < K;
               const float kk = sqdist(C, pp[u], chain);
-              const float k = valid ? kk : -1.f;
-              const bool take = (k > bk) | ((k == bk) & (qq[u] < bi));
-              bk = take ? k : bk;
-              bi = take ? qq[u] : bi;
-              bp.x = take ? pp[u].x : bp.x;
-              bp.y = take ? pp[u].y : bp.y;
-              bp.z = take ? pp[u].z : bp.z;
-              bp.w = take ? pp[u].w : bp.w;
+              const float k = (!check || (g * kGroup + u) * 64 + lane < K) ? kk : -1.f;
+              take_if((k > bk) | ((k == bk) & (qq[u] < bi)), k, qq[u], pp[u]);
             }
           };
-          scan(p0, q0, 0);
+          // group 0 (entry 0 of each lane taken outright)
+          bk = sqdist(C, p0[0], chain);
+          bi = q0[0];
+          bp_x = p0[0].x;
+          bp_y = p0[0].y;
+          bp_z = p0[0].z;
+          bp_w = p0[0].w;
+#pragma unroll
+          for (int u = 1; u < kGroup; ++u) {
+            const float k = sqdist(C, p0[u], chain);
+            take_if((k > bk) | ((k == bk) & (q0[u] < bi)), k, q0[u], p0[u]);
+          }
           float wk = wave_max_key(bk);
+          unsigned long long win = __ballot(bk == wk);
           int g = 1;
-          if (ngroups > 1 && !beats(wk, ub1)) {
-            scan(p1, q1, 1);
-            wk = wave_max_key(bk);
-            g = 2;
-            if (ngroups > 2 && !beats(wk, ub2)) {
-              float4 p[kGroup];
-              int q[kGroup];
-#pragma unroll
-              for (int u = 0; u < kGroup; ++u) {
-                p[u] = S.pt[(2 * kGroup + u) * 64 + lane];
-                q[u] = S.id[(2 * kGroup + u) * 64 + lane];
-              }
-              while (true) {
-                float4 np[kGroup];
-                int nq[kGroup];
-                const bool more = g + 1 < ngroups;
-                if (more) {
-#pragma unroll
-                  for (int u = 0; u < kGroup; ++u) {
-                    const int e = ((g + 1) * kGroup + u) * 64 + lane;
-                    np[u] = S.pt[e];
-                    nq[u] = S.id[e];
-                  }
-                }
-                scan(p, q, g);
-                wk = wave_max_key(bk);
-                ++g;
-                if (!more || beats(wk, S.chunk_ub[g * kGroup])) break;
+          if (!((!need_ub || beats(wk, ubf)) && __popcll(win) == 1)) {
+            // ------------------------------------------------ uncommon step
+            if (ngroups > 1 && !beats(wk, ub1)) {
+              scan(p1, q1, 1, false);
+              wk = wave_max_key(bk);
+              g = 2;
+              if (ngroups > 2 && !beats(wk, ub2)) {
+                float4 p[kGroup];
+                int q[kGroup];
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u) {
-                  p[u] = np[u];
-                  q[u] = nq[u];
+                  p[u] = S.pt[(2 * kGroup + u) * 64 + lane];
+                  q[u] = S.id[(2 * kGroup + u) * 64 + lane];
+                }
+                while (true) {
+                  float4 np[kGroup];
+                  int nq[kGroup];
+                  const bool more = g + 1 < ngroups;
+                  if (more) {
+#pragma unroll
+                    for (int u = 0; u < kGroup; ++u) {
+                      const int e = ((g + 1) * kGroup + u) * 64 + lane;
+                      np[u] = S.pt[e];
+                      nq[u] = S.id[e];
+                    }
+                  }
+                  scan(p, q, g, true);
+                  wk = wave_max_key(bk);
+                  ++g;
+                  if (!more || beats(wk, S.chunk_ub[g * kGroup])) break;
+#pragma unroll
+                  for (int u = 0; u < kGroup; ++u) {
+                    p[u] = np[u];
+                    q[u] = nq[u];
+                  }
                 }
               }
+            }
+            if (theta >= 0.f && !beats(wk, theta)) {
+              n_groups += g;
+              break;  // the shell no longer suffices
+            }
+            // winner: the one lane holding the maximum key, else (a tie) the
+            // lowest sample id among the lanes that hold it
+            win = __ballot(bk == wk);
+            if (__popcll(win) > 1) {
+              const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
+              win = __ballot(bk == wk && bi == wmin);
             }
           }
           n_groups += g;
-          if (theta >= 0.f && !beats(wk, theta)) break;  // the shell no longer suffices
-          // winner: the one lane holding the maximum key, else (a tie) the
-          // lowest sample id among the lanes that hold it
-          unsigned long long win = __ballot(bk == wk);
-          if (__popcll(win) > 1) {
-            const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
-            win = __ballot(bk == wk && bi == wmin);
-          }
           const int wl = (int)__ffsll((long long)win) - 1;
           const int wi = __builtin_amdgcn_readlane(bi, wl);
-          const float4 pt = make_float4(readlane_f(bp.x, wl), readlane_f(bp.y, wl), readlane_f(bp.z, wl),
-                                        readlane_f(bp.w, wl));
-          C = geodesic_step(C, pt, i, chain);
-          if (lane == 0) tr[2 * (i - 1)] = wi;
+          const float4 pt =
+              make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
+          C = geodesic_step_inv(C, pt, inv, i, chain);
+          trv = lane == i - ib ? wi : trv;
           if (i > T - avg) accumulate_iterate(C, chain, acc);
           ++i;
           if (g > kRecentreGroups && i - i0 > kMinShellSteps) break;  // re-centre the shell
         }
+        if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
         if (lane == 0) {
           st_C = C;
           st_i = i;
