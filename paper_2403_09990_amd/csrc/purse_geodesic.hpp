@@ -17,20 +17,20 @@ constexpr int kShortSeriesStep = 16;
 __device__ __forceinline__ void sincos_quadrant(float x, float &s, float &c) {
   const float z = x * x;
   float ps = 1.f / 6227020800.f;       // 1/13!
-  ps = ps * z - 1.f / 39916800.f;      // 1/11!
-  ps = ps * z + 1.f / 362880.f;        // 1/9!
-  ps = ps * z - 1.f / 5040.f;          // 1/7!
-  ps = ps * z + 1.f / 120.f;
-  ps = ps * z - 1.f / 6.f;
-  s = x + x * (ps * z);
+  ps = fmaf(ps, z, -1.f / 39916800.f);      // 1/11!
+  ps = fmaf(ps, z, 1.f / 362880.f);        // 1/9!
+  ps = fmaf(ps, z, -1.f / 5040.f);          // 1/7!
+  ps = fmaf(ps, z, 1.f / 120.f);
+  ps = fmaf(ps, z, -1.f / 6.f);
+  s = fmaf(x, ps * z, x);
   float pc = 1.f / 87178291200.f;      // 1/14!
-  pc = pc * z - 1.f / 479001600.f;     // 1/12!
-  pc = pc * z + 1.f / 3628800.f;       // 1/10!
-  pc = pc * z - 1.f / 40320.f;         // 1/8!
-  pc = pc * z + 1.f / 720.f;
-  pc = pc * z - 1.f / 24.f;
-  pc = pc * z + 0.5f;
-  c = 1.f - pc * z;
+  pc = fmaf(pc, z, -1.f / 479001600.f);     // 1/12!
+  pc = fmaf(pc, z, 1.f / 3628800.f);       // 1/10!
+  pc = fmaf(pc, z, -1.f / 40320.f);         // 1/8!
+  pc = fmaf(pc, z, 1.f / 720.f);
+  pc = fmaf(pc, z, -1.f / 24.f);
+  pc = fmaf(pc, z, 0.5f);
+  c = fmaf(-pc, z, 1.f);
 }
 
 // sin and cos on [0, pi/32] by their Taylor series through x^7 and x^6
@@ -38,13 +38,13 @@ __device__ __forceinline__ void sincos_quadrant(float x, float &s, float &c) {
 __device__ __forceinline__ void sincos_small(float x, float &s, float &c) {
   const float z = x * x;
   float ps = -1.f / 5040.f;
-  ps = ps * z + 1.f / 120.f;
-  ps = ps * z - 1.f / 6.f;
-  s = x + x * (ps * z);
+  ps = fmaf(ps, z, 1.f / 120.f);
+  ps = fmaf(ps, z, -1.f / 6.f);
+  s = fmaf(x, ps * z, x);
   float pc = -1.f / 720.f;
-  pc = pc * z + 1.f / 24.f;
-  pc = pc * z - 0.5f;
-  c = 1.f + pc * z;
+  pc = fmaf(pc, z, 1.f / 24.f);
+  pc = fmaf(pc, z, -0.5f);
+  c = fmaf(pc, z, 1.f);
 }
 
 // atan w for 0 <= w <= tan(pi/8): the odd Taylor series through w^19
@@ -52,15 +52,15 @@ __device__ __forceinline__ void sincos_small(float x, float &s, float &c) {
 __device__ __forceinline__ float atan_eighth(float w) {
   const float z = w * w;
   float p = 1.f / 19.f;
-  p = p * z - 1.f / 17.f;
-  p = p * z + 1.f / 15.f;
-  p = p * z - 1.f / 13.f;
-  p = p * z + 1.f / 11.f;
-  p = p * z - 1.f / 9.f;
-  p = p * z + 1.f / 7.f;
-  p = p * z - 1.f / 5.f;
-  p = p * z + 1.f / 3.f;
-  return w - w * (p * z);
+  p = fmaf(p, z, -1.f / 17.f);
+  p = fmaf(p, z, 1.f / 15.f);
+  p = fmaf(p, z, -1.f / 13.f);
+  p = fmaf(p, z, 1.f / 11.f);
+  p = fmaf(p, z, -1.f / 9.f);
+  p = fmaf(p, z, 1.f / 7.f);
+  p = fmaf(p, z, -1.f / 5.f);
+  p = fmaf(p, z, 1.f / 3.f);
+  return fmaf(-w, p * z, w);
 }
 
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).
@@ -76,28 +76,31 @@ __device__ __forceinline__ float atan_eighth(float w) {
 // short sin/cos series.
 template <bool SMALL>
 __device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int chain) {
-  if (chain == 1) return make_float4(a.x + (b.x - a.x) * inv, a.y + (b.y - a.y) * inv, a.z + (b.z - a.z) * inv, 1.f);
+  // (explicit fused multiply-adds: every caller rounds the step the same way)
+  if (chain == 1) return make_float4(fmaf(b.x - a.x, inv, a.x), fmaf(b.y - a.y, inv, a.y), fmaf(b.z - a.z, inv, a.z), 1.f);
   const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
   const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
-  const float x = m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3;  // |a - b|^2
-  const float y = p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3;  // |a + b|^2
+  const float x = fmaf(m3, m3, fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));  // |a - b|^2
+  const float y = fmaf(p3, p3, fmaf(p2, p2, fmaf(p1, p1, p0 * p0)));  // |a + b|^2
   const bool flip = x > y;                                // a . b < 0: use b' = -b
   const float xs = flip ? y : x;                          // |a - b'|^2
   const float ys = flip ? x : y;                          // |a + b'|^2
   const float rx = __builtin_amdgcn_sqrtf(xs), ry = __builtin_amdgcn_sqrtf(ys);
   const float quarter = atan_eighth(rx * __builtin_amdgcn_rcpf(2.f + ry));  // h / 4
+  const float th = (4.f * quarter) * inv;
   float st, ct;
   if (SMALL)
-    sincos_small(4.f * quarter * inv, st, ct);            // sin, cos of h / i
+    sincos_small(th, st, ct);  // sin, cos of h / i
   else
-    sincos_quadrant(4.f * quarter * inv, st, ct);
-  const float sh = 0.5f * rx * ry;                        // sin h
-  const float chh = 1.f - 0.5f * xs;                      // cos h
+    sincos_quadrant(th, st, ct);
+  const float sh = (0.5f * rx) * ry;                      // sin h
+  const float chh = fmaf(-0.5f, xs, 1.f);                 // cos h
   const float cb = st * __builtin_amdgcn_rcpf(fmaxf(sh, 1e-30f));
-  const float ca = ct - chh * cb;
+  const float ca = fmaf(-chh, cb, ct);
   const float cbs = flip ? -cb : cb;
-  float4 q = make_float4(ca * a.x + cbs * b.x, ca * a.y + cbs * b.y, ca * a.z + cbs * b.z, ca * a.w + cbs * b.w);
-  const float nn = __builtin_amdgcn_rsqf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);  // |q| ~ 1
+  const float4 q = make_float4(fmaf(cbs, b.x, ca * a.x), fmaf(cbs, b.y, ca * a.y), fmaf(cbs, b.z, ca * a.z),
+                               fmaf(cbs, b.w, ca * a.w));
+  const float nn = __builtin_amdgcn_rsqf(fmaf(q.w, q.w, fmaf(q.z, q.z, fmaf(q.y, q.y, q.x * q.x))));  // |q| ~ 1
   return make_float4(q.x * nn, q.y * nn, q.z * nn, q.w * nn);
 }
 

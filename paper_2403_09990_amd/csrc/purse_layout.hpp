@@ -48,6 +48,9 @@ struct MegbRec {
   unsigned long long max_trans;  // float64 bit pattern of max ||t* - t_s||^2
   float centre[12];       // R* row-major, t*
   long long n_groups[2];  // diagnostics: chunk groups scanned in shell steps per chain
+  float4 early_c[2];      // centre after the steps taken by the multi-workgroup first phase
+  int32_t early_arrive[2];  // workgroups of the current first-phase step that have finished
+  int32_t pad2[2];
 };
 
 // Backward scratch.

@@ -44,14 +44,19 @@ __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
 // Squared distance: ||R_a - R_b||_F^2 = 2 |a - b|^2 |a + b|^2 for unit
 // quaternions a, b (chain 0; both chords are formed directly, so the key stays
 // accurate whichever sign b carries); |a - b|^2 for translations (chain 1).
+// The sums are written as explicit fused multiply-adds so that every code path
+// (shell steps, full scans, the multi-workgroup first phase) rounds a key the
+// same way and takes the same argmax decisions.
 __device__ __forceinline__ float sqdist(float4 a, float4 b, int chain) {
   if (chain == 0) {
-    float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
-    float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
-    return 2.f * (m0 * m0 + m1 * m1 + m2 * m2 + m3 * m3) * (p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3);
+    const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
+    const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
+    const float x = fmaf(m3, m3, fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));
+    const float y = fmaf(p3, p3, fmaf(p2, p2, fmaf(p1, p1, p0 * p0)));
+    return (2.f * x) * y;
   }
-  float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
-  return d0 * d0 + d1 * d1 + d2 * d2;
+  const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z;
+  return fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
 }
 
 // (key desc, id asc) comparison
@@ -150,6 +155,111 @@ __global__ void k_megb_init(int n_inst, MegbRec *rec) {
   rec[j].n_feasible = 0ull;
   rec[j].max_rot = 0ull;
   rec[j].max_trans = 0ull;
+  rec[j].early_arrive[0] = rec[j].early_arrive[1] = 0;
+}
+
+// The first kEarlySteps steps move the centre across the whole sample cloud,
+// so each needs a scan of every feasible sample.  For instances of at least
+// kBigInstance samples these scans are spread over many workgroups, one
+// launch per step (k_megb_early); smaller instances take them inside their
+// chain's workgroup.  Host and device apply the same rule.
+constexpr int64_t kBigInstance = 32768;
+constexpr int kEarlyBlock = 256;
+constexpr int kEarlyPer = 8;                            // samples per thread
+constexpr int kEarlySpan = kEarlyBlock * kEarlyPer;     // samples per workgroup
+
+__host__ __device__ inline bool early_phase_applies(int64_t M, int T, int avg, int no_prune) {
+  return M >= kBigInstance && T > kEarlySteps + avg && !no_prune;
+}
+
+// One step i of both chains of every instance the rule selects, whose
+// feasible samples outnumber the shell capacity (else the shell holds them
+// all and the chain's workgroup needs no full scans).  Workgroup b of
+// (instance j, chain c) finds the farthest of its kEarlySpan samples from the
+// current centre and leaves (key, id) in the scratch of the chain's d_ref
+// array; the last workgroup to finish (arrival counter) reduces those, takes
+// the geodesic step and records the trace, and resets the counter.
+__global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__restrict__ sample_off, int64_t total,
+                                                            int64_t max_m, const float4 *__restrict__ quat,
+                                                            const float4 *__restrict__ trans, MegbRec *rec,
+                                                            float *dref_all, int32_t *trace, int T, int avg,
+                                                            int cap, int no_prune, int i) {
+  const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t off, M64;
+  sample_range(sample_off, j, total, max_m, off, M64);
+  if (!early_phase_applies(M64, T, avg, no_prune)) return;
+  const int M = (int)M64;
+  const int first = rec[j].first;
+  if (first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
+  const int nb = (M + kEarlySpan - 1) / kEarlySpan;
+  if (b >= nb) return;
+  const float4 *D = (chain ? trans : quat) + off;
+  const float4 C = i == 1 ? D[first] : rec[j].early_c[chain];
+  float bk = -1.f;
+  int bi = INT32_MAX;
+  float4 a[kEarlyPer];
+#pragma unroll
+  for (int u = 0; u < kEarlyPer; ++u) a[u] = D[min(b * kEarlySpan + u * kEarlyBlock + tid, M - 1)];
+#pragma unroll
+  for (int u = 0; u < kEarlyPer; ++u) {
+    const int s = b * kEarlySpan + u * kEarlyBlock + tid;
+    const float k = sqdist(C, a[u], chain);
+    // increasing s per thread: a strictly larger key replaces the best
+    if (s < M && feasible_pt(a[u], chain) && k > bk) {
+      bk = k;
+      bi = s;
+    }
+  }
+  __shared__ float red_k[kEarlyBlock / 64];
+  __shared__ int red_i[kEarlyBlock / 64];
+  __shared__ int last;
+  auto block_argmax = [&]() {
+    float wk;
+    int wi;
+    wave_argmax(bk, bi, wk, wi);
+    if (lane == 0) {
+      red_k[wave] = wk;
+      red_i[wave] = wi;
+    }
+    __syncthreads();
+    bk = red_k[0];
+    bi = red_i[0];
+#pragma unroll
+    for (int w = 1; w < kEarlyBlock / 64; ++w)
+      if (better(red_k[w], red_i[w], bk, bi)) {
+        bk = red_k[w];
+        bi = red_i[w];
+      }
+  };
+  block_argmax();
+  float *part = dref_all + (int64_t)chain * total + off;  // 2 nb floats <= M
+  if (tid == 0) {
+    part[2 * b] = bk;
+    part[2 * b + 1] = __int_as_float(bi);
+    __threadfence();
+    last = atomicAdd(&rec[j].early_arrive[chain], 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  bk = -1.f;
+  bi = INT32_MAX;
+  for (int k = tid; k < nb; k += kEarlyBlock) {
+    const float pk = part[2 * k];
+    const int pi = __float_as_int(part[2 * k + 1]);
+    if (better(pk, pi, bk, bi)) {
+      bk = pk;
+      bi = pi;
+    }
+  }
+  __syncthreads();  // red_k / red_i reused
+  block_argmax();
+  if (tid == 0) {
+    if (bi < M) rec[j].early_c[chain] = geodesic_step(C, D[bi], i, chain);
+    trace[((int64_t)j * T + i - 1) * 2 + chain] = bi;
+    rec[j].early_arrive[chain] = 0;
+  }
 }
 
 // Per sample: quaternion (w >= 0; w = -2 marks an infeasible sample) and
@@ -250,8 +360,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   }
   const int n_feas = (int)rec[j].n_feasible;
   if (tid == 0) {
-    st_C = D[first];
-    st_i = 1;
+    // the first steps were taken by k_megb_early when the rule selects it
+    const bool ep = early_phase_applies(M64, T, avg, no_prune) && n_feas > cap;
+    st_C = ep ? rec[j].early_c[chain] : D[first];
+    st_i = ep ? kEarlySteps + 1 : 1;
   }
   __syncthreads();
   float acc[9];
@@ -740,6 +852,12 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   const int cap = kCap;
   const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
   const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
+  if (early_phase_applies(max_samples, p.megb_iters, p.megb_avg, no_prune)) {
+    const dim3 eg((unsigned)((max_samples + kEarlySpan - 1) / kEarlySpan), 2u, (unsigned)n);
+    for (int i = 1; i <= kEarlySteps; ++i)
+      hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
+                         quat, trans, rec, dref, trace, p.megb_iters, p.megb_avg, cap, no_prune, i);
+  }
   hipLaunchKernelGGL(k_megb_chain, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat, trans,
                      rec, dref,
                      total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);

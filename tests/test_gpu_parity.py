@@ -184,12 +184,14 @@ def test_deterministic_and_batch_independent():
         assert torch.equal(single["trace"][0], r1["trace"][j])
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c2-full"])
 def test_megb_against_oracle_on_gpu_samples(cfg):
     """The GPU's MEGB against the oracle's MEGB on the GPU's own samples (read
-    back exactly), which isolates the MEGB arithmetic from sampler rounding."""
+    back exactly), which isolates the MEGB arithmetic from sampler rounding.
+    At the full 65,536 samples the first steps run in the multi-workgroup
+    first phase."""
     _log("case: megb", cfg)
-    b = W.config_c1(0) if cfg == "c1" else W.config_c2(0, n_samples=8192)
+    b = {"c1": W.config_c1(0), "c2": W.config_c2(0, n_samples=8192), "c2-full": W.config_c2(0)}[cfg]
     gp = _params(n_iters=50 if cfg == "c1" else 100)
     res = PT.run_gpu(b, gp)
     ora = PT.oracle_megb(res["poses"].cpu().numpy(), res["mask"].cpu().numpy(), gp.megb_iters, gp.megb_avg)
@@ -206,11 +208,14 @@ def test_megb_against_oracle_on_gpu_samples(cfg):
     assert int(res["n_feasible"][0]) == ora["n"]
 
 
-def test_megb_pruning_is_exact():
-    """The LDS shell with triangle-inequality checks gives bitwise the same
-    argmax trace and centre as scanning every sample at every step."""
-    _log("case: pruning")
-    b = W.config_c2(1, n_samples=12000)
+@pytest.mark.parametrize("m", [12000, 40000])
+def test_megb_pruning_is_exact(m):
+    """The LDS shell with triangle-inequality checks (and, from 32,768
+    samples, the first steps spread over many workgroups) gives bitwise the
+    same argmax trace and centre as scanning every sample at every step in
+    one workgroup."""
+    _log("case: pruning", m)
+    b = W.config_c2(1, n_samples=m)
     gp = _params(n_iters=40, megb_iters=1024)
     res = PT.run_gpu(b, gp)
     import paper_2403_09990_amd as P
