@@ -14,6 +14,8 @@
 // run in one wavefront with shuffles only.
 #include <float.h>
 
+#include <type_traits>
+
 #include "purse_geodesic.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
@@ -32,10 +34,9 @@ constexpr int kUnroll = 8;
 constexpr int kCap = 3072;
 constexpr int kMaxChunks = kCap / 64;
 constexpr int kEarlySteps = 32;
-constexpr int kGroup = 2;
-constexpr int kRecentreGroups = 2;   // a step scanning more groups than this ...
+constexpr int kRecentreChunks = 4;  // a step scanning more chunks than this ...
 constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
-static_assert(kCap % (64 * kGroup) == 0, "shell groups tile the shell");
+static_assert(kCap % 64 == 0, "chunks of 64 tile the shell");
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
   return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
@@ -372,6 +373,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   bool stalled = false;
   int n_rescan = 0, n_global = 0;
   long long n_groups = 0;
+  int stage_groups = 0;
 
   while (true) {
     const float4 Cref = st_C;
@@ -570,157 +572,142 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       stalled = false;
     } else {
       // ---------------------------------------------------------- shell steps
-      // Wave 0 alone.  Entries sit in chunks of 64 in decreasing fine bins of
-      // d_ref.  Each lane keeps its own best (key, id, point) over a group of
-      // kGroup chunks, one wavefront reduction per group, and the scan stops
-      // once no later chunk can beat the best found.  The first two groups,
-      // which almost every step needs, stay in registers for the whole stage
-      // (lanes past the shell's end hold copies of entry 0, which change no
-      // argmax); later groups are read from LDS, the next one while this one
-      // is reduced.  When a step needs many groups the centre has drifted from
-      // C_ref: the stage ends and the next one rescans there.
+      // Wave 0 alone.  Entries sit in chunks of 64 (one entry per lane) in
+      // decreasing fine bins of d_ref.  Each lane keeps its own best (key,
+      // id, point), one wavefront reduction per step of the scan, and the
+      // scan stops once no later chunk can beat the best found.  The first
+      // two chunks, which almost every step needs, stay in registers for the
+      // whole stage (lanes past the shell's end hold copies of entry 0, which
+      // change no argmax); later chunks are read from LDS, the next one while
+      // this one is reduced.  When a step needs many chunks the centre has
+      // drifted from C_ref: the stage ends and the next one rescans there.
       //
       // A single wavefront issues about one instruction every few cycles
-      // whatever the dependences, so the common step (the first group
-      // suffices, one lane holds the maximum) is one straight path: 1/i comes
+      // whatever the dependences, so the common step (the first chunk, or the
+      // first two once one has often not sufficed in this stage, bounds all
+      // others and one lane holds the maximum) is one straight path: 1/i comes
       // from a per-lane table of the next 64 values, and the winners' ids are
       // collected one per lane and written 64 at a time.
       const int K = (int)sh_n;
       const float theta = st_theta;
       const float slack = 4e-6f * st_rref + 1e-30f;
       const int nchunks = (K + 63) / 64;
-      const int ngroups = (nchunks + kGroup - 1) / kGroup;
       if (wave == 0) {
-        float4 p0[kGroup], p1[kGroup];
-        int q0[kGroup], q1[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-          const int e0 = u * 64 + lane, e1 = (kGroup + u) * 64 + lane;
-          p0[u] = S.pt[e0 < K ? e0 : 0];
-          q0[u] = S.id[e0 < K ? e0 : 0];
-          p1[u] = S.pt[e1 < K ? e1 : 0];
-          q1[u] = S.id[e1 < K ? e1 : 0];
-        }
-        const float ub1 = ngroups > 1 ? S.chunk_ub[kGroup] : 0.f;
-        const float ub2 = ngroups > 2 ? S.chunk_ub[2 * kGroup] : 0.f;
-        // the one bound the common step checks: entries past the first group,
-        // else (one group) samples outside the shell, else none
-        const bool need_ub = ngroups > 1 || theta >= 0.f;
-        const float ubf = ngroups > 1 ? ub1 : theta;
+        const float4 p0 = S.pt[lane < K ? lane : 0], p1 = S.pt[64 + lane < K ? 64 + lane : 0];
+        const int q0 = S.id[lane < K ? lane : 0], q1 = S.id[64 + lane < K ? 64 + lane : 0];
+        const float ub1 = nchunks > 1 ? S.chunk_ub[1] : 0.f;
+        const float ub2 = nchunks > 2 ? S.chunk_ub[2] : 0.f;
+        // the one bound a common step checks: entries past the chunks it
+        // scanned, else samples outside the shell, else none
+        const bool need_ub1 = nchunks > 1 || theta >= 0.f, need_ub2 = nchunks > 2 || theta >= 0.f;
+        const float ubf1 = nchunks > 1 ? ub1 : theta, ubf2 = nchunks > 2 ? ub2 : theta;
         float4 C = Cref;
         int i = i0;
         int ib = i;                                 // first step of the block of 64
         float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
         int trv = 0;                                // winner of step ib + lane
-        while (i <= T) {
-          if (i - ib == 64) {
-            tr[2 * (ib - 1 + lane)] = trv;
-            ib = i;
-            inv_tab = 1.f / (float)(ib + lane);
-          }
-          const float inv = readlane_f(inv_tab, i - ib);
-          // bounds compared squared; the raw square root is within the slack
-          const float dC = __builtin_amdgcn_sqrtf(sqdist(C, Cref, chain));
-          auto beats = [&](float key, float ub) {
-            const float b = ub + dC + slack;
-            return key > b * b;
-          };
-          float bk, bp_x, bp_y, bp_z, bp_w;
-          int bi;
-          auto take_if = [&](bool take, float k, int q, float4 pp) {
-            bk = take ? k : bk;
-            bi = take ? q : bi;
-            bp_x = take ? pp.x : bp_x;
-            bp_y = take ? pp.y : bp_y;
-            bp_z = take ? pp.z : bp_z;
-            bp_w = take ? pp.w : bp_w;
-          };
-          auto scan = [&](const float4 *pp, const int *qq, int g, bool check) {
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-              // selects only (no control flow): every lane evaluates every entry
-              const float kk = sqdist(C, pp[u], chain);
-              const float k = (!check || (g * kGroup + u) * 64 + lane < K) ? kk : -1.f;
-              take_if((k > bk) | ((k == bk) & (qq[u] < bi)), k, qq[u], pp[u]);
+        int misses = 0;                             // one-chunk steps that needed more
+        // Steps of the stage with WIDTH chunks in the common step; returns
+        // true when one-chunk steps often needed more and the stage should go
+        // on with two.
+        auto run_steps = [&](auto width) -> bool {
+          constexpr int W = decltype(width)::value;
+          while (i <= T) {
+            if (i - ib == 64) {
+              tr[2 * (ib - 1 + lane)] = trv;
+              ib = i;
+              inv_tab = 1.f / (float)(ib + lane);
             }
-          };
-          // group 0 (entry 0 of each lane taken outright)
-          bk = sqdist(C, p0[0], chain);
-          bi = q0[0];
-          bp_x = p0[0].x;
-          bp_y = p0[0].y;
-          bp_z = p0[0].z;
-          bp_w = p0[0].w;
-#pragma unroll
-          for (int u = 1; u < kGroup; ++u) {
-            const float k = sqdist(C, p0[u], chain);
-            take_if((k > bk) | ((k == bk) & (q0[u] < bi)), k, q0[u], p0[u]);
-          }
-          float wk = wave_max_key(bk);
-          unsigned long long win = __ballot(bk == wk);
-          int g = 1;
-          if (!((!need_ub || beats(wk, ubf)) && __popcll(win) == 1)) {
-            // ------------------------------------------------ uncommon step
-            if (ngroups > 1 && !beats(wk, ub1)) {
-              scan(p1, q1, 1, false);
-              wk = wave_max_key(bk);
-              g = 2;
-              if (ngroups > 2 && !beats(wk, ub2)) {
-                float4 p[kGroup];
-                int q[kGroup];
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u) {
-                  p[u] = S.pt[(2 * kGroup + u) * 64 + lane];
-                  q[u] = S.id[(2 * kGroup + u) * 64 + lane];
-                }
+            const float inv = readlane_f(inv_tab, i - ib);
+            // bounds compared squared; the raw square root is within the slack.
+            // Rotation: |C + C_ref|^2 = 4 - |C - C_ref|^2 for unit quaternions
+            // (C stays near C_ref within a stage; the form only feeds bounds).
+            float dC2;
+            if (CHAIN == 0) {
+              const float e0 = C.x - Cref.x, e1 = C.y - Cref.y, e2 = C.z - Cref.z, e3 = C.w - Cref.w;
+              const float xc = fmaf(e3, e3, fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
+              dC2 = (2.f * xc) * (4.f - xc);
+            } else {
+              dC2 = sqdist(C, Cref, chain);
+            }
+            const float dC = __builtin_amdgcn_sqrtf(dC2);
+            auto beats = [&](float key, float ub) {
+              const float b = ub + dC + slack;
+              return key > b * b;
+            };
+            float bk = sqdist(C, p0, chain), bp_x = p0.x, bp_y = p0.y, bp_z = p0.z, bp_w = p0.w;
+            int bi = q0;
+            auto take = [&](float k, int q, float4 pp) {
+              const bool t = (k > bk) | ((k == bk) & (q < bi));
+              bk = t ? k : bk;
+              bi = t ? q : bi;
+              bp_x = t ? pp.x : bp_x;
+              bp_y = t ? pp.y : bp_y;
+              bp_z = t ? pp.z : bp_z;
+              bp_w = t ? pp.w : bp_w;
+            };
+            int g = W;  // chunks scanned
+            if (W == 2) take(sqdist(C, p1, chain), q1, p1);
+            float wk = wave_max_key(bk);
+            unsigned long long win = __ballot(bk == wk);
+            const bool bounded = W == 2 ? (!need_ub2 || beats(wk, ubf2)) : (!need_ub1 || beats(wk, ubf1));
+            if (!(bounded && __popcll(win) == 1)) {
+              // ---------------------------------------------- uncommon step
+              if (W == 1 && nchunks > 1 && !beats(wk, ub1)) {
+                take(sqdist(C, p1, chain), q1, p1);
+                wk = wave_max_key(bk);
+                g = 2;
+              }
+              if (g == 2 && nchunks > 2 && !beats(wk, ub2)) {
+                float4 p = S.pt[2 * 64 + lane];
+                int q = S.id[2 * 64 + lane];
                 while (true) {
-                  float4 np[kGroup];
-                  int nq[kGroup];
-                  const bool more = g + 1 < ngroups;
+                  float4 np;
+                  int nq;
+                  const bool more = g + 1 < nchunks;
                   if (more) {
-#pragma unroll
-                    for (int u = 0; u < kGroup; ++u) {
-                      const int e = ((g + 1) * kGroup + u) * 64 + lane;
-                      np[u] = S.pt[e];
-                      nq[u] = S.id[e];
-                    }
+                    np = S.pt[(g + 1) * 64 + lane];
+                    nq = S.id[(g + 1) * 64 + lane];
                   }
-                  scan(p, q, g, true);
+                  const float kk = sqdist(C, p, chain);
+                  take(g * 64 + lane < K ? kk : -1.f, q, p);
                   wk = wave_max_key(bk);
                   ++g;
-                  if (!more || beats(wk, S.chunk_ub[g * kGroup])) break;
-#pragma unroll
-                  for (int u = 0; u < kGroup; ++u) {
-                    p[u] = np[u];
-                    q[u] = nq[u];
-                  }
+                  if (!more || beats(wk, S.chunk_ub[g])) break;
+                  p = np;
+                  q = nq;
                 }
               }
+              if (theta >= 0.f && !beats(wk, theta)) {
+                stage_groups += g;
+                return false;  // the shell no longer suffices
+              }
+              // winner: the one lane holding the maximum key, else (a tie)
+              // the lowest sample id among the lanes that hold it
+              win = __ballot(bk == wk);
+              if (__popcll(win) > 1) {
+                const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
+                win = __ballot(bk == wk && bi == wmin);
+              }
             }
-            if (theta >= 0.f && !beats(wk, theta)) {
-              n_groups += g;
-              break;  // the shell no longer suffices
-            }
-            // winner: the one lane holding the maximum key, else (a tie) the
-            // lowest sample id among the lanes that hold it
-            win = __ballot(bk == wk);
-            if (__popcll(win) > 1) {
-              const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
-              win = __ballot(bk == wk && bi == wmin);
-            }
+            stage_groups += g;
+            const int wl = (int)__ffsll((long long)win) - 1;
+            const int wi = __builtin_amdgcn_readlane(bi, wl);
+            const float4 pt =
+                make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
+            C = geodesic_step_inv(C, pt, inv, i, chain);
+            trv = lane == i - ib ? wi : trv;
+            if (i > T - avg) accumulate_iterate(C, chain, acc);
+            ++i;
+            if (g > kRecentreChunks && i - i0 > kMinShellSteps) return false;  // re-centre the shell
+            if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return true;
           }
-          n_groups += g;
-          const int wl = (int)__ffsll((long long)win) - 1;
-          const int wi = __builtin_amdgcn_readlane(bi, wl);
-          const float4 pt =
-              make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
-          C = geodesic_step_inv(C, pt, inv, i, chain);
-          trv = lane == i - ib ? wi : trv;
-          if (i > T - avg) accumulate_iterate(C, chain, acc);
-          ++i;
-          if (g > kRecentreGroups && i - i0 > kMinShellSteps) break;  // re-centre the shell
-        }
+          return false;
+        };
+        if (run_steps(std::integral_constant<int, 1>())) run_steps(std::integral_constant<int, 2>());
         if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
+        n_groups += stage_groups;
+        stage_groups = 0;
         if (lane == 0) {
           st_C = C;
           st_i = i;
