@@ -56,7 +56,7 @@ def read_traffic(kernel, workload):
         return None
     from paper_2403_09990_amd.profile_summary import source_hash
     rec = json.load(open(path))
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 

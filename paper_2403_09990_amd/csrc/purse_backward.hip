@@ -1,14 +1,15 @@
 // Backward of purse_sample + purse_megb with every discrete decision held as
 // taken (argmax trace, feasibility and bisection outcomes, clamp sides).
 //
-// 1. k_bwd_megb (one workgroup per instance): the descent is replayed in
-//    float64 from the trace, keeping every ckpt_every-th rotation iterate;
-//    the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
+// 1. k_bwd_megb (one workgroup per instance): the descent is replayed from
+//    the trace with the forward's own float32 steps (so it is linearised at
+//    the iterates the forward computed), keeping every ckpt_every-th rotation
+//    iterate as a quaternion checkpoint; the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
 //    centre projection, the last-iterate average and the T geodesic steps
 //    onto the few samples the trace touches (the active set): the 3x3
-//    tangent Jacobians of the steps are formed in parallel, a chunk of steps
-//    at a time, each step recomputed from its checkpoint, and only their
-//    products run serially.
+//    tangent Jacobians of the steps are formed in float64 in parallel, a
+//    chunk of steps at a time, each step's iterate recomputed from its
+//    checkpoint, and only their products run serially.
 // 2. k_bwd_frame: per input direction, the tangent of the centre fit, pivot
 //    and anchor (the fit re-run in float64 dual numbers from its start).
 // 3. k_bwd_traj: per (active sample, input direction), the trajectory re-run

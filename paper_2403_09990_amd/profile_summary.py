@@ -4,6 +4,9 @@
         Markdown table of the per-kernel statistics (--kernel-trace --stats)
         found under DIR.
 
+    python -m paper_2403_09990_amd.profile_summary shapes DIR [--match NAME]
+        Per (kernel, workgroup size, grid size) statistics (rocpd database).
+
     python -m paper_2403_09990_amd.profile_summary counters DIR --kernel NAME
         Mean per dispatch of every counter of a --pmc run for one kernel.
 
@@ -12,8 +15,8 @@
         HBM bytes per dispatch of a kernel from two --pmc runs (FETCH_SIZE, then
         WRITE_SIZE, both in KiB per dispatch), each scaled by what the same
         counter reads for the calibration copy of B bytes (the largest copy
-        kernel of the run).  Stamped with the hash of the kernel sources so a
-        stale figure is not reported after the kernels change.
+        kernel of the run).  Stamped with the hash of the kernel's sources so a
+        stale figure is not reported after they change.
 """
 import argparse
 import csv
@@ -27,11 +30,24 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_hash() -> str:
+# Sources each profiled kernel is compiled from (the file that defines it and
+# every header it includes); other kernels: all of csrc/.
+_SAMPLER_SOURCES = ("csrc/purse_sample.hip", "csrc/purse_launch.hpp", "csrc/purse_traj.hpp", "csrc/purse_device.hpp",
+                    "csrc/purse_dual.hpp", "csrc/purse_layout.hpp", "../include/purse.h")
+KERNEL_SOURCES = {"k_sample": _SAMPLER_SOURCES, "k_sample2d_pair": _SAMPLER_SOURCES}
+
+
+def source_hash(kernel=None) -> str:
+    """Hash of the sources the kernel is built from, so that a traffic figure
+    is not reported once they have changed."""
     h = hashlib.sha256()
-    d = os.path.join(PKG, "csrc")
-    for f in sorted(os.listdir(d)):
-        h.update(open(os.path.join(d, f), "rb").read())
+    if kernel in KERNEL_SOURCES:
+        files = [os.path.normpath(os.path.join(PKG, f)) for f in KERNEL_SOURCES[kernel]]
+    else:
+        d = os.path.join(PKG, "csrc")
+        files = [os.path.join(d, f) for f in sorted(os.listdir(d))]
+    for f in files:
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -100,6 +116,23 @@ def stats(dirname, title=None, cmd=None):
     return "\n".join(out) + "\n"
 
 
+def shapes(dirname, match=None):
+    """Per (kernel, workgroup size, grid size) statistics from the rocpd
+    database: the autotuner's candidates and the timed launches of one kernel
+    show up as separate rows."""
+    q = ("select name, workgroup_x, grid_x, count(*) as n, avg(duration) as a, min(duration) as lo, "
+         "max(duration) as hi, vgpr_count, sgpr_count from kernels group by name, workgroup_x, grid_x")
+    rows = [r for r in _db_rows(dirname, q) if match is None or match in r["name"]]
+    rows.sort(key=lambda r: (r["name"], r["workgroup_x"]))
+    out = ["| kernel | workgroup | grid (threads) | calls | avg us | min us | max us | VGPRs | SGPRs |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| %s | %d | %d | %d | %.2f | %.2f | %.2f | %d | %d |" % (
+            _short(r["name"]), r["workgroup_x"], r["grid_x"], r["n"], r["a"] / 1e3, r["lo"] / 1e3, r["hi"] / 1e3,
+            r["vgpr_count"], r["sgpr_count"]))
+    return "\n".join(out) + "\n"
+
+
 def _per_dispatch(dirname, counter):
     """[(kernel name, value)] of one counter, one entry per dispatch (values
     of the counter's instances summed)."""
@@ -141,7 +174,7 @@ def _mean_for(disp, pred):
 
 
 def traffic(fetch_dir, write_dir, kernel, copy_bytes, out, cmd_fetch=None, cmd_write=None):
-    res = {"kernel": kernel, "copy_bytes": copy_bytes, "source_hash": source_hash(),
+    res = {"kernel": kernel, "copy_bytes": copy_bytes, "source_hash": source_hash(kernel),
            "cmd_fetch": cmd_fetch, "cmd_write": cmd_write}
     total = 0.0
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
@@ -169,6 +202,9 @@ def main(argv=None):
     a.add_argument("--title")
     a.add_argument("--cmd")
     a.add_argument("--out")
+    sh = sub.add_parser("shapes")
+    sh.add_argument("dir")
+    sh.add_argument("--match")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
@@ -181,6 +217,9 @@ def main(argv=None):
     b.add_argument("--cmd-fetch")
     b.add_argument("--cmd-write")
     args = ap.parse_args(argv)
+    if args.mode == "shapes":
+        sys.stdout.write(shapes(args.dir, args.match))
+        return
     if args.mode == "counters":
         print(json.dumps(counters(args.dir, args.kernel), indent=1))
         return
