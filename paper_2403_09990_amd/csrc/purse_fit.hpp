@@ -81,12 +81,21 @@ __device__ inline bool dlt_2d(const float *Z, const float *z, int n, const float
   if (!chol12(L)) return false;
   double v[12];
   for (int a = 0; a < 12; ++a) v[a] = 1.0 + 0.01 * a;
+  // until the unit iterate moves by less than 1e-14 (a start for the
+  // Gauss-Newton fit, which converges from it), at most 80 solves
   for (int it = 0; it < 80; ++it) {
+    double u[12];
+    for (int a = 0; a < 12; ++a) u[a] = v[a];
     chol12_solve(L, v);
     double nn = 0;
     for (int a = 0; a < 12; ++a) nn += v[a] * v[a];
     nn = 1.0 / sqrt(nn);
-    for (int a = 0; a < 12; ++a) v[a] *= nn;
+    double dv = 0;
+    for (int a = 0; a < 12; ++a) {
+      v[a] *= nn;
+      dv = fmax(dv, fabs(v[a] - u[a]));
+    }
+    if (it >= 2 && dv <= 1e-14) break;
   }
   // undo the model normalisation: P = P' [[I/sc, -zb/sc], [0, 1]]
   double P[12];
@@ -254,9 +263,24 @@ struct ObsPlain {
   }
 };
 
+// Observations with the whitening factors computed once (3 doubles per
+// keypoint, e.g. in LDS): the same values ObsPlain computes on every call.
+struct ObsCached {
+  const float *z;
+  const double *w;
+  __device__ void operator()(int i, double zz[2], double ww[3]) const {
+    zz[0] = z[3 * i];
+    zz[1] = z[3 * i + 1];
+    ww[0] = w[3 * i];
+    ww[1] = w[3 * i + 1];
+    ww[2] = w[3 * i + 2];
+  }
+};
+
 // Weighted cost sum ||z_i - Pi(R Z_i + t)||^2_Lambda_i of a 2D-3D pose.
-__device__ inline double cost_2d(const float *Z, const float *z, const float *shapes, int n, const float K[4],
-                          const double R[9], const double t[3]) {
+template <typename OBS>
+__device__ inline double cost_2d_obs(const float *Z, const OBS &obs, int n, const float K[4], const double R[9],
+                                     const double t[3]) {
   double c = 0;
   for (int i = 0; i < n; ++i) {
     double m[3] = {Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]}, P[3];
@@ -264,13 +288,18 @@ __device__ inline double cost_2d(const float *Z, const float *z, const float *sh
     for (int r = 0; r < 3; ++r) P[r] += t[r];
     double iz = 1.0 / P[2];
     double u = (double)K[0] * (P[0] * iz) + K[2], v = (double)K[1] * (P[1] * iz) + K[3];
-    double w[3];
-    whiten_factor<double>(shapes + 4 * i, w);
-    double r0 = (double)z[3 * i] - u, r1 = (double)z[3 * i + 1] - v;
+    double zz[2], w[3];
+    obs(i, zz, w);
+    double r0 = zz[0] - u, r1 = zz[1] - v;
     double a = w[0] * r0 + w[1] * r1, b = w[2] * r1;
     c += a * a + b * b;
   }
   return c;
+}
+
+__device__ inline double cost_2d(const float *Z, const float *z, const float *shapes, int n, const float K[4],
+                                 const double R[9], const double t[3]) {
+  return cost_2d_obs(Z, ObsPlain{z, shapes}, n, K, R, t);
 }
 
 // Arun's method in float64: R = proj_SO3(sum (b_i - bbar)(a_i - abar)^T).

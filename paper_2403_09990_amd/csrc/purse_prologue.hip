@@ -1,108 +1,140 @@
 // Per-instance prologue: validation, keypoint records, centre fit (float64),
-// pivot and feasible anchor.  One wavefront per instance; the fit is serial
-// in lane 0 (it is a few thousand float64 operations per instance).
+// pivot and feasible anchor.  Two wavefronts per instance: the 2D-3D centre
+// fit is a serial float64 Gauss-Newton iteration from two starts, one start
+// per wavefront (lane 0 of each), so the two run on different SIMDs at once;
+// everything else is serial in lane 0 of wavefront 0.
 #include "purse_fit.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
 
 namespace purse {
 
-__global__ void __launch_bounds__(64) k_prologue(DevBatch b, DevParams p, InstRec *inst, KpRec *kprec,
-                                                 int32_t *inst_status) {
+constexpr int kPrologueBlock = 128;
+
+__global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevParams p, InstRec *inst, KpRec *kprec,
+                                                             int32_t *inst_status) {
   const int j = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  InstRec I;
-  I.kind = b.kind[j];
-  I.n_kp = b.n_kp[j];
-  I.kp_off = b.kp_off[j];
-  int64_t soff, sM;
-  sample_range(b.sample_off, j, b.total_samples, b.max_samples, soff, sM);
-  I.sample_off = soff;
-  I.n_samples = sM;
-  const bool kp_ok = I.kp_off >= 0 && b.kp_off[j + 1] - I.kp_off == (int64_t)I.n_kp &&
-                     b.kp_off[j + 1] <= b.total_kp;
-  I.seed = b.seed[j];
-  I.has_anchor = 0;
-  I.status = PURSE_INST_OK;
-  for (int k = 0; k < 4; ++k) I.K[k] = (I.kind == PURSE_KIND_2D3D) ? b.intrinsics[4 * j + k] : 0.f;
-  for (int k = 0; k < 9; ++k) I.Rc[k] = I.Ra[k] = (k % 4 == 0) ? 1.f : 0.f;
-  for (int k = 0; k < 3; ++k) I.tc[k] = I.ta[k] = I.oc[k] = I.abar[k] = 0.f;
-  I.pad[0] = I.pad[1] = 0.f;
-  const int n = I.n_kp;
-  const bool is2d = I.kind == PURSE_KIND_2D3D;
-  const int64_t ko = kp_ok ? I.kp_off : 0;
-  const float *a = b.model_pts + 3 * ko;
-  const float *c = b.centres + 3 * ko;
-  const float *L = b.shapes + 4 * ko;
-  const float *beta = b.bounds + ko;
-  // ---- validation
-  if ((I.kind != PURSE_KIND_3D3D && !is2d) || !kp_ok || n < (is2d ? 6 : 3) || n > PURSE_MAX_KP ||
-      I.n_samples < 1 || n > b.max_kp) {
-    I.status = PURSE_INST_BAD_SIZE;
-  } else {
-    bool good = true;
-    for (int i = 0; i < n && good; ++i) {
-      for (int r = 0; r < 3; ++r) good = good && finite_f(a[3 * i + r]);
-      good = good && finite_f(c[3 * i]) && finite_f(c[3 * i + 1]) && (is2d || finite_f(c[3 * i + 2]));
-      good = good && finite_f(beta[i]) && beta[i] >= 0.f;
-      if (is2d) {
-        const float *l = L + 4 * i;
-        good = good && finite_f(l[0]) && finite_f(l[1]) && finite_f(l[2]) && finite_f(l[3]);
-        good = good && l[1] == l[2] && l[0] > 0.f && (double)l[0] * l[3] - (double)l[1] * l[2] > 0.0;
+  const int tid = threadIdx.x;
+  __shared__ double w_s[3 * PURSE_MAX_KP];  // whitening factors of the keypoints
+  __shared__ double fit_R[2][9], fit_t[2][3], fit_cost[2];
+  __shared__ int fit_good[2], stage;         // stage: 0 invalid, 1 valid 3D-3D, 2 valid 2D-3D
+  InstRec I;                                 // (lane 0 of wavefront 0)
+  double ab[3] = {0, 0, 0};
+  if (tid == 0) {
+    I.kind = b.kind[j];
+    I.n_kp = b.n_kp[j];
+    I.kp_off = b.kp_off[j];
+    int64_t soff, sM;
+    sample_range(b.sample_off, j, b.total_samples, b.max_samples, soff, sM);
+    I.sample_off = soff;
+    I.n_samples = sM;
+    const bool kp_ok = I.kp_off >= 0 && b.kp_off[j + 1] - I.kp_off == (int64_t)I.n_kp &&
+                       b.kp_off[j + 1] <= b.total_kp;
+    I.seed = b.seed[j];
+    I.has_anchor = 0;
+    I.status = PURSE_INST_OK;
+    for (int k = 0; k < 4; ++k) I.K[k] = (I.kind == PURSE_KIND_2D3D) ? b.intrinsics[4 * j + k] : 0.f;
+    for (int k = 0; k < 9; ++k) I.Rc[k] = I.Ra[k] = (k % 4 == 0) ? 1.f : 0.f;
+    for (int k = 0; k < 3; ++k) I.tc[k] = I.ta[k] = I.oc[k] = I.abar[k] = 0.f;
+    I.pad[0] = I.pad[1] = 0.f;
+    const int n = I.n_kp;
+    const bool is2d = I.kind == PURSE_KIND_2D3D;
+    const int64_t ko = kp_ok ? I.kp_off : 0;
+    const float *a = b.model_pts + 3 * ko;
+    const float *c = b.centres + 3 * ko;
+    const float *L = b.shapes + 4 * ko;
+    const float *beta = b.bounds + ko;
+    // ---- validation
+    if ((I.kind != PURSE_KIND_3D3D && !is2d) || !kp_ok || n < (is2d ? 6 : 3) || n > PURSE_MAX_KP ||
+        I.n_samples < 1 || n > b.max_kp) {
+      I.status = PURSE_INST_BAD_SIZE;
+    } else {
+      bool good = true;
+      for (int i = 0; i < n && good; ++i) {
+        for (int r = 0; r < 3; ++r) good = good && finite_f(a[3 * i + r]);
+        good = good && finite_f(c[3 * i]) && finite_f(c[3 * i + 1]) && (is2d || finite_f(c[3 * i + 2]));
+        good = good && finite_f(beta[i]) && beta[i] >= 0.f;
+        if (is2d) {
+          const float *l = L + 4 * i;
+          good = good && finite_f(l[0]) && finite_f(l[1]) && finite_f(l[2]) && finite_f(l[3]);
+          good = good && l[1] == l[2] && l[0] > 0.f && (double)l[0] * l[3] - (double)l[1] * l[2] > 0.0;
+        }
+      }
+      if (is2d)
+        for (int k = 0; k < 4; ++k) good = good && finite_f(I.K[k]);
+      if (is2d) good = good && I.K[0] > 0.f && I.K[1] > 0.f;
+      if (!good) I.status = PURSE_INST_BAD_SHAPE;
+    }
+    if (I.status == PURSE_INST_OK) {
+      // ---- keypoint records (and the whitening factors of the fit)
+      for (int i = 0; i < n; ++i)
+        for (int r = 0; r < 3; ++r) ab[r] += a[3 * i + r];
+      for (int r = 0; r < 3; ++r) ab[r] /= n;
+      for (int r = 0; r < 3; ++r) I.abar[r] = (float)ab[r];
+      const float tau = is2d ? p.tau2 : p.tau3;
+      KpRec *kp = kprec + I.kp_off;
+      for (int i = 0; i < n; ++i) {
+        KpRec k;
+        for (int r = 0; r < 3; ++r) {
+          k.m[r] = is2d ? a[3 * i + r] : (float)((double)a[3 * i + r] - ab[r]);
+          k.c[r] = (r < 2 || !is2d) ? c[3 * i + r] : 0.f;
+          k.w[r] = 0.f;
+        }
+        if (is2d) {
+          double *w = w_s + 3 * i;
+          whiten_factor<double>(L + 4 * i, w);
+          for (int r = 0; r < 3; ++r) k.w[r] = (float)w[r];
+        }
+        k.kb = (float)((double)p.kappa * beta[i]);
+        k.kb2 = k.kb * k.kb;
+        k.bt = (float)((double)beta[i] + tau);
+        kp[i] = k;
       }
     }
-    if (is2d)
-      for (int k = 0; k < 4; ++k) good = good && finite_f(I.K[k]);
-    if (is2d) good = good && I.K[0] > 0.f && I.K[1] > 0.f;
-    if (!good) I.status = PURSE_INST_BAD_SHAPE;
+    stage = I.status != PURSE_INST_OK ? 0 : (is2d ? 2 : 1);
   }
-  if (I.status != PURSE_INST_OK) {
+  __syncthreads();
+  const int st = stage;
+  if (st == 2 && (tid == 0 || tid == 64)) {
+    // Gauss-Newton from the DLT (wavefront 0) and from the weak-perspective
+    // fit (wavefront 1)
+    const int f = tid >> 6;
+    const int n = b.n_kp[j];
+    const int64_t ko = b.kp_off[j];
+    const float *a = b.model_pts + 3 * ko, *c = b.centres + 3 * ko;
+    const float K[4] = {b.intrinsics[4 * j], b.intrinsics[4 * j + 1], b.intrinsics[4 * j + 2], b.intrinsics[4 * j + 3]};
+    const ObsCached obs{c, w_s};
+    double R[9], t[3];
+    bool ok = f == 0 ? dlt_2d(a, c, n, K, R, t) : affine_2d(a, c, n, K, R, t);
+    if (ok) ok = gn_centre_2d<double>(a, obs, n, K, p.centre_gn, (double)p.z_min, R, t);
+    fit_good[f] = ok;
+    if (ok) {
+      for (int k = 0; k < 9; ++k) fit_R[f][k] = R[k];
+      for (int k = 0; k < 3; ++k) fit_t[f][k] = t[k];
+      fit_cost[f] = cost_2d_obs(a, obs, n, K, R, t);
+    }
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  if (st == 0) {
     inst[j] = I;
     inst_status[j] = I.status;
     return;
   }
-  // ---- keypoint records
-  double ab[3] = {0, 0, 0};
-  for (int i = 0; i < n; ++i)
-    for (int r = 0; r < 3; ++r) ab[r] += a[3 * i + r];
-  for (int r = 0; r < 3; ++r) ab[r] /= n;
-  for (int r = 0; r < 3; ++r) I.abar[r] = (float)ab[r];
-  const float tau = is2d ? p.tau2 : p.tau3;
+  const int n = I.n_kp;
+  const bool is2d = st == 2;
+  const float *a = b.model_pts + 3 * I.kp_off;
+  const float *c = b.centres + 3 * I.kp_off;
   KpRec *kp = kprec + I.kp_off;
-  for (int i = 0; i < n; ++i) {
-    KpRec k;
-    for (int r = 0; r < 3; ++r) {
-      k.m[r] = is2d ? a[3 * i + r] : (float)((double)a[3 * i + r] - ab[r]);
-      k.c[r] = (r < 2 || !is2d) ? c[3 * i + r] : 0.f;
-      k.w[r] = 0.f;
-    }
-    if (is2d) {
-      double w[3];
-      whiten_factor<double>(L + 4 * i, w);
-      for (int r = 0; r < 3; ++r) k.w[r] = (float)w[r];
-    }
-    k.kb = (float)((double)p.kappa * beta[i]);
-    k.kb2 = k.kb * k.kb;
-    k.bt = (float)((double)beta[i] + tau);
-    kp[i] = k;
-  }
-  // ---- centre fit
+  // ---- centre fit: the successful fit with the lower cost (ties: the DLT one)
   double Rd[9], td[3];
   bool fit_ok = true;
   if (is2d) {
-    // Gauss-Newton from the DLT and from the weak-perspective fit; the
-    // successful fit with the lower cost is kept (ties: the DLT one)
-    double Ra_[9], ta_[3];
-    const ObsPlain obs{c, L};
-    bool ok1 = dlt_2d(a, c, n, I.K, Rd, td);
-    if (ok1) ok1 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, Rd, td);
-    bool ok2 = affine_2d(a, c, n, I.K, Ra_, ta_);
-    if (ok2) ok2 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, Ra_, ta_);
-    if (ok2 && (!ok1 || cost_2d(a, c, L, n, I.K, Ra_, ta_) < cost_2d(a, c, L, n, I.K, Rd, td))) {
-      for (int k = 0; k < 9; ++k) Rd[k] = Ra_[k];
-      for (int k = 0; k < 3; ++k) td[k] = ta_[k];
-    }
+    const bool ok1 = fit_good[0] != 0, ok2 = fit_good[1] != 0;
+    const int f = (ok2 && (!ok1 || fit_cost[1] < fit_cost[0])) ? 1 : 0;
     fit_ok = ok1 || ok2;
+    for (int k = 0; k < 9; ++k) Rd[k] = fit_ok ? fit_R[f][k] : (k % 4 == 0 ? 1.0 : 0.0);
+    for (int k = 0; k < 3; ++k) td[k] = fit_ok ? fit_t[f][k] : 0.0;
   } else {
     kabsch_centre(a, c, n, Rd, td);
   }
@@ -153,7 +185,7 @@ __global__ void __launch_bounds__(64) k_prologue(DevBatch b, DevParams p, InstRe
 
 void launch_prologue(const DevBatch &b, const DevParams &p, InstRec *inst, KpRec *kp, int32_t *inst_status,
                      hipStream_t stream) {
-  hipLaunchKernelGGL(k_prologue, dim3(b.n_inst), dim3(64), 0, stream, b, p, inst, kp, inst_status);
+  hipLaunchKernelGGL(k_prologue, dim3(b.n_inst), dim3(kPrologueBlock), 0, stream, b, p, inst, kp, inst_status);
 }
 
 }  // namespace purse
