@@ -47,20 +47,18 @@ __device__ __forceinline__ void sincos_small(float x, float &s, float &c) {
   c = fmaf(pc, z, 1.f);
 }
 
-// atan w for 0 <= w <= tan(pi/8): the odd Taylor series through w^19
-// (truncation below 5e-10 there).
+// atan w for 0 <= w <= tan(pi/8): w + w^3 P(w^2), P of degree 4 fitted to
+// (atan w - w) / w^3 by Lawson's iteratively reweighted least squares toward
+// the minimax fit (paper_2403_09990_amd/fit_series.py): error below 2e-10
+// in exact arithmetic, at the float32 rounding level when evaluated here.
 __device__ __forceinline__ float atan_eighth(float w) {
   const float z = w * w;
-  float p = 1.f / 19.f;
-  p = fmaf(p, z, -1.f / 17.f);
-  p = fmaf(p, z, 1.f / 15.f);
-  p = fmaf(p, z, -1.f / 13.f);
-  p = fmaf(p, z, 1.f / 11.f);
-  p = fmaf(p, z, -1.f / 9.f);
-  p = fmaf(p, z, 1.f / 7.f);
-  p = fmaf(p, z, -1.f / 5.f);
-  p = fmaf(p, z, 1.f / 3.f);
-  return fmaf(-w, p * z, w);
+  float p = -5.945400894e-02f;
+  p = fmaf(p, z, 1.053481475e-01f);
+  p = fmaf(p, z, -1.423431039e-01f);
+  p = fmaf(p, z, 1.999788284e-01f);
+  p = fmaf(p, z, -3.333330154e-01f);
+  return fmaf(w, p * z, w);
 }
 
 // C <- C Exp(Log(C^T R_s) / i) (rotation), c <- c + (t_s - c) / i (translation).

@@ -607,12 +607,15 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
         int trv = 0;                                // winner of step ib + lane
         int misses = 0;                             // one-chunk steps that needed more
-        // Steps of the stage with WIDTH chunks in the common step; returns
-        // true when one-chunk steps often needed more and the stage should go
-        // on with two.
-        auto run_steps = [&](auto width) -> bool {
+        // Steps of the stage up to step `end` with WIDTH chunks in the common
+        // step and (SHORT) the short sin/cos series of the geodesic step;
+        // returns kStageEnds, kGoWide when one-chunk steps often needed more
+        // and the stage should go on with two, or kRangeDone at `end`.
+        constexpr int kStageEnds = 0, kGoWide = 1, kRangeDone = 2;
+        auto run_steps = [&](auto width, auto short_series, int end) -> int {
           constexpr int W = decltype(width)::value;
-          while (i <= T) {
+          constexpr bool SHORT = decltype(short_series)::value;
+          while (i <= end) {
             if (i - ib == 64) {
               tr[2 * (ib - 1 + lane)] = trv;
               ib = i;
@@ -680,7 +683,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               }
               if (theta >= 0.f && !beats(wk, theta)) {
                 stage_groups += g;
-                return false;  // the shell no longer suffices
+                return kStageEnds;  // the shell no longer suffices
               }
               // winner: the one lane holding the maximum key, else (a tie)
               // the lowest sample id among the lanes that hold it
@@ -695,16 +698,30 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             const int wi = __builtin_amdgcn_readlane(bi, wl);
             const float4 pt =
                 make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
-            C = geodesic_step_inv(C, pt, inv, i, chain);
+            C = geodesic_step_inv<SHORT>(C, pt, inv, chain);
             trv = lane == i - ib ? wi : trv;
             if (i > T - avg) accumulate_iterate(C, chain, acc);
             ++i;
-            if (g > kRecentreChunks && i - i0 > kMinShellSteps) return false;  // re-centre the shell
-            if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return true;
+            if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
+            if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
           }
-          return false;
+          return kRangeDone;
         };
-        if (run_steps(std::integral_constant<int, 1>())) run_steps(std::integral_constant<int, 2>());
+        // steps before kShortSeriesStep, then the rest: no per-step choice
+        // of the series
+        bool wide = false, ended = false;
+        auto run_range = [&](auto short_series, int end) {
+          if (ended || i > end) return;
+          int r = wide ? run_steps(std::integral_constant<int, 2>(), short_series, end)
+                       : run_steps(std::integral_constant<int, 1>(), short_series, end);
+          if (r == kGoWide) {
+            wide = true;
+            r = run_steps(std::integral_constant<int, 2>(), short_series, end);
+          }
+          ended = r == kStageEnds;
+        };
+        run_range(std::false_type(), min(T, kShortSeriesStep - 1));
+        run_range(std::true_type(), T);
         if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
         n_groups += stage_groups;
         stage_groups = 0;
