@@ -612,9 +612,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         // returns kStageEnds, kGoWide when one-chunk steps often needed more
         // and the stage should go on with two, or kRangeDone at `end`.
         constexpr int kStageEnds = 0, kGoWide = 1, kRangeDone = 2;
-        auto run_steps = [&](auto width, auto short_series, int end) -> int {
+        auto run_steps = [&](auto width, auto short_series, auto accumulate, int end) -> int {
           constexpr int W = decltype(width)::value;
           constexpr bool SHORT = decltype(short_series)::value;
+          constexpr bool ACC = decltype(accumulate)::value;  // within the last avg steps
           while (i <= end) {
             if (i - ib == 64) {
               tr[2 * (ib - 1 + lane)] = trv;
@@ -700,28 +701,33 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
             C = geodesic_step_inv<SHORT>(C, pt, inv, chain);
             trv = lane == i - ib ? wi : trv;
-            if (i > T - avg) accumulate_iterate(C, chain, acc);
+            if (ACC) accumulate_iterate(C, chain, acc);
             ++i;
             if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
             if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
           }
           return kRangeDone;
         };
-        // steps before kShortSeriesStep, then the rest: no per-step choice
-        // of the series
+        // Ranges of steps with no per-step choice of the sin/cos series or of
+        // accumulating the iterate: before kShortSeriesStep, then the rest,
+        // each split at the last avg steps.
         bool wide = false, ended = false;
-        auto run_range = [&](auto short_series, int end) {
+        auto run_range = [&](auto short_series, auto accumulate, int end) {
           if (ended || i > end) return;
-          int r = wide ? run_steps(std::integral_constant<int, 2>(), short_series, end)
-                       : run_steps(std::integral_constant<int, 1>(), short_series, end);
+          int r = wide ? run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end)
+                       : run_steps(std::integral_constant<int, 1>(), short_series, accumulate, end);
           if (r == kGoWide) {
             wide = true;
-            r = run_steps(std::integral_constant<int, 2>(), short_series, end);
+            r = run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end);
           }
           ended = r == kStageEnds;
         };
-        run_range(std::false_type(), min(T, kShortSeriesStep - 1));
-        run_range(std::true_type(), T);
+        const int last_plain = T - avg;  // steps after this one accumulate their iterate
+        const int long_end = min(T, kShortSeriesStep - 1);
+        run_range(std::false_type(), std::false_type(), min(long_end, last_plain));
+        run_range(std::false_type(), std::true_type(), long_end);
+        run_range(std::true_type(), std::false_type(), last_plain);
+        run_range(std::true_type(), std::true_type(), T);
         if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
         n_groups += stage_groups;
         stage_groups = 0;
