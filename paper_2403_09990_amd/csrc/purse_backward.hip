@@ -137,7 +137,12 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __shared__ float4 qact[kMaxActive];          // their rotations as quaternions
   __shared__ uint8_t tslot[2 * kLdsTrace];     // trace as active-set slots
   __shared__ double jac[kBwdBlock][2][9];      // J_C, J_R of the steps of one chunk
-  __shared__ double jadd[kBwdBlock][3];        // averaged-iterate terms of those steps
+  __shared__ double jadd[kBwdBlock][3];        // averaged-iterate terms of those steps, then rho terms
+  __shared__ double gstep[kBwdBlock][3];       // g at each step of the chunk
+  __shared__ int cslot[kBwdBlock];             // active slot of each step of the chunk (rotation)
+  __shared__ int tslot_c[kBwdBlock];           // and of its translation winner
+  __shared__ double twt[kBwdBlock];            // translation weight of each step of the chunk
+  __shared__ double tbar[3];                   // cotangent of t*
   __shared__ double rho[kMaxActive][3];        // tangent cotangents of active rotations
   __shared__ double Sbar_s[9], gvec[3];
   __shared__ double Rstar[9], tstar[3], Ssum[9];
@@ -152,19 +157,25 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   sample_range(b.sample_off, j, b.total_samples, b.max_samples, off, M64);
   const int M = (int)M64;
   BwdRec *rec = recs + j;
-  // ---- first feasible sample
-  int first = INT32_MAX;
-  for (int s = tid; s < M; s += kBwdBlock)
-    if (mask[off + s] & PURSE_MASK_FEASIBLE) first = min(first, s);
-  for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
-  if (lane == 0) red_i[wave] = first;
+  // ---- first feasible sample: rounds of 8 masks per thread (loads issued
+  // together), stopping at the first round that holds one
+  if (tid == 0) s0_s = INT32_MAX;
   __syncthreads();
-  if (tid == 0) {
-    int f = INT32_MAX;
-    for (int w = 0; w < kBwdWaves; ++w) f = min(f, red_i[w]);
-    s0_s = f;
+  for (int r0 = 0; r0 < M; r0 += 8 * kBwdBlock) {
+    uint8_t m8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m8[u] = mask[off + min(r0 + u * kBwdBlock + tid, M - 1)];
+    int first = INT32_MAX;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = r0 + u * kBwdBlock + tid;
+      if (s < M && (m8[u] & PURSE_MASK_FEASIBLE)) first = min(first, s);
+    }
+    for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
+    if (lane == 0 && first != INT32_MAX) atomicMin(&s0_s, first);
+    __syncthreads();
+    if (s0_s != INT32_MAX) break;
   }
-  __syncthreads();
   const int s0 = s0_s;
   if (s0 == INT32_MAX) {
     if (tid == 0) {
@@ -234,74 +245,134 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   auto load_act = [&](int a, D R[9]) {
     for (int q = 0; q < 9; ++q) R[q] = (D)pact[a][q];
   };
-  // ---- replay the descent (thread 0: rotation, thread 64: translation).
-  // The rotation chain repeats the forward's float32 quaternion steps, so the
-  // backward linearises at the iterates the forward computed; every ck-th
-  // iterate is kept as a checkpoint.
+  // ---- replay the descent (wavefront 0: rotation, wavefront 1: translation;
+  // every lane of a wavefront runs the same steps, so 1/i comes from a
+  // per-lane table of the next 64 values).  The rotation chain repeats the
+  // forward's float32 quaternion steps, so the backward linearises at the
+  // iterates the forward computed; every ck-th iterate is kept as a
+  // checkpoint.
   float *ckq = reinterpret_cast<float *>(ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9);
-  if (tid == 0 && !overflow_s) {
+  if (wave == 0 && !overflow_s) {
     float4 C = qact[find_active(act, n_act_s, s0)];
-    float4 Bn = qact[slot_of(0)];  // sample of the next step, read one step ahead
     D S[9];
     for (int k = 0; k < 9; ++k) S[k] = 0;
+    // per lane, 1/i and the sample quaternion of step ib + lane
+    int ib = 1, kc = 0, q = 0;
+    float inv_tab = 1.f / (float)(ib + lane);
+    float4 B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
     for (int i = 1; i <= T; ++i) {
-      const float4 B = Bn;
-      if (i < T) Bn = qact[slot_of(2 * i)];
-      if ((i - 1) % ck == 0) {
-        float *c = ckq + 4 * ((i - 1) / ck);
-        c[0] = C.x;
-        c[1] = C.y;
-        c[2] = C.z;
-        c[3] = C.w;
+      if (i - ib == 64) {
+        ib = i;
+        inv_tab = 1.f / (float)(ib + lane);
+        B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
       }
-      C = geodesic_step(C, B, i, 0);
+      const int l = i - ib;
+      const float inv = readlane_f(inv_tab, l);
+      const float4 B = make_float4(readlane_f(B_tab.x, l), readlane_f(B_tab.y, l), readlane_f(B_tab.z, l),
+                                   readlane_f(B_tab.w, l));
+      if (kc == 0) {  // (i - 1) % ck == 0
+        if (lane == 0) {
+          float *c = ckq + 4 * q;
+          c[0] = C.x;
+          c[1] = C.y;
+          c[2] = C.z;
+          c[3] = C.w;
+        }
+        ++q;
+        kc = ck;
+      }
+      --kc;
+      C = geodesic_step_inv(C, B, inv, i, 0);
       if (i > T - avg) {
         D Cm[9];
         rot_of_quat_d(C, Cm);
         for (int k = 0; k < 9; ++k) S[k] += Cm[k];
       }
     }
-    D Rs[9];
-    polar_so3<D>(S, Rs, 12);
-    for (int k = 0; k < 9; ++k) {
-      Rstar[k] = Rs[k];
-      Ssum[k] = S[k];
+    if (lane == 0) {
+      D Rs[9];
+      polar_so3<D>(S, Rs, 12);
+      for (int k = 0; k < 9; ++k) {
+        Rstar[k] = Rs[k];
+        Ssum[k] = S[k];
+      }
     }
-  } else if (tid == 64 && !overflow_s) {
+  } else if (wave == 1 && !overflow_s) {
     D c[3], acc[3] = {0, 0, 0};
     for (int r = 0; r < 3; ++r) c[r] = poses[12 * (off + s0) + 9 + r];
+    // per lane, 1/i and the sample translation of step ib + lane
+    int ib = 1;
+    D inv_tab = 1.0 / (D)(ib + lane);
+    const float *Pt = pact[slot_of(2 * min(ib - 1 + lane, T - 1) + 1)];
+    float t_tab[3] = {Pt[9], Pt[10], Pt[11]};
     for (int i = 1; i <= T; ++i) {
-      const float *P = pact[slot_of(2 * (i - 1) + 1)];
-      const D inv = 1.0 / (D)i;
+      if (i - ib == 64) {
+        ib = i;
+        inv_tab = 1.0 / (D)(ib + lane);
+        const float *Pn = pact[slot_of(2 * min(ib - 1 + lane, T - 1) + 1)];
+        for (int r = 0; r < 3; ++r) t_tab[r] = Pn[9 + r];
+      }
+      const int l = i - ib;
+      const long long ib64 = __double_as_longlong(inv_tab);
+      const int lo = __builtin_amdgcn_readlane((int)(ib64 & 0xffffffff), l);
+      const int hi = __builtin_amdgcn_readlane((int)(ib64 >> 32), l);
+      const D inv = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+      const float P[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, readlane_f(t_tab[0], l), readlane_f(t_tab[1], l),
+                           readlane_f(t_tab[2], l)};
       for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) * inv;
       if (i > T - avg)
         for (int r = 0; r < 3; ++r) acc[r] += c[r];
     }
-    for (int r = 0; r < 3; ++r) tstar[r] = acc[r] / avg;
+    if (lane == 0)
+      for (int r = 0; r < 3; ++r) tstar[r] = acc[r] / avg;
   }
   __syncthreads();
   // ---- samples realising the radii about (R*, t*)
   D br = -1, bt = -1;
   int ir = INT32_MAX, it = INT32_MAX;
-  for (int s = tid; s < M; s += kBwdBlock) {
-    if (!(mask[off + s] & PURSE_MASK_FEASIBLE)) continue;
-    const float *P = poses + 12 * (off + s);
-    D fr = 0, ft = 0;
-    for (int k = 0; k < 9; ++k) {
-      D d = Rstar[k] - (D)P[k];
-      fr += d * d;
-    }
-    for (int k = 0; k < 3; ++k) {
-      D d = tstar[k] - (D)P[9 + k];
-      ft += d * d;
-    }
-    if (fr > br || (fr == br && s < ir)) {
-      br = fr;
-      ir = s;
-    }
-    if (ft > bt || (ft == bt && s < it)) {
-      bt = ft;
-      it = s;
+  {
+    // 4 samples per thread and round, their loads issued together
+    constexpr int U = 4;
+    D Rs[9], ts[3];
+    for (int k = 0; k < 9; ++k) Rs[k] = Rstar[k];
+    for (int k = 0; k < 3; ++k) ts[k] = tstar[k];
+    for (int r0 = 0; r0 < M; r0 += U * kBwdBlock) {
+      float4 q[U][3];
+      uint8_t m4[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int s = min(r0 + u * kBwdBlock + tid, M - 1);
+        const float4 *P = reinterpret_cast<const float4 *>(poses + 12 * (off + s));
+        q[u][0] = P[0];
+        q[u][1] = P[1];
+        q[u][2] = P[2];
+        m4[u] = mask[off + s];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int s = r0 + u * kBwdBlock + tid;
+        if (s >= M || !(m4[u] & PURSE_MASK_FEASIBLE)) continue;
+        const float P[12] = {q[u][0].x, q[u][0].y, q[u][0].z, q[u][0].w, q[u][1].x, q[u][1].y,
+                             q[u][1].z, q[u][1].w, q[u][2].x, q[u][2].y, q[u][2].z, q[u][2].w};
+        D fr = 0, ft = 0;
+        for (int k = 0; k < 9; ++k) {
+          D d = Rs[k] - (D)P[k];
+          fr += d * d;
+        }
+        for (int k = 0; k < 3; ++k) {
+          D d = ts[k] - (D)P[9 + k];
+          ft += d * d;
+        }
+        // increasing s per thread: a strictly larger value replaces the best
+        if (fr > br) {
+          br = fr;
+          ir = s;
+        }
+        if (ft > bt) {
+          bt = ft;
+          it = s;
+        }
+      }
     }
   }
   for (int o = 32; o >= 1; o >>= 1) {
@@ -443,7 +514,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   // Translation chain: c_i = c_{i-1} + (t_{s_i} - c_{i-1}) / i is linear, so
   // its reverse is a scalar recurrence per coordinate, swept by thread 64 over
   // each chunk while thread 0 sweeps the rotation chain.
-  D cb[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+  D tb[3] = {0, 0, 0};
   if (tid == 64 && !overflow_s) {
     const float *gc = g_centre + 6 * j;
     tb[0] = gc[3];
@@ -460,7 +531,15 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         cot[pd][9 + r] -= gd * dv[r] / dn;
       }
     }
+    for (int r = 0; r < 3; ++r) tbar[r] = tb[r];
   }
+  // Translation chain in closed form: t* = (1/avg) sum_{k > T - avg} c_{k+1}
+  // with c_{k+1} the mean of the first k winners, so step i's winner gets
+  // tbar (1/avg) sum_{k >= max(i, T - avg + 1)} 1/k; hsum = that sum for the
+  // steps before the last avg.
+  D hsum = 0;
+  for (int k = T - avg + 1; k <= T; ++k) hsum += 1.0 / (D)k;
+  __syncthreads();
   if (!overflow_s) {
     for (int i_hi = T; i_hi >= 1; i_hi -= kBwdBlock) {
       const int i_lo = max(1, i_hi - kBwdBlock + 1);
@@ -518,38 +597,84 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       }
       __syncthreads();
       if (tid == 0) {
+        // the serial part: g through the chunk's steps, each step's g kept;
+        // the next step's J_C and term are read while this step is computed
         D g[3] = {gvec[0], gvec[1], gvec[2]};
+        D jc[9], ja[3];
+        {
+          const int t = i_hi - i_lo;
+          for (int k = 0; k < 9; ++k) jc[k] = jac[t][0][k];
+          for (int k = 0; k < 3; ++k) ja[k] = jadd[t][k];
+        }
         for (int ii = i_hi; ii >= i_lo; --ii) {
           const int t = ii - i_lo;
-          for (int k = 0; k < 3; ++k) g[k] += jadd[t][k];
-          const D *JC = jac[t][0], *JR = jac[t][1];
-          const int pa = slot_of(2 * (ii - 1));
-          for (int c = 0; c < 3; ++c) rho[pa][c] += JR[c] * g[0] + JR[3 + c] * g[1] + JR[6 + c] * g[2];
+          const int tn = t > 0 ? t - 1 : 0;
+          D jcn[9], jan[3];
+          for (int k = 0; k < 9; ++k) jcn[k] = jac[tn][0][k];
+          for (int k = 0; k < 3; ++k) jan[k] = jadd[tn][k];
+          for (int k = 0; k < 3; ++k) {
+            g[k] += ja[k];
+            gstep[t][k] = g[k];
+          }
           D gn[3];
-          for (int c = 0; c < 3; ++c) gn[c] = JC[c] * g[0] + JC[3 + c] * g[1] + JC[6 + c] * g[2];
+          for (int c = 0; c < 3; ++c) gn[c] = jc[c] * g[0] + jc[3 + c] * g[1] + jc[6 + c] * g[2];
           for (int k = 0; k < 3; ++k) g[k] = gn[k];
+          for (int k = 0; k < 9; ++k) jc[k] = jcn[k];
+          for (int k = 0; k < 3; ++k) ja[k] = jan[k];
         }
         for (int k = 0; k < 3; ++k) gvec[k] = g[k];
-      } else if (tid == 64) {
-        for (int ii = i_hi; ii >= i_lo; --ii) {
-          if (ii > T - avg)
-            for (int r = 0; r < 3; ++r) cb[r] += tb[r] / avg;
-          const int pa = slot_of(2 * (ii - 1) + 1);
-          const D inv = 1.0 / (D)ii;
-          for (int r = 0; r < 3; ++r) {
-            cot[pa][9 + r] += cb[r] * inv;
-            cb[r] *= (1.0 - inv);
+      }
+      __syncthreads();
+      // rho_{s_i} += J_R^T g_i: each step's term in parallel, then summed per
+      // active sample in step order (deterministic; every term read by every
+      // summing thread, selected by its slot)
+      if (i <= i_hi) {
+        const D *JR = jac[tid][1];
+        for (int c = 0; c < 3; ++c) jadd[tid][c] = JR[c] * gstep[tid][0] + JR[3 + c] * gstep[tid][1] + JR[6 + c] * gstep[tid][2];
+        cslot[tid] = slot_of(2 * (i - 1));
+        D h = hsum;
+        if (i > T - avg) {
+          h = 0;
+          for (int k = i; k <= T; ++k) h += 1.0 / (D)k;
+        }
+        twt[tid] = h / avg;
+        tslot_c[tid] = slot_of(2 * (i - 1) + 1);
+      } else {
+        cslot[tid] = -1;
+        tslot_c[tid] = -1;
+      }
+      __syncthreads();
+      // per active sample (one thread each), in step order: the rotation
+      // terms into rho, the translation weights into the cotangent
+      for (int a = tid; a < n_act; a += kBwdBlock) {
+        D r0 = 0, r1 = 0, r2 = 0, w = 0;
+        for (int t0 = kBwdBlock - 8; t0 >= 0; t0 -= 8) {
+          int cs[8], ts[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            cs[u] = cslot[t0 + u];
+            ts[u] = tslot_c[t0 + u];
+          }
+#pragma unroll
+          for (int u = 7; u >= 0; --u) {
+            const int t = t0 + u;
+            const bool m = cs[u] == a;
+            r0 += m ? jadd[t][0] : 0.0;
+            r1 += m ? jadd[t][1] : 0.0;
+            r2 += m ? jadd[t][2] : 0.0;
+            w += ts[u] == a ? twt[t] : 0.0;
           }
         }
+        rho[a][0] += r0;
+        rho[a][1] += r1;
+        rho[a][2] += r2;
+        for (int r = 0; r < 3; ++r) cot[a][9 + r] += tbar[r] * w;
       }
       __syncthreads();
     }
     if (tid == 0) {
       const int p0 = find_active(act, n_act, s0);
       for (int k = 0; k < 3; ++k) rho[p0][k] += gvec[k];
-    } else if (tid == 64) {
-      const int p0 = find_active(act, n_act, s0);
-      for (int r = 0; r < 3; ++r) cot[p0][9 + r] += cb[r];
     }
     __syncthreads();
     // rho -> ambient cotangent R [rho]x / 2

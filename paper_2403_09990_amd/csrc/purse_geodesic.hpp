@@ -8,6 +8,11 @@
 
 namespace purse {
 
+// v of lane `lane` of the wavefront (a wave-uniform lane index).
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // From this step on the descent moves by at most (pi/2)/16 in quaternion
 // angle, where the short sin/cos series below are exact to float32.
 constexpr int kShortSeriesStep = 16;

@@ -88,10 +88,6 @@ __device__ __forceinline__ int wave_min_i32(int v) {
   return __builtin_amdgcn_readlane(v, 63);
 }
 
-__device__ __forceinline__ float readlane_f(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
 // Keys are squared distances (>= 0) or the sentinel -1: their float bit
 // patterns order like the values under signed integer comparison.
 __device__ __forceinline__ float wave_max_key(float k) { return __int_as_float(wave_max_i32(__float_as_int(k))); }
