@@ -797,15 +797,39 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p,
   const int j = blockIdx.x;
   const int d = threadIdx.x;
   const InstRec I = inst[j];
-  if ((I.status & 0xFF) != PURSE_INST_OK || recs[j].n_act == 0) return;
+  if ((I.status & 0xFF) != PURSE_INST_OK || recs[j].n_act == 0) return;  // (whole workgroup)
   const bool is2d = I.kind == PURSE_KIND_2D3D;
   const int dpk = dirs_per_kp(I.kind);
-  if (d >= I.n_kp * dpk) return;
-  const int i_d = d / dpk, c = d % dpk;
   const int n = I.n_kp;
   const float *a = b.model_pts + 3 * I.kp_off;
   const float *cz = b.centres + 3 * I.kp_off;
   const float *L = b.shapes + 4 * I.kp_off;
+  // 2D-3D: the forward's choice between the two starts, made once for all
+  // directions: wavefront 0 fits from the DLT start, wavefront 1 from the
+  // weak-perspective start (whitening factors cached), as the prologue does
+  __shared__ double w_s[3 * PURSE_MAX_KP];
+  __shared__ double st_R[2][9], st_t[2][3], st_cost[2];
+  __shared__ int st_ok[2];
+  if (is2d) {
+    for (int i = d; i < n; i += blockDim.x) whiten_factor<double>(L + 4 * i, w_s + 3 * i);
+    __syncthreads();
+    if (d == 0 || d == 64) {
+      const int f = d >> 6;
+      const ObsCached obs{cz, w_s};
+      double R[9], t[3], R0[9], t0[3];
+      bool ok = f == 0 ? dlt_2d(a, cz, n, I.K, R, t) : affine_2d(a, cz, n, I.K, R, t);
+      for (int k = 0; k < 9; ++k) R0[k] = R[k];
+      for (int k = 0; k < 3; ++k) t0[k] = t[k];
+      if (ok) ok = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, R, t);
+      st_ok[f] = ok;
+      for (int k = 0; k < 9; ++k) st_R[f][k] = R0[k];  // the start, not the fit
+      for (int k = 0; k < 3; ++k) st_t[f][k] = t0[k];
+      st_cost[f] = ok ? cost_2d_obs(a, obs, n, I.K, R, t) : 0.0;
+    }
+    __syncthreads();
+  }
+  if (d >= n * dpk) return;
+  const int i_d = d / dpk, c = d % dpk;
   Dual<double> Rd[9], td[3];
   if (!is2d) {
     // Arun's fit with b_{i_d} perturbed
@@ -830,18 +854,11 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p,
     polar_so3<Dual<double>>(H, Rd, 12);
     for (int r = 0; r < 3; ++r) td[r] = bb[r] - (Rd[3 * r] * ab[0] + Rd[3 * r + 1] * ab[1] + Rd[3 * r + 2] * ab[2]);
   } else {
-    // both starts, the one the forward kept (lower cost) decides
-    double R1[9], t1[3], R2[9], t2[3];
-    const ObsPlain obs{cz, L};
-    bool ok1 = dlt_2d(a, cz, n, I.K, R1, t1);
-    if (ok1) ok1 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, R1, t1);
-    bool ok2 = affine_2d(a, cz, n, I.K, R2, t2);
-    if (ok2) ok2 = gn_centre_2d<double>(a, obs, n, I.K, p.centre_gn, (double)p.z_min, R2, t2);
-    const bool use2 = ok2 && (!ok1 || cost_2d(a, cz, L, n, I.K, R2, t2) < cost_2d(a, cz, L, n, I.K, R1, t1));
-    double Ri[9], ti[3];
-    ok1 = use2 ? affine_2d(a, cz, n, I.K, Ri, ti) : dlt_2d(a, cz, n, I.K, Ri, ti);
-    for (int k = 0; k < 9; ++k) Rd[k] = Dual<double>(Ri[k], 0.0);
-    for (int k = 0; k < 3; ++k) td[k] = Dual<double>(ti[k], 0.0);
+    // from the start whose fit the forward kept (lower cost; ties: the DLT one)
+    const bool ok1 = st_ok[0] != 0, ok2 = st_ok[1] != 0;
+    const int f = (ok2 && (!ok1 || st_cost[1] < st_cost[0])) ? 1 : 0;
+    for (int k = 0; k < 9; ++k) Rd[k] = Dual<double>(st_R[f][k], 0.0);
+    for (int k = 0; k < 3; ++k) td[k] = Dual<double>(st_t[f][k], 0.0);
     const ObsDual od{cz, L, i_d, c};
     gn_centre_2d<Dual<double>>(a, od, n, I.K, p.centre_gn, (double)p.z_min, Rd, td);
   }
