@@ -29,6 +29,7 @@ namespace {
 constexpr int kBwdBlock = 256;
 constexpr int kBwdWaves = kBwdBlock / 64;
 constexpr int kLdsTrace = 8192;  // descents up to this length are replayed from LDS
+constexpr int kTrajGroup = 4;  // lanes per direction in the 2D-3D tangent kernel
 static_assert(kMaxActive <= 256, "active-set slots are bytes");
 
 using D = double;
@@ -937,6 +938,194 @@ __global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const 
   contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
 }
 
+// ---------------------------------------------------------------------------
+// 2D-3D tangents with G lanes per (active sample, direction): lane q of a
+// group takes the keypoints i = q, q + G, ...; the normal equations and the
+// depth and feasibility tests are combined across the group by DPP lane
+// permutations (butterfly sums: every lane of the group ends with the same
+// value, addition being commutative), so each lane carries 1/G of the
+// keypoint work and a small batch of active samples fills G times more
+// wavefronts.  The arithmetic per keypoint is that of gn_pass2d.
+template <int G>
+__device__ __forceinline__ float group_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  if (G >= 4) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  if (G >= 8) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, false));  // half mirror
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ Dual<float> group_sum(Dual<float> x) {
+  return Dual<float>(group_sum<G>(x.v), group_sum<G>(x.d));
+}
+
+template <int G>
+__device__ __forceinline__ bool group_and(bool b) {
+  int v = b ? 1 : 0;
+  v &= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if (G >= 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  if (G >= 8) v &= __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+  return v != 0;
+}
+
+using DF = Dual<float>;
+
+template <bool FIRST, int G>
+__device__ __forceinline__ bool gn_pass2d_group(const KpDual &kpl, int n, int q, const float K[4], const DF oc[3],
+                                                float z_min, float band, const PoseT<DF> &xk, PoseT<DF> &x) {
+  DF A[21], g[6];
+  for (int k = 0; k < 21; ++k) A[k] = DF(0.f);
+  for (int k = 0; k < 6; ++k) g[k] = DF(0.f);
+  bool ok = true;
+  for (int i = q; i < n; i += G) {
+    const auto k = kpl(i);
+    DF P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    ok = ok && (P[2] > z_min);
+    DF rt0, rt1;
+    if (FIRST) {
+      DF e0 = u - k.c[0], e1 = v - k.c[1];
+      DF et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      DF r2 = et0 * et0 + et1 * et1;
+      DF sc = (r2 <= k.kb2 * band) ? DF(1.f) : k.kb * drsqrt(r2);
+      rt0 = (sc - 1.f) * et0;
+      rt1 = (sc - 1.f) * et1;
+    } else {
+      DF Pk[3], izk, uk, vk;
+      project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
+      DF e0 = uk - k.c[0], e1 = vk - k.c[1];
+      DF et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      DF r2 = et0 * et0 + et1 * et1;
+      DF sc = (r2 <= k.kb2 * band) ? DF(1.f) : k.kb * drsqrt(r2);
+      DF r0 = k.c[0] + sc * e0 - u, r1 = k.c[1] + sc * e1 - v;
+      rt0 = k.w[0] * r0 + k.w[1] * r1;
+      rt1 = k.w[2] * r1;
+    }
+    DF pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+    gn_accumulate<DF>(P, pt, iz, DF(K[0]), DF(K[1]), k.w, rt0, rt1, A, g);
+  }
+  for (int k = 0; k < 21; ++k) A[k] = group_sum<G>(A[k]);
+  for (int k = 0; k < 6; ++k) g[k] = group_sum<G>(g[k]);
+  ok = group_and<G>(ok);
+  DF d[6];
+  ok = ok && chol6_solve<DF>(A, g, d);
+  if (!ok) return false;
+  apply_update<DF>(d, oc, x.R, x.t);
+  return true;
+}
+
+template <int G>
+__device__ __forceinline__ bool feasible2d_group(const KpDual &kpl, int n, int q, const float K[4],
+                                                 const PoseT<DF> &x, float z_min) {
+  bool ok = true;
+  for (int i = q; i < n; i += G) {
+    const auto k = kpl(i);
+    DF P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    DF e0 = u - k.c[0], e1 = v - k.c[1];
+    DF et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+    const float rr = sqrtf(value_of(et0 * et0 + et1 * et1));
+    ok = ok && (value_of(P[2]) > z_min) && (rr <= value_of(k.bt));
+  }
+  return group_and<G>(ok);
+}
+
+// run_trajectory (2D-3D) on a lane group: iterations, feasibility test,
+// bisection pull-in towards the anchor.
+template <int G, typename FR>
+__device__ __forceinline__ uint8_t run_trajectory_group(const InstRec &I, const FR &F, const KpDual &kpl, int q,
+                                                        PoseT<DF> &x, const DevParams &p) {
+  const float band = ClampBand<DF>::v;
+  const DF oc[3] = {DF(F.oc[0]), DF(F.oc[1]), DF(F.oc[2])};
+  bool ok = true;
+  for (int it = 0; it < p.n_iters && ok; ++it) {
+    const PoseT<DF> xk = x;
+    ok = gn_pass2d_group<true, G>(kpl, I.n_kp, q, I.K, oc, p.z_min, band, xk, x);
+    for (int gs = 1; gs < p.n_gn && ok; ++gs) ok = gn_pass2d_group<false, G>(kpl, I.n_kp, q, I.K, oc, p.z_min, band, xk, x);
+  }
+  reorthonormalise(x.R);
+  if (!ok) return PURSE_MASK_FAILED;
+  if (feasible2d_group<G>(kpl, I.n_kp, q, I.K, x, p.z_min)) return PURSE_MASK_FEASIBLE;
+  if (!I.has_anchor) return 0;
+  DF Ra[9], ta[3], RtR[9], RaT[9], w[3];
+  for (int k = 0; k < 9; ++k) Ra[k] = F.Ra[k];
+  for (int r = 0; r < 3; ++r) ta[r] = F.ta[r];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) RaT[3 * r + c] = Ra[3 * c + r];
+  matmul3(RaT, x.R, RtR);
+  log_so3(RtR, w);
+  float lo = 0.f, hi = 1.f;
+  for (int b = 0; b < p.n_bis; ++b) {
+    const float mid = 0.5f * (lo + hi);
+    DF wm[3] = {mid * w[0], mid * w[1], mid * w[2]}, E[9];
+    PoseT<DF> m;
+    exp_so3(wm, E);
+    matmul3(Ra, E, m.R);
+    for (int r = 0; r < 3; ++r) m.t[r] = ta[r] + mid * (x.t[r] - ta[r]);
+    if (feasible2d_group<G>(kpl, I.n_kp, q, I.K, m, p.z_min))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  if (lo == 0.f) {
+    for (int k = 0; k < 9; ++k) x.R[k] = Ra[k];
+    for (int r = 0; r < 3; ++r) x.t[r] = ta[r];
+  } else {
+    DF wl[3] = {lo * w[0], lo * w[1], lo * w[2]}, E[9];
+    exp_so3(wl, E);
+    DF Rn[9];
+    matmul3(Ra, E, Rn);
+    for (int k = 0; k < 9; ++k) x.R[k] = Rn[k];
+    for (int r = 0; r < 3; ++r) x.t[r] = ta[r] + lo * (x.t[r] - ta[r]);
+  }
+  return PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
+}
+
+// k_bwd_traj for 2D-3D instances with G lanes per direction: workgroup
+// (a, j, z) covers active sample a and directions z * 64 / G ... of instance j.
+template <int G>
+__global__ void __launch_bounds__(64) k_bwd_traj2d_group(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
+                                                         const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                         const float *__restrict__ tan_all, float *contrib,
+                                                         int max_dirs) {
+  const int a = blockIdx.x, j = blockIdx.y;
+  const int q = threadIdx.x % G;
+  const int d = blockIdx.z * (64 / G) + threadIdx.x / G;
+  const InstRec I = inst[j];
+  if (I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK) return;
+  const BwdRec *rec = recs + j;
+  if (a >= rec->n_act) return;
+  const int dpk = dirs_per_kp(PURSE_KIND_2D3D);
+  if (d >= I.n_kp * dpk) return;  // (whole lane groups)
+  const int i_d = d / dpk, c = d % dpk;
+  const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
+  FrameT<DF> F;
+  for (int k = 0; k < 9; ++k) {
+    F.Rc[k] = DF(I.Rc[k], tan[k]);
+    F.Ra[k] = DF(I.Ra[k], tan[15 + k]);
+  }
+  for (int r = 0; r < 3; ++r) {
+    F.tc[r] = DF(I.tc[r], tan[9 + r]);
+    F.oc[r] = DF(I.oc[r], tan[12 + r]);
+    F.ta[r] = DF(I.ta[r], tan[24 + r]);
+  }
+  KpDual kpl;
+  kpl.kp = kprec + I.kp_off;
+  kpl.i_d = i_d;
+  kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
+             kpl.tk);
+  const int s = rec->active[a];
+  PoseT<DF> x = initial_pose<DF>(F, I.seed, (uint64_t)s, p);
+  const uint8_t m = run_trajectory_group<G>(I, F, kpl, q, x, p);
+  if (q != 0) return;
+  double acc = 0.0;
+  if (m & PURSE_MASK_FEASIBLE) {
+    for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
+    for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
+  }
+  contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
+}
+
 // Sum over active samples (fixed order) and scatter into the gradients.
 __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstRec *__restrict__ inst,
                                                         const BwdRec *recs, const float *__restrict__ contrib,
@@ -959,7 +1148,8 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstR
     g = __int_as_float(0x7fc00000);  // active set beyond capacity: no gradient
   } else if ((I.status & 0xFF) == PURSE_INST_OK) {
     double acc = 0.0;
-    for (int a = 0; a < rec->n_act; ++a) acc += (double)contrib[((int64_t)j * kMaxActive + a) * max_dirs + d];
+    const int n_act = min(max(rec->n_act, 0), kMaxActive);  // (the record's capacity)
+    for (int a = 0; a < n_act; ++a) acc += (double)contrib[((int64_t)j * kMaxActive + a) * max_dirs + d];
     g = (float)acc;
   }
   const int64_t k = ko + i;
@@ -1000,7 +1190,10 @@ void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, 
   const int max_dirs = 6 * b.max_kp;
   hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, recs, tan, max_dirs);
   dim3 grid(kMaxActive, n, (max_dirs + 63) / 64);
-  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_2D3D>, grid, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
+  // 2D-3D directions on lane groups (every 2D-3D instance, so its gradients
+  // do not depend on the batch around it)
+  dim3 grid_g(kMaxActive, n, (max_dirs * kTrajGroup + 63) / 64);
+  hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, grid_g, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
                      max_dirs);
   hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, grid, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
                      max_dirs);
