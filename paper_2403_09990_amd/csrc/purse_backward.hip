@@ -175,7 +175,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o, 64));
     if (lane == 0 && first != INT32_MAX) atomicMin(&s0_s, first);
     __syncthreads();
-    if (s0_s != INT32_MAX) break;
+    const bool found = s0_s != INT32_MAX;
+    __syncthreads();  // every wave has read s0_s before any wave's next round may write it
+    if (found) break;
   }
   const int s0 = s0_s;
   if (s0 == INT32_MAX) {
