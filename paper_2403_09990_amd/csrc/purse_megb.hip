@@ -11,7 +11,9 @@
 // so when the shell's best exceeds that bound (with a rounding slack) the
 // shell argmax is the argmax over all samples and the step is exact; when it
 // does not, the chain rescans around the current centre.  Steps on the shell
-// run in one wavefront with shuffles only.
+// run in one wavefront with shuffles only, or, once the winners keep coming
+// from a few samples, pipelined: one wavefront runs the descent ahead with
+// predicted winners and the others check each step's argmax.
 #include <float.h>
 
 #include <type_traits>
@@ -36,6 +38,10 @@ constexpr int kMaxChunks = kCap / 64;
 constexpr int kEarlySteps = 32;
 constexpr int kRecentreChunks = 4;  // a step scanning more chunks than this ...
 constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
+constexpr int kPipeSteps = 64;       // steps per round of a pipelined segment (one per lane)
+constexpr int kVerifySkip = 4;       // wave on wave 0's SIMD (waves go round the 4 SIMDs)
+constexpr int kPipeMinSeq = 8;       // steps with no new winner before a pipelined segment, doubled after
+constexpr int kPipeMaxSeq = 256;     // each failed prediction up to this
 static_assert(kCap % 64 == 0, "chunks of 64 tile the shell");
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
@@ -329,7 +335,7 @@ __device__ __forceinline__ int bin_of(float d, float lo, float w) {
   return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
 }
 
-template <int CHAIN>
+template <int CHAIN, bool PIPE>
 __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *__restrict__ sample_off,
                                           int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
                                           float *dref_all, int64_t total_samples, int32_t *trace, int T, int avg,
@@ -340,6 +346,12 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   __shared__ int st_bstar;
   __shared__ int st_mode;  // 0 shell in LDS, 1 scan of every sample
   __shared__ unsigned int sh_n;
+  // pipelined shell steps
+  __shared__ float4 pl_C[3][kPipeSteps];  // starting iterate of each step of a round (3 rounds in flight)
+  __shared__ int pl_W[3][kPipeSteps];     // and its predicted winner
+  __shared__ int pl_fail[3];              // first step of a round whose prediction failed
+  __shared__ float4 pl_Cend;
+  __shared__ int pl_go;
 
   constexpr int chain = CHAIN;
   const int j = blockIdx.x >> 1;
@@ -568,171 +580,373 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       stalled = false;
     } else {
       // ---------------------------------------------------------- shell steps
-      // Wave 0 alone.  Entries sit in chunks of 64 (one entry per lane) in
-      // decreasing fine bins of d_ref.  Each lane keeps its own best (key,
-      // id, point), one wavefront reduction per step of the scan, and the
-      // scan stops once no later chunk can beat the best found.  The first
-      // two chunks, which almost every step needs, stay in registers for the
-      // whole stage (lanes past the shell's end hold copies of entry 0, which
-      // change no argmax); later chunks are read from LDS, the next one while
-      // this one is reduced.  When a step needs many chunks the centre has
-      // drifted from C_ref: the stage ends and the next one rescans there.
+      // Entries sit in chunks of 64 (one entry per lane) in decreasing fine
+      // bins of d_ref.  Each lane keeps its own best (key, id, point), one
+      // wavefront reduction per step of the scan, and the scan stops once no
+      // later chunk can beat the best found.  The first two chunks, which
+      // almost every step needs, stay in registers for the whole stage (lanes
+      // past the shell's end hold copies of entry 0, which change no argmax);
+      // later chunks are read from LDS.  When a step needs many chunks the
+      // centre has drifted from C_ref: the stage ends and the next one
+      // rescans there.
       //
-      // A single wavefront issues about one instruction every few cycles
-      // whatever the dependences, so the common step (the first chunk, or the
-      // first two once one has often not sufficed in this stage, bounds all
-      // others and one lane holds the maximum) is one straight path: 1/i comes
-      // from a per-lane table of the next 64 values, and the winners' ids are
-      // collected one per lane and written 64 at a time.
+      // Steps run in segments of two kinds.  Sequential segments run in wave
+      // 0 alone.  A single wavefront issues about one instruction every few
+      // cycles whatever the dependences, so the common step (the first chunk,
+      // or the first two once one has often not sufficed in this stage,
+      // bounds all others and one lane holds the maximum) is one straight
+      // path: 1/i comes from a per-lane table of the next 64 values, and the
+      // winners' ids are collected one per lane and written 64 at a time.
+      //
+      // Late in the descent the winners cycle among a few samples (the
+      // support of the ball).  Wave 0 keeps the last distinct winners (up to
+      // 8, one per lane); once no new one has appeared for a while, a
+      // pipelined segment takes over: wave 0 runs the descent ahead, taking
+      // as the winner of each step the one of those candidates farthest from
+      // its iterate (a cheap key that only has to predict), kPipeSteps steps
+      // per round, and leaves each step's starting iterate and predicted
+      // winner in LDS, while the other waves check the steps of the previous
+      // round with the full argmax of a sequential step.  Rounds end at a
+      // workgroup barrier.  Every iterate wave 0 computes from verified
+      // predictions is the one the sequential descent computes (same inputs,
+      // same arithmetic), so the trace and the centre are unchanged; at the
+      // first step whose prediction fails, the segment ends with that step's
+      // starting iterate and a sequential segment redoes the step.
       const int K = (int)sh_n;
       const float theta = st_theta;
       const float slack = 4e-6f * st_rref + 1e-30f;
       const int nchunks = (K + 63) / 64;
-      if (wave == 0) {
-        const float4 p0 = S.pt[lane < K ? lane : 0], p1 = S.pt[64 + lane < K ? 64 + lane : 0];
-        const int q0 = S.id[lane < K ? lane : 0], q1 = S.id[64 + lane < K ? 64 + lane : 0];
-        const float ub1 = nchunks > 1 ? S.chunk_ub[1] : 0.f;
-        const float ub2 = nchunks > 2 ? S.chunk_ub[2] : 0.f;
-        // the one bound a common step checks: entries past the chunks it
-        // scanned, else samples outside the shell, else none
-        const bool need_ub1 = nchunks > 1 || theta >= 0.f, need_ub2 = nchunks > 2 || theta >= 0.f;
-        const float ubf1 = nchunks > 1 ? ub1 : theta, ubf2 = nchunks > 2 ? ub2 : theta;
-        float4 C = Cref;
-        int i = i0;
-        int ib = i;                                 // first step of the block of 64
-        float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
-        int trv = 0;                                // winner of step ib + lane
-        int misses = 0;                             // one-chunk steps that needed more
-        // Steps of the stage up to step `end` with WIDTH chunks in the common
-        // step and (SHORT) the short sin/cos series of the geodesic step;
-        // returns kStageEnds, kGoWide when one-chunk steps often needed more
-        // and the stage should go on with two, or kRangeDone at `end`.
-        constexpr int kStageEnds = 0, kGoWide = 1, kRangeDone = 2;
-        auto run_steps = [&](auto width, auto short_series, auto accumulate, int end) -> int {
-          constexpr int W = decltype(width)::value;
-          constexpr bool SHORT = decltype(short_series)::value;
-          constexpr bool ACC = decltype(accumulate)::value;  // within the last avg steps
-          while (i <= end) {
-            if (i - ib == 64) {
-              tr[2 * (ib - 1 + lane)] = trv;
-              ib = i;
-              inv_tab = 1.f / (float)(ib + lane);
-            }
-            const float inv = readlane_f(inv_tab, i - ib);
-            // bounds compared squared; the raw square root is within the slack.
-            // Rotation: |C + C_ref|^2 = 4 - |C - C_ref|^2 for unit quaternions
-            // (C stays near C_ref within a stage; the form only feeds bounds).
-            float dC2;
-            if (CHAIN == 0) {
-              const float e0 = C.x - Cref.x, e1 = C.y - Cref.y, e2 = C.z - Cref.z, e3 = C.w - Cref.w;
-              const float xc = fmaf(e3, e3, fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
-              dC2 = (2.f * xc) * (4.f - xc);
-            } else {
-              dC2 = sqdist(C, Cref, chain);
-            }
-            const float dC = __builtin_amdgcn_sqrtf(dC2);
-            auto beats = [&](float key, float ub) {
-              const float b = ub + dC + slack;
-              return key > b * b;
-            };
-            float bk = sqdist(C, p0, chain), bp_x = p0.x, bp_y = p0.y, bp_z = p0.z, bp_w = p0.w;
-            int bi = q0;
-            auto take = [&](float k, int q, float4 pp) {
-              const bool t = (k > bk) | ((k == bk) & (q < bi));
-              bk = t ? k : bk;
-              bi = t ? q : bi;
-              bp_x = t ? pp.x : bp_x;
-              bp_y = t ? pp.y : bp_y;
-              bp_z = t ? pp.z : bp_z;
-              bp_w = t ? pp.w : bp_w;
-            };
-            int g = W;  // chunks scanned
-            if (W == 2) take(sqdist(C, p1, chain), q1, p1);
-            float wk = wave_max_key(bk);
-            unsigned long long win = __ballot(bk == wk);
-            const bool bounded = W == 2 ? (!need_ub2 || beats(wk, ubf2)) : (!need_ub1 || beats(wk, ubf1));
-            if (!(bounded && __popcll(win) == 1)) {
-              // ---------------------------------------------- uncommon step
-              if (W == 1 && nchunks > 1 && !beats(wk, ub1)) {
-                take(sqdist(C, p1, chain), q1, p1);
-                wk = wave_max_key(bk);
-                g = 2;
+      const float4 p0 = S.pt[lane < K ? lane : 0], p1 = S.pt[64 + lane < K ? 64 + lane : 0];
+      const int q0 = S.id[lane < K ? lane : 0], q1 = S.id[64 + lane < K ? 64 + lane : 0];
+      const float ub1 = nchunks > 1 ? S.chunk_ub[1] : 0.f;
+      const float ub2 = nchunks > 2 ? S.chunk_ub[2] : 0.f;
+      // the one bound a common step checks: entries past the chunks it
+      // scanned, else samples outside the shell, else none
+      const bool need_ub1 = nchunks > 1 || theta >= 0.f, need_ub2 = nchunks > 2 || theta >= 0.f;
+      const float ubf1 = nchunks > 1 ? ub1 : theta, ubf2 = nchunks > 2 ? ub2 : theta;
+      // distance of C from C_ref, compared squared in the bounds (the raw
+      // square root is within the slack).  Rotation: |C + C_ref|^2 = 4 -
+      // |C - C_ref|^2 for unit quaternions (C stays near C_ref within a stage;
+      // the form only feeds bounds).
+      auto drift = [&](float4 Cc) {
+        float dC2;
+        if (CHAIN == 0) {
+          const float e0 = Cc.x - Cref.x, e1 = Cc.y - Cref.y, e2 = Cc.z - Cref.z, e3 = Cc.w - Cref.w;
+          const float xc = fmaf(e3, e3, fmaf(e2, e2, fmaf(e1, e1, e0 * e0)));
+          dC2 = (2.f * xc) * (4.f - xc);
+        } else {
+          dC2 = sqdist(Cc, Cref, chain);
+        }
+        return __builtin_amdgcn_sqrtf(dC2);
+      };
+      // wave-0 state carried across the segments of the stage
+      float4 C = Cref;
+      int i = i0;
+      int misses = 0;                // one-chunk steps that needed more
+      bool wide = false, ended = false;
+      int backoff = kPipeMinSeq;     // steps with no new winner before a pipelined segment
+      const int last_plain = T - avg;  // steps after this one accumulate their iterate
+      // wave 0: candidate winners in lanes 0..7 (id -1: empty, its point C_ref,
+      // which is never the farthest), the slot the next new winner takes, and
+      // the steps since a new winner appeared
+      int cand_id = -1;
+      float4 cand_p = Cref;
+      int nins = 0, stable = 0;
+      int last_w = -1;  // winner of the last sequential step
+      while (true) {
+        if (wave == 0) {
+          int ib = i;                                 // first step of the block of 64
+          float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
+          int trv = 0;                                // winner of step ib + lane
+          bool piped = false;
+          // Steps of the segment up to step `end` with WIDTH chunks in the
+          // common step and (SHORT) the short sin/cos series of the geodesic
+          // step; returns kStageEnds, kGoWide when one-chunk steps often
+          // needed more and the stage should go on with two, kPipe when no
+          // new winner has appeared for `backoff` steps and enough steps
+          // remain for a pipelined segment, or kRangeDone at `end`.
+          constexpr int kStageEnds = 0, kGoWide = 1, kRangeDone = 2, kPipe = 3;
+          auto run_steps = [&](auto width, auto short_series, auto accumulate, int end) -> int {
+            constexpr int W = decltype(width)::value;
+            constexpr bool SHORT = decltype(short_series)::value;
+            constexpr bool ACC = decltype(accumulate)::value;  // within the last avg steps
+            while (i <= end) {
+              if (i - ib == 64) {
+                tr[2 * (ib - 1 + lane)] = trv;
+                ib = i;
+                inv_tab = 1.f / (float)(ib + lane);
               }
-              if (g == 2 && nchunks > 2 && !beats(wk, ub2)) {
-                float4 p = S.pt[2 * 64 + lane];
-                int q = S.id[2 * 64 + lane];
-                while (true) {
-                  float4 np;
-                  int nq;
-                  const bool more = g + 1 < nchunks;
-                  if (more) {
-                    np = S.pt[(g + 1) * 64 + lane];
-                    nq = S.id[(g + 1) * 64 + lane];
-                  }
-                  const float kk = sqdist(C, p, chain);
-                  take(g * 64 + lane < K ? kk : -1.f, q, p);
+              const float inv = readlane_f(inv_tab, i - ib);
+              const float dC = drift(C);
+              auto beats = [&](float key, float ub) {
+                const float b = ub + dC + slack;
+                return key > b * b;
+              };
+              float bk = sqdist(C, p0, chain), bp_x = p0.x, bp_y = p0.y, bp_z = p0.z, bp_w = p0.w;
+              int bi = q0;
+              auto take = [&](float k, int q, float4 pp) {
+                const bool t = (k > bk) | ((k == bk) & (q < bi));
+                bk = t ? k : bk;
+                bi = t ? q : bi;
+                bp_x = t ? pp.x : bp_x;
+                bp_y = t ? pp.y : bp_y;
+                bp_z = t ? pp.z : bp_z;
+                bp_w = t ? pp.w : bp_w;
+              };
+              int g = W;  // chunks scanned
+              if (W == 2) take(sqdist(C, p1, chain), q1, p1);
+              float wk = wave_max_key(bk);
+              unsigned long long win = __ballot(bk == wk);
+              const bool bounded = W == 2 ? (!need_ub2 || beats(wk, ubf2)) : (!need_ub1 || beats(wk, ubf1));
+              if (!(bounded && __popcll(win) == 1)) {
+                // -------------------------------------------- uncommon step
+                if (W == 1 && nchunks > 1 && !beats(wk, ub1)) {
+                  take(sqdist(C, p1, chain), q1, p1);
                   wk = wave_max_key(bk);
-                  ++g;
-                  if (!more || beats(wk, S.chunk_ub[g])) break;
-                  p = np;
-                  q = nq;
+                  g = 2;
+                }
+                if (g == 2 && nchunks > 2 && !beats(wk, ub2)) {
+                  float4 p = S.pt[2 * 64 + lane];
+                  int q = S.id[2 * 64 + lane];
+                  while (true) {
+                    float4 np;
+                    int nq;
+                    const bool more = g + 1 < nchunks;
+                    if (more) {
+                      np = S.pt[(g + 1) * 64 + lane];
+                      nq = S.id[(g + 1) * 64 + lane];
+                    }
+                    const float kk = sqdist(C, p, chain);
+                    take(g * 64 + lane < K ? kk : -1.f, q, p);
+                    wk = wave_max_key(bk);
+                    ++g;
+                    if (!more || beats(wk, S.chunk_ub[g])) break;
+                    p = np;
+                    q = nq;
+                  }
+                }
+                if (theta >= 0.f && !beats(wk, theta)) {
+                  stage_groups += g;
+                  return kStageEnds;  // the shell no longer suffices
+                }
+                // winner: the one lane holding the maximum key, else (a tie)
+                // the lowest sample id among the lanes that hold it
+                win = __ballot(bk == wk);
+                if (__popcll(win) > 1) {
+                  const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
+                  win = __ballot(bk == wk && bi == wmin);
                 }
               }
-              if (theta >= 0.f && !beats(wk, theta)) {
-                stage_groups += g;
-                return kStageEnds;  // the shell no longer suffices
+              stage_groups += g;
+              const int wl = (int)__ffsll((long long)win) - 1;
+              const int wi = __builtin_amdgcn_readlane(bi, wl);
+              const float4 pt = make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl),
+                                            readlane_f(bp_w, wl));
+              C = geodesic_step_inv<SHORT>(C, pt, inv, chain);
+              trv = lane == i - ib ? wi : trv;
+              if (ACC) accumulate_iterate(C, chain, acc);
+              ++i;
+              if (PIPE && SHORT && !ACC) {
+                last_w = wi;
+                const bool known = (__ballot(cand_id == wi) & 0xFFull) != 0ull;
+                const bool ins = !known && lane == nins;
+                cand_id = ins ? wi : cand_id;
+                cand_p = make_float4(ins ? pt.x : cand_p.x, ins ? pt.y : cand_p.y, ins ? pt.z : cand_p.z,
+                                     ins ? pt.w : cand_p.w);
+                nins = known ? nins : ((nins + 1) & 7);
+                stable = known ? stable + 1 : 0;
               }
-              // winner: the one lane holding the maximum key, else (a tie)
-              // the lowest sample id among the lanes that hold it
-              win = __ballot(bk == wk);
-              if (__popcll(win) > 1) {
-                const int wmin = wave_min_i32(bk == wk ? bi : INT32_MAX);
-                win = __ballot(bk == wk && bi == wmin);
-              }
+              if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
+              if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
+              if (PIPE && SHORT && !ACC && stable >= backoff && end - i + 1 >= 2 * kPipeSteps) return kPipe;
             }
-            stage_groups += g;
-            const int wl = (int)__ffsll((long long)win) - 1;
-            const int wi = __builtin_amdgcn_readlane(bi, wl);
-            const float4 pt =
-                make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl), readlane_f(bp_w, wl));
-            C = geodesic_step_inv<SHORT>(C, pt, inv, chain);
-            trv = lane == i - ib ? wi : trv;
-            if (ACC) accumulate_iterate(C, chain, acc);
-            ++i;
-            if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
-            if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
+            return kRangeDone;
+          };
+          // Ranges of steps with no per-step choice of the sin/cos series or
+          // of accumulating the iterate: before kShortSeriesStep, then the
+          // rest, each split at the last avg steps.
+          auto run_range = [&](auto short_series, auto accumulate, int end) {
+            if (ended || piped || i > end) return;
+            int r = wide ? run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end)
+                         : run_steps(std::integral_constant<int, 1>(), short_series, accumulate, end);
+            if (r == kGoWide) {
+              wide = true;
+              r = run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end);
+            }
+            ended = r == kStageEnds;
+            piped = r == kPipe;
+          };
+          const int long_end = min(T, kShortSeriesStep - 1);
+          run_range(std::false_type(), std::false_type(), min(long_end, last_plain));
+          run_range(std::false_type(), std::true_type(), long_end);
+          run_range(std::true_type(), std::false_type(), last_plain);
+          run_range(std::true_type(), std::true_type(), T);
+          if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
+          n_groups += stage_groups;
+          stage_groups = 0;
+          if (lane == 0) {
+            st_C = C;
+            st_i = i;
+            pl_go = piped ? 1 : 0;
           }
-          return kRangeDone;
-        };
-        // Ranges of steps with no per-step choice of the sin/cos series or of
-        // accumulating the iterate: before kShortSeriesStep, then the rest,
-        // each split at the last avg steps.
-        bool wide = false, ended = false;
-        auto run_range = [&](auto short_series, auto accumulate, int end) {
-          if (ended || i > end) return;
-          int r = wide ? run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end)
-                       : run_steps(std::integral_constant<int, 1>(), short_series, accumulate, end);
-          if (r == kGoWide) {
-            wide = true;
-            r = run_steps(std::integral_constant<int, 2>(), short_series, accumulate, end);
-          }
-          ended = r == kStageEnds;
-        };
-        const int last_plain = T - avg;  // steps after this one accumulate their iterate
-        const int long_end = min(T, kShortSeriesStep - 1);
-        run_range(std::false_type(), std::false_type(), min(long_end, last_plain));
-        run_range(std::false_type(), std::true_type(), long_end);
-        run_range(std::true_type(), std::false_type(), last_plain);
-        run_range(std::true_type(), std::true_type(), T);
-        if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
-        n_groups += stage_groups;
-        stage_groups = 0;
-        if (lane == 0) {
-          st_C = C;
-          st_i = i;
+          for (int k = lane; k < 3; k += 64) pl_fail[k] = INT32_MAX;
         }
+        __syncthreads();
+        if (!PIPE || !pl_go) break;
+        // ------------------------------------------------ pipelined segment
+        const int pi0 = st_i, pend = last_plain;
+        const int nrounds = (pend - pi0 + kPipeSteps) / kPipeSteps;
+        float4 Cs = st_C;                       // wave 0: the iterate ahead
+        float4 cv = Cs;                         // wave 0: starting iterate of step (round start + lane)
+        int pv = 0;                             // wave 0: predicted winner of that step
+        int fail_step = INT32_MAX;
+        float4 fail_C = Cs;
+        // wave 0: when only two samples have won since the stage began the
+        // winners alternate; the first predicted winner is then the one not
+        // taken last
+        const unsigned long long vm = __ballot(cand_id >= 0) & 0xFFull;
+        const bool two = __popcll(vm) == 2;
+        const int l0 = (int)__ffsll((long long)vm) - 1, l1 = (int)__ffsll((long long)(vm & (vm - 1ull))) - 1;
+        const bool zero_last = __builtin_amdgcn_readlane(cand_id, two ? l0 : 0) == last_w;
+        const int la = two ? (zero_last ? l1 : l0) : 0, lb = two ? (zero_last ? l0 : l1) : 0;
+        const int idA = __builtin_amdgcn_readlane(cand_id, la), idB = __builtin_amdgcn_readlane(cand_id, lb);
+        const float4 pA = make_float4(readlane_f(cand_p.x, la), readlane_f(cand_p.y, la), readlane_f(cand_p.z, la),
+                                      readlane_f(cand_p.w, la));
+        const float4 pB = make_float4(readlane_f(cand_p.x, lb), readlane_f(cand_p.y, lb), readlane_f(cand_p.z, lb),
+                                      readlane_f(cand_p.w, lb));
+        for (int r = 0; r <= nrounds; ++r) {
+          const int s_r = pi0 + r * kPipeSteps;
+          const int slot = r % 3;
+          if (tid == 0) pl_fail[slot] = INT32_MAX;  // (read last at the start of round r - 2)
+          if (wave == 0) {
+            if (r < nrounds) {
+              const int n_r = min(kPipeSteps, pend - s_r + 1);
+              const float pinv_tab = 1.f / (float)(s_r + lane);  // 1/i of step s_r + lane
+              // (kPipeSteps is even: step k of every round takes A when k is even)
+              if (two) {
+                for (int k = 0; k < n_r; ++k) {
+                  const float inv = readlane_f(pinv_tab, k);
+                  const bool odd = (k & 1) != 0;
+                  const float4 pp = odd ? pB : pA;
+                  const bool mine = lane == k;
+                  cv = make_float4(mine ? Cs.x : cv.x, mine ? Cs.y : cv.y, mine ? Cs.z : cv.z, mine ? Cs.w : cv.w);
+                  pv = mine ? (odd ? idB : idA) : pv;
+                  Cs = geodesic_step_inv<true>(Cs, pp, inv, chain);
+                }
+              } else
+              for (int k = 0; k < n_r; ++k) {
+                const float inv = readlane_f(pinv_tab, k);
+                // predicted winner: the argmax over the candidates (lanes
+                // 0..7) with the keys and tie rule of the full argmax, near
+                // convergence the candidates being almost equidistant
+                const float u = sqdist(Cs, cand_p, chain);
+                int ub = __float_as_int(u);
+                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x141, 0xF, 0xF, false));  // row_half_mirror
+                const int umax = __builtin_amdgcn_readlane(ub, 0);
+                const bool at_max = __float_as_int(u) == umax;
+                unsigned long long tie = __ballot(at_max) & 0xFFull;
+                if (__popcll(tie) > 1) {  // equal keys: the lowest sample id
+                  int iv = at_max ? cand_id : INT32_MAX;
+                  iv = min(iv, __builtin_amdgcn_update_dpp(INT32_MAX, iv, 0xB1, 0xF, 0xF, false));
+                  iv = min(iv, __builtin_amdgcn_update_dpp(INT32_MAX, iv, 0x4E, 0xF, 0xF, false));
+                  iv = min(iv, __builtin_amdgcn_update_dpp(INT32_MAX, iv, 0x141, 0xF, 0xF, false));
+                  const int imin = __builtin_amdgcn_readlane(iv, 0);
+                  tie = __ballot(at_max && cand_id == imin) & 0xFFull;
+                }
+                const int wl = (int)__ffsll((long long)tie) - 1;
+                const int pid = __builtin_amdgcn_readlane(cand_id, wl);
+                const float4 pp = make_float4(readlane_f(cand_p.x, wl), readlane_f(cand_p.y, wl),
+                                              readlane_f(cand_p.z, wl), readlane_f(cand_p.w, wl));
+                const bool mine = lane == k;
+                cv = make_float4(mine ? Cs.x : cv.x, mine ? Cs.y : cv.y, mine ? Cs.z : cv.z, mine ? Cs.w : cv.w);
+                pv = mine ? pid : pv;
+                Cs = geodesic_step_inv<true>(Cs, pp, inv, chain);
+              }
+              if (lane < n_r) {
+                pl_C[slot][lane] = cv;
+                pl_W[slot][lane] = pv;
+              }
+              if (r == nrounds - 1 && lane == 0) pl_Cend = Cs;
+            }
+          } else if (r >= 1 && wave != kVerifySkip) {
+            // check the steps of round r - 1, one wave per step (not the wave
+            // that shares a SIMD with wave 0)
+            const int s_p = s_r - kPipeSteps, n_p = min(kPipeSteps, pend - s_p + 1);
+            const int pslot = (r + 2) % 3;
+            const int vw = wave < kVerifySkip ? wave - 1 : wave - 2;
+            for (int k = vw; k < n_p; k += kChainWaves - 2) {
+              const float4 Cv = pl_C[pslot][k];
+              const int pid = pl_W[pslot][k];
+              const float dC = drift(Cv);
+              auto beats = [&](float key, float ub) {
+                const float b = ub + dC + slack;
+                return key > b * b;
+              };
+              float bk = sqdist(Cv, p0, chain);
+              int bi = q0;
+              auto take = [&](float kk, int q) {
+                const bool t = (kk > bk) | ((kk == bk) & (q < bi));
+                bk = t ? kk : bk;
+                bi = t ? q : bi;
+              };
+              take(sqdist(Cv, p1, chain), q1);
+              float wk = wave_max_key(bk);
+              bool ok = true;
+              if (need_ub2 && !beats(wk, ubf2)) {
+                // further chunks until one bounds the rest, then the samples
+                // outside the shell
+                int g = 2;
+                while (g < nchunks) {
+                  const float4 p = S.pt[g * 64 + lane];
+                  const int q = S.id[g * 64 + lane];
+                  take(g * 64 + lane < K ? sqdist(Cv, p, chain) : -1.f, q);
+                  wk = wave_max_key(bk);
+                  ++g;
+                  if (g < nchunks && beats(wk, S.chunk_ub[g])) break;
+                }
+                if (theta >= 0.f && !beats(wk, theta)) ok = false;
+                // a step that needs many chunks goes to a sequential segment,
+                // which re-centres the shell
+                if (g > kRecentreChunks && s_p + k - i0 > kMinShellSteps) ok = false;
+              }
+              if (ok) {
+                const unsigned long long win = __ballot(bk == wk);
+                const int wi = __popcll(win) > 1 ? wave_min_i32(bk == wk ? bi : INT32_MAX)
+                                                 : __builtin_amdgcn_readlane(bi, (int)__ffsll((long long)win) - 1);
+                ok = wi == pid;
+              }
+              if (!ok && lane == 0) atomicMin(&pl_fail[pslot], k);
+            }
+          }
+          __syncthreads();
+          if (r >= 1) {
+            const int s_p = s_r - kPipeSteps, n_p = min(kPipeSteps, pend - s_p + 1);
+            const int pslot = (r + 2) % 3;
+            const int f = pl_fail[pslot];
+            // the verified steps of round r - 1 enter the trace
+            if (wave == 1 && lane < min(n_p, f)) tr[2 * (s_p + lane - 1)] = pl_W[pslot][lane];
+            if (f != INT32_MAX) {
+              fail_step = s_p + f;
+              fail_C = pl_C[pslot][f];
+              break;
+            }
+          }
+        }
+        if (fail_step == INT32_MAX) {
+          C = pl_Cend;
+          i = pend + 1;
+        } else {
+          C = fail_C;
+          i = fail_step;
+          backoff = min(2 * backoff, kPipeMaxSeq);
+          stable = 0;
+        }
+        // (pl_Cend and the failing slot are read before any later write:
+        // the next write to either follows the barrier that ends the next
+        // sequential segment)
       }
-      __syncthreads();
       stalled = st_i == i0;
     }
   }
@@ -758,6 +972,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
 
 // One workgroup of kChainBlock threads per (instance, chain): even blocks
 // run the rotation chain, odd blocks the translation chain.
+template <bool PIPE>
 __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
                                                             const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
@@ -772,9 +987,9 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
   __shared__ int red_i[2][kChainWaves];
   const ChainShared S{sh_pt, reinterpret_cast<int *>(sh_pt + cap), hist, cursor, chunk_ub, red_k, red_i};
   if (blockIdx.x & 1)
-    chain_run<1>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
+    chain_run<1, PIPE>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
   else
-    chain_run<0>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
+    chain_run<0, PIPE>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
 }
 
 // float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.
@@ -864,9 +1079,19 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
       hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
                          quat, trans, rec, dref, trace, p.megb_iters, p.megb_avg, cap, no_prune, i);
   }
-  hipLaunchKernelGGL(k_megb_chain, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat, trans,
-                     rec, dref,
-                     total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
+  // Pipelined shell steps trade extra work (every step's argmax checked on
+  // other wavefronts) for a shorter chain; they pay while the chains leave
+  // compute units idle, i.e. while there are at most as many chain
+  // workgroups as compute units.
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    n_cu = 0;
+  if (2 * n <= n_cu)
+    hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat,
+                       trans, rec, dref, total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
+  else
+    hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples,
+                       quat, trans, rec, dref, total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                      poses, mask, rec);
   hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,

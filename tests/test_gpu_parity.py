@@ -227,6 +227,25 @@ def test_megb_pruning_is_exact(m):
     assert torch.equal(full["radii"], res["radii"])
 
 
+@pytest.mark.parametrize("cfg", ["c1", "c2-16k", "c3-8"])
+def test_megb_full_descent_is_exact(cfg):
+    """Over the whole descent (T = 4096, where most steps run in pipelined
+    segments with predicted winners), the shell path gives bitwise the trace,
+    centre and radii of scanning every sample at every step."""
+    _log("case: full descent", cfg)
+    import paper_2403_09990_amd as P
+    b = {"c1": W.config_c1(0), "c2-16k": W.config_c2(0, n_samples=16384),
+         "c3-8": W.config_c3(2, n_inst=8, m_range=(1024, 16384), n_range=(6, 48))}[cfg]
+    gp = _params(n_iters=50)
+    res = PT.run_gpu(b, gp)
+    gp2 = _params(n_iters=50, flags=P.PURSE_FLAG_NO_PRUNING)
+    full = P.megb(res["db"], gp2, res["poses"], res["mask"], res["inst_status"].clone())
+    torch.cuda.synchronize()
+    assert torch.equal(full["trace"], res["trace"])
+    assert torch.equal(full["centre"], res["centre"])
+    assert torch.equal(full["radii"], res["radii"])
+
+
 def test_fp64_polar_path_agrees():
     """Forcing the float64 polar step changes 3D-3D samples by rounding only."""
     _log("case: fp64 polar")
