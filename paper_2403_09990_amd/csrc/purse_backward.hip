@@ -599,33 +599,60 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         for (int k = 0; k < 3; ++k) jadd[tid][k] = a[k];
       }
       __syncthreads();
-      if (tid == 0) {
-        // the serial part: g through the chunk's steps, each step's g kept;
-        // the next step's J_C and term are read while this step is computed
-        D g[3] = {gvec[0], gvec[1], gvec[2]};
-        D jc[9], ja[3];
-        {
-          const int t = i_hi - i_lo;
-          for (int k = 0; k < 9; ++k) jc[k] = jac[t][0][k];
-          for (int k = 0; k < 3; ++k) ja[k] = jadd[t][k];
+      {
+        // g through the chunk's steps: with g_i the cotangent entering step i
+        // (from above), step i leaves J_C^T (g_i + a_i), an affine map F_i of
+        // g_i, and keeps g_i + a_i.  The g_i of all steps come from suffix
+        // compositions S_t = F_t o ... o F_top of the chunk's maps, formed by
+        // a log-depth scan (each level composes with the map d steps below),
+        // the maps exchanged through the J_C slots and gstep.
+        const int n = i_hi - i_lo + 1;
+        D M[9], bv[3], at[3];
+        if (tid < n) {
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = jac[tid][0][3 * c + r];  // J_C^T
+          for (int k = 0; k < 3; ++k) at[k] = jadd[tid][k];
+          for (int r = 0; r < 3; ++r) bv[r] = M[3 * r] * at[0] + M[3 * r + 1] * at[1] + M[3 * r + 2] * at[2];
         }
-        for (int ii = i_hi; ii >= i_lo; --ii) {
-          const int t = ii - i_lo;
-          const int tn = t > 0 ? t - 1 : 0;
-          D jcn[9], jan[3];
-          for (int k = 0; k < 9; ++k) jcn[k] = jac[tn][0][k];
-          for (int k = 0; k < 3; ++k) jan[k] = jadd[tn][k];
-          for (int k = 0; k < 3; ++k) {
-            g[k] += ja[k];
-            gstep[t][k] = g[k];
+        for (int d = 1; d < n; d <<= 1) {
+          __syncthreads();
+          if (tid < n) {
+            for (int k = 0; k < 9; ++k) jac[tid][0][k] = M[k];
+            for (int k = 0; k < 3; ++k) gstep[tid][k] = bv[k];
           }
-          D gn[3];
-          for (int c = 0; c < 3; ++c) gn[c] = jc[c] * g[0] + jc[3 + c] * g[1] + jc[6 + c] * g[2];
-          for (int k = 0; k < 3; ++k) g[k] = gn[k];
-          for (int k = 0; k < 9; ++k) jc[k] = jcn[k];
-          for (int k = 0; k < 3; ++k) ja[k] = jan[k];
+          __syncthreads();
+          if (tid + d < n) {
+            // S_t o S_{t+d}: S_{t+d} (the steps above) first
+            D M2[9], b2[3], Mn[9];
+            for (int k = 0; k < 9; ++k) M2[k] = jac[tid + d][0][k];
+            for (int k = 0; k < 3; ++k) b2[k] = gstep[tid + d][k];
+            for (int r = 0; r < 3; ++r) {
+              for (int c = 0; c < 3; ++c) Mn[3 * r + c] = M[3 * r] * M2[c] + M[3 * r + 1] * M2[3 + c] + M[3 * r + 2] * M2[6 + c];
+              bv[r] += M[3 * r] * b2[0] + M[3 * r + 1] * b2[1] + M[3 * r + 2] * b2[2];
+            }
+            for (int k = 0; k < 9; ++k) M[k] = Mn[k];
+          }
         }
-        for (int k = 0; k < 3; ++k) gvec[k] = g[k];
+        __syncthreads();
+        if (tid < n) {
+          for (int k = 0; k < 9; ++k) jac[tid][0][k] = M[k];
+          for (int k = 0; k < 3; ++k) gstep[tid][k] = bv[k];
+        }
+        __syncthreads();
+        const D g0[3] = {gvec[0], gvec[1], gvec[2]};
+        D gb[3] = {g0[0], g0[1], g0[2]}, gout[3];
+        if (tid + 1 < n) {
+          const D *Mu = jac[tid + 1][0];
+          const D *bu = gstep[tid + 1];
+          for (int r = 0; r < 3; ++r) gb[r] = Mu[3 * r] * g0[0] + Mu[3 * r + 1] * g0[1] + Mu[3 * r + 2] * g0[2] + bu[r];
+        }
+        if (tid == 0)
+          for (int r = 0; r < 3; ++r) gout[r] = M[3 * r] * g0[0] + M[3 * r + 1] * g0[1] + M[3 * r + 2] * g0[2] + bv[r];
+        __syncthreads();
+        if (tid < n)
+          for (int k = 0; k < 3; ++k) gstep[tid][k] = gb[k] + at[k];
+        if (tid == 0)
+          for (int k = 0; k < 3; ++k) gvec[k] = gout[k];
       }
       __syncthreads();
       // rho_{s_i} += J_R^T g_i: each step's term in parallel, then summed per
@@ -647,31 +674,30 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         tslot_c[tid] = -1;
       }
       __syncthreads();
-      // per active sample (one thread each), in step order: the rotation
-      // terms into rho, the translation weights into the cotangent
-      for (int a = tid; a < n_act; a += kBwdBlock) {
-        D r0 = 0, r1 = 0, r2 = 0, w = 0;
-        for (int t0 = kBwdBlock - 8; t0 >= 0; t0 -= 8) {
-          int cs[8], ts[8];
+      // per active sample (one wavefront each): the rotation terms into rho,
+      // the translation weights into the cotangent; lane l sums steps 4l ..
+      // 4l + 3, then a butterfly of fixed shape (the same sums every run)
+      static_assert(kBwdBlock == 4 * 64, "four steps of the chunk per lane");
+      for (int a = wave; a < n_act; a += kBwdWaves) {
+        D v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            cs[u] = cslot[t0 + u];
-            ts[u] = tslot_c[t0 + u];
-          }
-#pragma unroll
-          for (int u = 7; u >= 0; --u) {
-            const int t = t0 + u;
-            const bool m = cs[u] == a;
-            r0 += m ? jadd[t][0] : 0.0;
-            r1 += m ? jadd[t][1] : 0.0;
-            r2 += m ? jadd[t][2] : 0.0;
-            w += ts[u] == a ? twt[t] : 0.0;
-          }
+        for (int u = 3; u >= 0; --u) {
+          const int t = 4 * lane + u;
+          const bool m = cslot[t] == a;
+          v[0] += m ? jadd[t][0] : 0.0;
+          v[1] += m ? jadd[t][1] : 0.0;
+          v[2] += m ? jadd[t][2] : 0.0;
+          v[3] += tslot_c[t] == a ? twt[t] : 0.0;
         }
-        rho[a][0] += r0;
-        rho[a][1] += r1;
-        rho[a][2] += r2;
-        for (int r = 0; r < 3; ++r) cot[a][9 + r] += tbar[r] * w;
+        for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], o, 64);
+        if (lane == 0) {
+          rho[a][0] += v[0];
+          rho[a][1] += v[1];
+          rho[a][2] += v[2];
+          for (int r = 0; r < 3; ++r) cot[a][9 + r] += tbar[r] * v[3];
+        }
       }
       __syncthreads();
     }
