@@ -83,6 +83,9 @@ typedef int32_t purse_status;
                                          trajectory on two lanes (twice the wavefronts, for batches too
                                          small to fill the GPU); results agree with one lane per
                                          trajectory to float32 rounding */
+#define PURSE_FLAG_REPLAY_DESCENT 64  /* purse_megb_backward: replay the MEGB descent from the trace even
+                                         when purse_megb left its checkpoints for this trace in the
+                                         workspace (same results; for testing) */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints
@@ -180,6 +183,8 @@ purse_status purse_sample(const purse_batch *b, const purse_params *p, float *po
  *               index) of each step, rotation then translation; -1 if empty.
  *   inst_status [n_inst] int32: PURSE_INST_EMPTY is OR-ed in for empty instances.
  */
+/* The workspace keeps, for purse_megb_backward, every min(ckpt_every, 16)-th
+ * rotation iterate of each descent with a signature of its trace. */
 purse_status purse_megb(const purse_batch *b, const purse_params *p, const float *poses,
                         const uint8_t *mask, float *centre, double *radii,
                         int64_t *n_feasible, int32_t *trace, int32_t *inst_status,
@@ -193,6 +198,10 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
  * trajectories are recomputed from their Philox counters with checkpoints
  * every ckpt_every iterations and swept backwards, then through the centre
  * fit.
+ *
+ * The descent's iterates come from the checkpoints purse_megb left in the
+ * workspace when their signature matches `trace` (same batch, params and
+ * workspace); otherwise the descent is replayed from `trace`.
  *
  * Inputs: poses, mask, trace as produced by the forward calls;
  *   g_radii  [n_inst][2] double: cotangents of D_hat and d_hat;

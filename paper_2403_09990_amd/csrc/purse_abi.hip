@@ -194,8 +194,9 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
   const purse::DevBatch db = dev_batch(b);
   const purse::DevParams dp = dev_params(p);
   purse::launch_megb(db, dp, poses, mask, at<purse::MegbRec>(ws, L.megb), at<float4>(ws, L.quat),
-                     at<float4>(ws, L.trans), at<float>(ws, L.dref), centre, radii, n_feasible, trace, inst_status,
-                     b->max_samples, b->total_samples, static_cast<hipStream_t>(stream));
+                     at<float4>(ws, L.trans), at<float>(ws, L.dref), at<float4>(ws, L.ckpt), centre, radii,
+                     n_feasible, trace, inst_status, b->max_samples, b->total_samples,
+                     static_cast<hipStream_t>(stream));
   return hip_check(hipGetLastError(), "megb launch");
 }
 
@@ -214,7 +215,8 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
   const purse::DevBatch db = dev_batch(b);
   const purse::DevParams dp = dev_params(p);
   purse::launch_backward(db, dp, poses, mask, trace, g_radii, g_centre, at<purse::InstRec>(ws, L.inst),
-                         at<purse::KpRec>(ws, L.kp), at<purse::BwdRec>(ws, L.bwd), at<double>(ws, L.ckpt),
+                         at<purse::KpRec>(ws, L.kp), at<purse::MegbRec>(ws, L.megb), at<purse::BwdRec>(ws, L.bwd),
+                         at<float4>(ws, L.ckpt),
                          at<float>(ws, L.tan), at<float>(ws, L.contrib), g_centres, g_shapes, g_bounds,
                          static_cast<hipStream_t>(stream));
   return hip_check(hipGetLastError(), "backward launch");

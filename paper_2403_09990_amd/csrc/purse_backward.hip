@@ -1,15 +1,15 @@
 // Backward of purse_sample + purse_megb with every discrete decision held as
 // taken (argmax trace, feasibility and bisection outcomes, clamp sides).
 //
-// 1. k_bwd_megb (one workgroup per instance): the descent is replayed from
-//    the trace with the forward's own float32 steps (so it is linearised at
-//    the iterates the forward computed), keeping every ckpt_every-th rotation
-//    iterate as a quaternion checkpoint; the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
+// 1. k_bwd_megb (one workgroup per instance): the rotation iterates are the
+//    forward's own float32 ones: every ckpt_every-th is a checkpoint that
+//    purse_megb left (or, for a trace it did not produce, that a replay of the
+//    descent from the trace writes); the cotangents of (D_hat, d_hat, R*, t*) are swept back through the
 //    centre projection, the last-iterate average and the T geodesic steps
 //    onto the few samples the trace touches (the active set): the 3x3
 //    tangent Jacobians of the steps are formed in float64 in parallel, a
 //    chunk of steps at a time, each step's iterate recomputed from its
-//    checkpoint, and only their products run serially.
+//    checkpoint, and their products composed by a log-depth scan.
 // 2. k_bwd_frame: per input direction, the tangent of the centre fit, pivot
 //    and anchor (the fit re-run in float64 dual numbers from its start).
 // 3. k_bwd_traj: per (active sample, input direction), the trajectory re-run
@@ -129,8 +129,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
                                                         const uint8_t *__restrict__ mask,
                                                         const int32_t *__restrict__ trace,
                                                         const double *__restrict__ g_radii,
-                                                        const float *__restrict__ g_centre, BwdRec *recs,
-                                                        double *ckpt_all, int ck) {
+                                                        const float *__restrict__ g_centre,
+                                                        MegbRec *megb, BwdRec *recs,
+                                                        float4 *ckpt_all, int ck) {
   __shared__ int act[kMaxActive];
   __shared__ int n_act_s, overflow_s;
   __shared__ double cot[kMaxActive][12];
@@ -150,6 +151,8 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __shared__ double red_v[kBwdWaves];
   __shared__ int red_i[kBwdWaves];
   __shared__ int s0_s, sD_s, sd_s;
+  __shared__ unsigned long long red_h[kBwdWaves];
+  __shared__ int stored_s;
   const int j = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int T = p.megb_iters;
@@ -205,9 +208,28 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       return;
     }
   }
-  if (tid == 0) {
-    n_act_s = 0;
-    overflow_s = 0;
+  // ---- the rotation checkpoints purse_megb left are used when their
+  // signature matches this trace (else the descent is replayed below)
+  {
+    unsigned long long h = 0ull;
+    for (int i = 1 + tid; i <= T; i += kBwdBlock) h += trace_mix(i, tr[2 * (i - 1)]);
+    for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+    if (lane == 0) red_h[wave] = h;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long t = 0ull;
+      for (int w = 0; w < kBwdWaves; ++w) t += red_h[w];
+      const MegbRec &mr = megb[j];
+      stored_s = !(p.flags & PURSE_FLAG_REPLAY_DESCENT) && mr.ck_T == T && mr.ck_every == ck && mr.ck_hash == t;
+      if (!stored_s) {
+        // the replay below rewrites the checkpoints: they then belong to this trace
+        megb[j].ck_hash = t;
+        megb[j].ck_T = 0;  // (set to T once written)
+        megb[j].ck_every = ck;
+      }
+      n_act_s = 0;
+      overflow_s = 0;
+    }
   }
   __syncthreads();
   int last = -1;
@@ -248,48 +270,56 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   auto load_act = [&](int a, D R[9]) {
     for (int q = 0; q < 9; ++q) R[q] = (D)pact[a][q];
   };
-  // ---- replay the descent (wavefront 0: rotation, wavefront 1: translation;
-  // every lane of a wavefront runs the same steps, so 1/i comes from a
-  // per-lane table of the next 64 values).  The rotation chain repeats the
-  // forward's float32 quaternion steps, so the backward linearises at the
-  // iterates the forward computed; every ck-th iterate is kept as a
-  // checkpoint.
-  float *ckq = reinterpret_cast<float *>(ckpt_all + (int64_t)j * ((T + ck - 1) / ck) * 9);
+  // ---- the rotation iterates.  The chain repeats the forward's float32
+  // quaternion steps, so the backward linearises at the iterates the forward
+  // computed; C_0, C_ck, C_2ck, ... are the checkpoints.  With the forward's
+  // checkpoints only the last avg iterates are recomputed (from the one at or
+  // before step T - avg); otherwise wavefront 0 replays the whole descent
+  // (every lane runs the same steps, 1/i and the winners' quaternions from
+  // per-lane tables of the next 64 steps) and writes the checkpoints.
+  float4 *ckq = ckpt_all + (int64_t)j * ckpt_count(T, ck);
+  const bool stored = stored_s != 0;
   if (wave == 0 && !overflow_s) {
-    float4 C = qact[find_active(act, n_act_s, s0)];
     D S[9];
     for (int k = 0; k < 9; ++k) S[k] = 0;
-    // per lane, 1/i and the sample quaternion of step ib + lane
-    int ib = 1, kc = 0, q = 0;
-    float inv_tab = 1.f / (float)(ib + lane);
-    float4 B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
-    for (int i = 1; i <= T; ++i) {
-      if (i - ib == 64) {
-        ib = i;
-        inv_tab = 1.f / (float)(ib + lane);
-        B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
-      }
-      const int l = i - ib;
-      const float inv = readlane_f(inv_tab, l);
-      const float4 B = make_float4(readlane_f(B_tab.x, l), readlane_f(B_tab.y, l), readlane_f(B_tab.z, l),
-                                   readlane_f(B_tab.w, l));
-      if (kc == 0) {  // (i - 1) % ck == 0
-        if (lane == 0) {
-          float *c = ckq + 4 * q;
-          c[0] = C.x;
-          c[1] = C.y;
-          c[2] = C.z;
-          c[3] = C.w;
+    if (stored) {
+      const int q0 = (T - avg) / ck;
+      float4 C = ckq[q0];
+      for (int i = q0 * ck + 1; i <= T; ++i) {
+        C = geodesic_step(C, qact[slot_of(2 * (i - 1))], i, 0);
+        if (i > T - avg) {
+          D Cm[9];
+          rot_of_quat_d(C, Cm);
+          for (int k = 0; k < 9; ++k) S[k] += Cm[k];
         }
-        ++q;
-        kc = ck;
       }
-      --kc;
-      C = geodesic_step_inv(C, B, inv, i, 0);
-      if (i > T - avg) {
-        D Cm[9];
-        rot_of_quat_d(C, Cm);
-        for (int k = 0; k < 9; ++k) S[k] += Cm[k];
+    } else {
+      float4 C = qact[find_active(act, n_act_s, s0)];
+      int ib = 1, kc = 0, q = 0;
+      float inv_tab = 1.f / (float)(ib + lane);
+      float4 B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
+      for (int i = 1; i <= T; ++i) {
+        if (i - ib == 64) {
+          ib = i;
+          inv_tab = 1.f / (float)(ib + lane);
+          B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
+        }
+        const int l = i - ib;
+        const float inv = readlane_f(inv_tab, l);
+        const float4 B = make_float4(readlane_f(B_tab.x, l), readlane_f(B_tab.y, l), readlane_f(B_tab.z, l),
+                                     readlane_f(B_tab.w, l));
+        if (kc == 0) {  // (i - 1) % ck == 0
+          if (lane == 0) ckq[q] = C;
+          ++q;
+          kc = ck;
+        }
+        --kc;
+        C = geodesic_step_inv(C, B, inv, i, 0);
+        if (i > T - avg) {
+          D Cm[9];
+          rot_of_quat_d(C, Cm);
+          for (int k = 0; k < 9; ++k) S[k] += Cm[k];
+        }
       }
     }
     if (lane == 0) {
@@ -299,36 +329,38 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         Rstar[k] = Rs[k];
         Ssum[k] = S[k];
       }
+      if (!stored) megb[j].ck_T = T;
     }
-  } else if (wave == 1 && !overflow_s) {
-    D c[3], acc[3] = {0, 0, 0};
-    for (int r = 0; r < 3; ++r) c[r] = poses[12 * (off + s0) + 9 + r];
-    // per lane, 1/i and the sample translation of step ib + lane
-    int ib = 1;
-    D inv_tab = 1.0 / (D)(ib + lane);
-    const float *Pt = pact[slot_of(2 * min(ib - 1 + lane, T - 1) + 1)];
-    float t_tab[3] = {Pt[9], Pt[10], Pt[11]};
-    for (int i = 1; i <= T; ++i) {
-      if (i - ib == 64) {
-        ib = i;
-        inv_tab = 1.0 / (D)(ib + lane);
-        const float *Pn = pact[slot_of(2 * min(ib - 1 + lane, T - 1) + 1)];
-        for (int r = 0; r < 3; ++r) t_tab[r] = Pn[9 + r];
-      }
-      const int l = i - ib;
-      const long long ib64 = __double_as_longlong(inv_tab);
-      const int lo = __builtin_amdgcn_readlane((int)(ib64 & 0xffffffff), l);
-      const int hi = __builtin_amdgcn_readlane((int)(ib64 >> 32), l);
-      const D inv = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-      const float P[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, readlane_f(t_tab[0], l), readlane_f(t_tab[1], l),
-                           readlane_f(t_tab[2], l)};
-      for (int r = 0; r < 3; ++r) c[r] = c[r] + ((D)P[9 + r] - c[r]) * inv;
-      if (i > T - avg)
-        for (int r = 0; r < 3; ++r) acc[r] += c[r];
-    }
-    if (lane == 0)
-      for (int r = 0; r < 3; ++r) tstar[r] = acc[r] / avg;
   }
+  // ---- t* = (1/avg) sum_{i > T - avg} c_i, where c_i (c_i = c_{i-1} + (t_{s_i}
+  // - c_{i-1}) / i, c_1 = t_{s_1}) is the mean of the first i winners: winner
+  // k carries (1/avg) sum_{i >= max(k, T - avg + 1)} 1/i.  All threads, in
+  // float64, summed in a fixed order.
+  if (!overflow_s) {
+    D hs = 0;
+    for (int k = T - avg + 1; k <= T; ++k) hs += 1.0 / (D)k;
+    D ta[3] = {0.0, 0.0, 0.0};
+    for (int k = 1 + tid; k <= T; k += kBwdBlock) {
+      D w = hs;
+      if (k > T - avg) {
+        w = 0;
+        for (int m = k; m <= T; ++m) w += 1.0 / (D)m;
+      }
+      const float *P = pact[slot_of(2 * (k - 1) + 1)];
+      for (int r = 0; r < 3; ++r) ta[r] += w * (D)P[9 + r];
+    }
+    for (int o = 1; o < 64; o <<= 1)
+      for (int r = 0; r < 3; ++r) ta[r] += __shfl_xor(ta[r], o, 64);
+    if (lane == 0)
+      for (int r = 0; r < 3; ++r) gstep[wave][r] = ta[r];
+  }
+  __syncthreads();
+  if (tid == 0 && !overflow_s)
+    for (int r = 0; r < 3; ++r) {
+      D t = 0;
+      for (int w = 0; w < kBwdWaves; ++w) t += gstep[w][r];
+      tstar[r] = t / avg;
+    }
   __syncthreads();
   // ---- samples realising the radii about (R*, t*)
   D br = -1, bt = -1;
@@ -550,8 +582,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       if (i <= i_hi) {
         // C_{i-1}: the forward's float32 steps from the checkpoint C_{q ck}, q = (i - 1) / ck
         const int q = (i - 1) / ck;
-        const float *cq = ckq + 4 * q;
-        float4 Cf = make_float4(cq[0], cq[1], cq[2], cq[3]);
+        float4 Cf = ckq[q];
         for (int m = q * ck + 1; m <= i - 1; ++m) Cf = geodesic_step(Cf, qact[slot_of(2 * (m - 1))], m, 0);
         D C[9];
         rot_of_quat_d(Cf, C);
@@ -1209,12 +1240,12 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstR
 
 void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                      const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
-                     const KpRec *kp, BwdRec *recs, double *ckpt, float *tan, float *contrib, float *g_centres,
-                     float *g_shapes, float *g_bounds, hipStream_t stream) {
+                     const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
+                     float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream) {
   const int n = b.n_inst;
-  const int ck = p.ckpt_every < kMaxCkpt ? p.ckpt_every : kMaxCkpt;
+  const int ck = ckpt_spacing(p.ckpt_every);
   hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii, g_centre,
-                     recs, ckpt, ck);
+                     megb, recs, ckpt, ck);
   const int max_dirs = 6 * b.max_kp;
   hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, recs, tan, max_dirs);
   dim3 grid(kMaxActive, n, (max_dirs + 63) / 64);

@@ -18,14 +18,19 @@ int64_t sample_grid(int64_t total_samples, int n_inst, int tile);
 void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
                    float *poses, uint8_t *mask, int tile, hipStream_t stream);
 
+// ckpt: the rotation iterates C_0, C_ck, ... of every descent, left for the
+// backward ([n_inst][ckpt_count] quaternions) with their trace signature in rec.
 void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
-                 MegbRec *rec, float4 *quat, float4 *trans, float *dref, float *centre, double *radii,
-                 int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
+                 MegbRec *rec, float4 *quat, float4 *trans, float *dref, float4 *ckpt, float *centre,
+                 double *radii, int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
                  int64_t total_samples, hipStream_t stream);
 
+// megb / ckpt: the records and checkpoints purse_megb left in the workspace,
+// used when the signature matches the given trace; otherwise the descent is
+// replayed from the trace and the checkpoints (and signature) rewritten.
 void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                      const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
-                     const KpRec *kp, BwdRec *recs, double *ckpt, float *tan, float *contrib, float *g_centres,
-                     float *g_shapes, float *g_bounds, hipStream_t stream);
+                     const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
+                     float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream);
 
 }  // namespace purse

@@ -51,11 +51,32 @@ struct MegbRec {
   float4 early_c[2];      // centre after the steps taken by the multi-workgroup first phase
   int32_t early_arrive[2];  // workgroups of the current first-phase step that have finished
   int32_t pad2[2];
+  // rotation iterates C_0, C_ck, C_2ck, ... left for the backward, valid for
+  // the trace whose signature is ck_hash (ck_T = 0: none)
+  unsigned long long ck_hash;
+  int32_t ck_T, ck_every;
 };
+
+// Per-step term of the signature that ties the stored iterates to the
+// rotation argmax trace they belong to: the splitmix64 finaliser of (i, id),
+// summed over the steps (wrapping), so the sum does not depend on order.
+__host__ __device__ inline unsigned long long trace_mix(int i, int id) {
+  unsigned long long z = ((unsigned long long)(unsigned)i << 32) | (unsigned)id;
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Checkpoint spacing of the rotation iterates and their count per instance.
+constexpr int kMaxCkpt = 16;  // largest checkpoint spacing
+__host__ __device__ inline int ckpt_spacing(int ckpt_every) {
+  return ckpt_every < kMaxCkpt ? (ckpt_every > 0 ? ckpt_every : 1) : kMaxCkpt;
+}
+__host__ __device__ inline int ckpt_count(int T, int ck) { return (T + ck - 1) / ck; }
 
 // Backward scratch.
 constexpr int kMaxActive = 256;  // distinct samples the descent may touch per instance
-constexpr int kMaxCkpt = 16;     // largest checkpoint spacing of the descent replay
 constexpr int kMaxDirs = 6 * PURSE_MAX_KP;
 
 struct BwdRec {
@@ -101,9 +122,9 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   o += align_up(8 * (size_t)total_samples);  // one float per sample per chain
   L.bwd = o;
   o += align_up(sizeof(BwdRec) * (size_t)n_inst);
-  const int ck = ckpt_every < kMaxCkpt ? (ckpt_every > 0 ? ckpt_every : 1) : kMaxCkpt;
-  L.ckpt = o;
-  o += align_up(sizeof(double) * 9 * (size_t)n_inst * (size_t)((megb_iters + ck - 1) / ck));
+  const int ck = ckpt_spacing(ckpt_every);
+  L.ckpt = o;  // rotation checkpoints, [n_inst][ckpt_count] quaternions
+  o += align_up(16 * (size_t)n_inst * (size_t)ckpt_count(megb_iters, ck));
   const size_t dirs = 6 * (size_t)max_kp;
   L.tan = o;
   o += align_up(sizeof(float) * 27 * (size_t)n_inst * dirs);

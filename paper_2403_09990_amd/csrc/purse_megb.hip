@@ -105,12 +105,21 @@ __device__ __forceinline__ void wave_argmax(float k, int id, float &wk, int &wi)
 }
 
 // Running sum of the last iterates: rotation matrices (chain 0) or centres.
+// The rotation of the unit quaternion (w, x, y, z) is written out with
+// explicit fused multiply-adds, so that every code path (full scans, shell
+// steps) rounds the sum the same way.
 __device__ __forceinline__ void accumulate_iterate(float4 C, int chain, float acc[9]) {
   if (chain == 0) {
-    float Rm[9];
-    rot_from_quat(C, Rm);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] += Rm[k];
+    const float w = C.x, x = C.y, y = C.z, z = C.w;
+    acc[0] += fmaf(-2.f, fmaf(y, y, z * z), 1.f);
+    acc[1] = fmaf(2.f, fmaf(x, y, -(w * z)), acc[1]);
+    acc[2] = fmaf(2.f, fmaf(x, z, w * y), acc[2]);
+    acc[3] = fmaf(2.f, fmaf(x, y, w * z), acc[3]);
+    acc[4] += fmaf(-2.f, fmaf(x, x, z * z), 1.f);
+    acc[5] = fmaf(2.f, fmaf(y, z, -(w * x)), acc[5]);
+    acc[6] = fmaf(2.f, fmaf(x, z, -(w * y)), acc[6]);
+    acc[7] = fmaf(2.f, fmaf(y, z, w * x), acc[7]);
+    acc[8] += fmaf(-2.f, fmaf(x, x, y * y), 1.f);
   } else {
     acc[0] += C.x;
     acc[1] += C.y;
@@ -159,6 +168,9 @@ __global__ void k_megb_init(int n_inst, MegbRec *rec) {
   rec[j].max_rot = 0ull;
   rec[j].max_trans = 0ull;
   rec[j].early_arrive[0] = rec[j].early_arrive[1] = 0;
+  rec[j].ck_hash = 0ull;
+  rec[j].ck_T = 0;
+  rec[j].ck_every = 0;
 }
 
 // The first kEarlySteps steps move the centre across the whole sample cloud,
@@ -185,8 +197,8 @@ __host__ __device__ inline bool early_phase_applies(int64_t M, int T, int avg, i
 __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__restrict__ sample_off, int64_t total,
                                                             int64_t max_m, const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
-                                                            float *dref_all, int32_t *trace, int T, int avg,
-                                                            int cap, int no_prune, int i) {
+                                                            float *dref_all, int32_t *trace, float4 *ckpt, int ck,
+                                                            int T, int avg, int cap, int no_prune, int i) {
   const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
@@ -259,6 +271,7 @@ __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__res
   __syncthreads();  // red_k / red_i reused
   block_argmax();
   if (tid == 0) {
+    if (chain == 0 && (i - 1) % ck == 0) ckpt[(int64_t)j * ckpt_count(T, ck) + (i - 1) / ck] = C;
     if (bi < M) rec[j].early_c[chain] = geodesic_step(C, D[bi], i, chain);
     trace[((int64_t)j * T + i - 1) * 2 + chain] = bi;
     rec[j].early_arrive[chain] = 0;
@@ -338,8 +351,8 @@ __device__ __forceinline__ int bin_of(float d, float lo, float w) {
 template <int CHAIN, bool PIPE>
 __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *__restrict__ sample_off,
                                           int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
-                                          float *dref_all, int64_t total_samples, int32_t *trace, int T, int avg,
-                                          int cap, int no_prune) {
+                                          float *dref_all, int64_t total_samples, int32_t *trace,
+                                          float4 *ckpt_all, int ck, int T, int avg, int cap, int no_prune) {
   __shared__ float4 st_C;
   __shared__ int st_i;
   __shared__ float st_theta, st_lo, st_w, st_rref;
@@ -362,6 +375,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   const float4 *D = pts + off;
   float *dref = dref_all + chain * total_samples + off;
   int32_t *tr = trace + (int64_t)j * T * 2 + chain;
+  // rotation iterates C_{q ck} for the backward (each step's path leaves the
+  // ones it starts from)
+  float4 *ckq = ckpt_all + (int64_t)j * ckpt_count(T, ck);
   const int first = rec[j].first;
   if (first == INT32_MAX) {
     for (int k = tid; k < T; k += kChainBlock) tr[2 * k] = -1;
@@ -567,6 +583,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             bi = S.red_i[par][w];
           }
         par ^= 1;
+        if (CHAIN == 0 && tid == 0 && (i - 1) % ck == 0) ckq[(i - 1) / ck] = C;
         C = geodesic_step(C, D[bi], i, chain);
         if (tid == 0) tr[2 * (i - 1)] = bi;
         if (i > T - avg && wave == 0) accumulate_iterate(C, chain, acc);
@@ -659,6 +676,8 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           float inv_tab = 1.f / (float)(ib + lane);   // 1/i of step ib + lane
           int trv = 0;                                // winner of step ib + lane
           bool piped = false;
+          int next_ck = (i - 1 + ck - 1) / ck * ck;   // next iterate index kept as a checkpoint
+          int q_next = next_ck / ck;
           // Steps of the segment up to step `end` with WIDTH chunks in the
           // common step and (SHORT) the short sin/cos series of the geodesic
           // step; returns kStageEnds, kGoWide when one-chunk steps often
@@ -742,6 +761,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               const int wi = __builtin_amdgcn_readlane(bi, wl);
               const float4 pt = make_float4(readlane_f(bp_x, wl), readlane_f(bp_y, wl), readlane_f(bp_z, wl),
                                             readlane_f(bp_w, wl));
+              if (CHAIN == 0 && i - 1 == next_ck) {
+                if (lane == 0) ckq[q_next] = C;
+                next_ck += ck;
+                ++q_next;
+              }
               C = geodesic_step_inv<SHORT>(C, pt, inv, chain);
               trv = lane == i - ib ? wi : trv;
               if (ACC) accumulate_iterate(C, chain, acc);
@@ -867,6 +891,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               if (lane < n_r) {
                 pl_C[slot][lane] = cv;
                 pl_W[slot][lane] = pv;
+                // (a checkpoint from a step found wrong later is rewritten
+                // when the step is redone)
+                const int im1 = s_r + lane - 1;
+                if (CHAIN == 0 && im1 % ck == 0) ckq[im1 / ck] = cv;
               }
               if (r == nrounds - 1 && lane == 0) pl_Cend = Cs;
             }
@@ -977,8 +1005,8 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
                                                             const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
-                                                            int32_t *trace, int T, int avg, int cap,
-                                                            int no_prune) {
+                                                            int32_t *trace, float4 *ckpt, int ck, int T, int avg,
+                                                            int cap, int no_prune) {
   extern __shared__ float4 sh_pt[];
   __shared__ unsigned int hist[kBins];
   __shared__ unsigned int cursor[kBins];
@@ -987,9 +1015,11 @@ __global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__res
   __shared__ int red_i[2][kChainWaves];
   const ChainShared S{sh_pt, reinterpret_cast<int *>(sh_pt + cap), hist, cursor, chunk_ub, red_k, red_i};
   if (blockIdx.x & 1)
-    chain_run<1, PIPE>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
+    chain_run<1, PIPE>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
+                       no_prune);
   else
-    chain_run<0, PIPE>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, T, avg, cap, no_prune);
+    chain_run<0, PIPE>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
+                       no_prune);
 }
 
 // float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.
@@ -1040,6 +1070,27 @@ __global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict
   }
 }
 
+// Signature of each instance's rotation trace, stored with the checkpoints
+// the descent left, so that the backward uses them only for this trace.
+__global__ void __launch_bounds__(kBlock) k_megb_sign(const int32_t *__restrict__ trace, MegbRec *rec, int T, int ck) {
+  const int j = blockIdx.x;
+  const int32_t *tr = trace + (int64_t)j * T * 2;
+  unsigned long long h = 0ull;
+  for (int i = 1 + (int)threadIdx.x; i <= T; i += kBlock) h += trace_mix(i, tr[2 * (i - 1)]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+  __shared__ unsigned long long part[kWaves];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0ull;
+    for (int w = 0; w < kWaves; ++w) t += part[w];
+    rec[j].ck_hash = t;
+    rec[j].ck_T = rec[j].first != INT32_MAX ? T : 0;
+    rec[j].ck_every = ck;
+  }
+}
+
 __global__ void k_megb_final(int n_inst, const MegbRec *rec, float *centre, double *radii, int64_t *n_feasible,
                              int32_t *inst_status) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1062,9 +1113,10 @@ __global__ void k_megb_final(int n_inst, const MegbRec *rec, float *centre, doub
 }
 
 void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask, MegbRec *rec,
-                 float4 *quat, float4 *trans, float *dref, float *centre, double *radii, int64_t *n_feasible,
-                 int32_t *trace, int32_t *inst_status, int64_t max_samples, int64_t total_samples,
-                 hipStream_t stream) {
+                 float4 *quat, float4 *trans, float *dref, float4 *ckpt, float *centre, double *radii,
+                 int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
+                 int64_t total_samples, hipStream_t stream) {
+  const int ck = ckpt_spacing(p.ckpt_every);
   const int n = b.n_inst;
   hipLaunchKernelGGL(k_megb_init, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec);
   dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
@@ -1077,7 +1129,7 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
     const dim3 eg((unsigned)((max_samples + kEarlySpan - 1) / kEarlySpan), 2u, (unsigned)n);
     for (int i = 1; i <= kEarlySteps; ++i)
       hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
-                         quat, trans, rec, dref, trace, p.megb_iters, p.megb_avg, cap, no_prune, i);
+                         quat, trans, rec, dref, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
   }
   // Pipelined shell steps trade extra work (every step's argmax checked on
   // other wavefronts) for a shorter chain; they pay while the chains leave
@@ -1088,10 +1140,12 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
     n_cu = 0;
   if (2 * n <= n_cu)
     hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat,
-                       trans, rec, dref, total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
+                       trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune);
   else
     hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples,
-                       quat, trans, rec, dref, total_samples, trace, p.megb_iters, p.megb_avg, cap, no_prune);
+                       quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap,
+                       no_prune);
+  hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, trace, rec, p.megb_iters, ck);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                      poses, mask, rec);
   hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,

@@ -104,6 +104,42 @@ def test_backward_batched_equals_single():
             np.testing.assert_array_equal(a[k0:k1], s)
 
 
+def test_backward_checkpoints_from_the_forward():
+    """The backward takes the rotation iterates from the checkpoints purse_megb
+    left (written by the first-phase kernel, full scans, sequential and
+    pipelined shell steps alike): its gradients equal those of replaying the
+    descent from the trace, bitwise; and for a trace the workspace's
+    checkpoints do not belong to, it replays the descent."""
+    _log("case: backward checkpoints")
+    import paper_2403_09990_amd as P
+    b = W.config_c2(0)
+    gp = P.purse_default_params(n_iters=40)
+    res = PT.run_gpu(b, gp)
+    rng = np.random.default_rng(8)
+    g_radii = rng.normal(size=(1, 2))
+    g_centre = rng.normal(size=(1, 6))
+    stored = _gpu_backward(res, gp, g_radii, g_centre)
+    db = res["db"]
+    # the same descent again, then the backward made to replay it
+    m = P.megb(db, gp, res["poses"], res["mask"], res["inst_status"].clone(), ws=res["ws"])
+    torch.cuda.synchronize()
+    assert torch.equal(m["trace"], res["trace"])
+    replay = _gpu_backward(res, P.purse_default_params(n_iters=40, flags=P.PURSE_FLAG_REPLAY_DESCENT),
+                           g_radii, g_centre)
+    for a, r in zip(stored, replay):
+        np.testing.assert_array_equal(a, r)
+    # another descent (its first rotation winner masked out) leaves its own
+    # checkpoints; the backward of the first trace must not use them
+    mask2 = res["mask"].clone()
+    mask2[int(res["trace"][0, 0, 0])] = 0
+    m2 = P.megb(db, gp, res["poses"], mask2, res["inst_status"].clone(), ws=res["ws"])
+    torch.cuda.synchronize()
+    assert not torch.equal(m2["trace"], res["trace"])
+    again = _gpu_backward(res, gp, g_radii, g_centre)
+    for a, r in zip(stored, again):
+        np.testing.assert_array_equal(a, r)
+
+
 def test_autograd_function():
     """PurseMEGB inside torch.autograd: loss.backward() reproduces the ABI call."""
     _log("case: autograd")
