@@ -17,6 +17,8 @@
 //    with its cotangent.
 // 4. k_bwd_reduce: per direction, the sum over active samples in a fixed
 //    order, scattered into the gradient arrays.
+#include <mutex>
+
 #include "purse_fit.hpp"
 #include "purse_geodesic.hpp"
 #include "purse_launch.hpp"
@@ -851,13 +853,14 @@ struct ObsDual {
 };
 
 // Tangent of the centre, pivot and anchor along one input direction.
+// (It reads nothing k_bwd_megb writes, so the two run concurrently.)
 __global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
-                                                       const KpRec *__restrict__ kprec, const BwdRec *recs,
-                                                       float *tan_all, int max_dirs) {
+                                                       const KpRec *__restrict__ kprec, float *tan_all,
+                                                       int max_dirs) {
   const int j = blockIdx.x;
   const int d = threadIdx.x;
   const InstRec I = inst[j];
-  if ((I.status & 0xFF) != PURSE_INST_OK || recs[j].n_act == 0) return;  // (whole workgroup)
+  if ((I.status & 0xFF) != PURSE_INST_OK) return;  // (whole workgroup)
   const bool is2d = I.kind == PURSE_KIND_2D3D;
   const int dpk = dirs_per_kp(I.kind);
   const int n = I.n_kp;
@@ -1238,16 +1241,65 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstR
   }
 }
 
+namespace {
+
+// One auxiliary stream (default priority) and two events per device, created
+// on first use and kept until the process ends.
+struct Aux {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_aux_mu;
+Aux g_aux[64];
+
+Aux *aux_stream() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  Aux &a = g_aux[dev];
+  if (!a.s) {
+    hipStream_t s = nullptr;
+    hipEvent_t f = nullptr, jn = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&jn, hipEventDisableTiming) != hipSuccess) {
+      if (f) hipEventDestroy(f);
+      hipStreamDestroy(s);
+      return nullptr;
+    }
+    a.s = s;
+    a.fork = f;
+    a.join = jn;
+  }
+  return &a;
+}
+
+}  // namespace
+
 void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                      const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
                      const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
                      float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream) {
   const int n = b.n_inst;
   const int ck = ckpt_spacing(p.ckpt_every);
-  hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii, g_centre,
-                     megb, recs, ckpt, ck);
   const int max_dirs = 6 * b.max_kp;
-  hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, recs, tan, max_dirs);
+  // k_bwd_frame on the device's auxiliary stream, concurrently with
+  // k_bwd_megb (a fork and a join by events, which graph capture records as
+  // edges); on the caller's stream when there is none
+  {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    Aux *a = aux_stream();
+    if (a && hipEventRecord(a->fork, stream) == hipSuccess && hipStreamWaitEvent(a->s, a->fork, 0) == hipSuccess) {
+      hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, a->s, b, p, inst, kp, tan, max_dirs);
+      hipEventRecord(a->join, a->s);
+      hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
+                         g_centre, megb, recs, ckpt, ck);
+      hipStreamWaitEvent(stream, a->join, 0);
+    } else {
+      hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
+                         g_centre, megb, recs, ckpt, ck);
+      hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, tan, max_dirs);
+    }
+  }
   dim3 grid(kMaxActive, n, (max_dirs + 63) / 64);
   // 2D-3D directions on lane groups (every 2D-3D instance, so its gradients
   // do not depend on the batch around it)
