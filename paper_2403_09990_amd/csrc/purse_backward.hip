@@ -31,7 +31,7 @@ namespace {
 constexpr int kBwdBlock = 256;
 constexpr int kBwdWaves = kBwdBlock / 64;
 constexpr int kLdsTrace = 8192;  // descents up to this length are replayed from LDS
-constexpr int kTrajGroup = 4;  // lanes per direction in the 2D-3D tangent kernel
+constexpr int kTrajGroup = 16;  // lanes per direction in the 2D-3D tangent kernel
 static_assert(kMaxActive <= 256, "active-set slots are bytes");
 
 using D = double;
@@ -1010,9 +1010,11 @@ __global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const 
 // wavefronts.  The arithmetic per keypoint is that of gn_pass2d.
 template <int G>
 __device__ __forceinline__ float group_sum(float x) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "lane groups within a row of 16");
   x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
   if (G >= 4) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
   if (G >= 8) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, false));  // half mirror
+  if (G >= 16) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x140, 0xF, 0xF, false));  // row mirror
   return x;
 }
 
@@ -1027,6 +1029,7 @@ __device__ __forceinline__ bool group_and(bool b) {
   v &= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
   if (G >= 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
   if (G >= 8) v &= __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+  if (G >= 16) v &= __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
   return v != 0;
 }
 
