@@ -173,9 +173,10 @@ def main():
     ms_traj = time_events(lambda: do_sample(gp_reuse), args.roofline_reps, stream)
     flops = F.batch_flops(batch, cfg["iters"], gp.n_gn)
     achieved = flops / (ms_traj * 1e-3) / 1e12
-    # the trajectory kernel that carries the workload: the pair-lane variant
-    # when the schedule runs 2D-3D trajectories on two lanes each
-    traj_kernel = "k_sample2d_pair" if gp.flags & P.PURSE_FLAG_PAIR_LANES else "k_sample"
+    # the trajectory kernel that carries the workload: the lane-group variant
+    # when the schedule runs 2D-3D trajectories on two or four lanes each
+    traj_kernel = ("k_sample2d_lanes" if gp.flags & (P.PURSE_FLAG_PAIR_LANES | P.PURSE_FLAG_QUAD_LANES)
+                   else "k_sample")
     traffic = read_traffic(traj_kernel, args.config)
     # forward + backward: the step followed by the gradients of random
     # cotangents of the radii and the centre

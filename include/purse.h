@@ -88,6 +88,8 @@ typedef int32_t purse_status;
                                          trajectory on two lanes (twice the wavefronts, for batches too
                                          small to fill the GPU); results agree with one lane per
                                          trajectory to float32 rounding */
+#define PURSE_FLAG_QUAD_LANES 128     /* purse_sample: as PURSE_FLAG_PAIR_LANES with four lanes per
+                                         trajectory (takes precedence over it) */
 #define PURSE_FLAG_REPLAY_DESCENT 64  /* purse_megb_backward: replay the MEGB descent from the trace even
                                          when purse_megb left its checkpoints for this trace in the
                                          workspace (same results; for testing) */

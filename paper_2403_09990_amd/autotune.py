@@ -4,9 +4,9 @@ The sampler's results do not depend on the schedule: only the workgroup size
 (params.tile: 64, 128 or 256 samples), the tile order (heaviest instances
 first, or instance order with PURSE_FLAG_INSTANCE_ORDER) and, for 2D-3D
 instances of at most 16 keypoints, the keypoint loop (unrolled; the general
-one with PURSE_FLAG_GENERIC_LOOP; two lanes per trajectory with
-PURSE_FLAG_PAIR_LANES) change its speed; the last two change float32 rounding
-only.
+one with PURSE_FLAG_GENERIC_LOOP; two or four lanes per trajectory with
+PURSE_FLAG_PAIR_LANES or PURSE_FLAG_QUAD_LANES) change its speed; the last
+three change float32 rounding only.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -17,14 +17,14 @@ import json
 import os
 from typing import Optional
 
-from . import (PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, purse_default_params,
-               purse_sample)
+from . import (PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES,
+               purse_default_params, purse_sample)
 
 TILES = (64, 128, 256)
 ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
-LOOPS = (0, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_PAIR_LANES)
+LOOPS = (0, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES)
 SMALL_N = 16
-_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES
+_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES | PURSE_FLAG_QUAD_LANES
 
 
 def default_cache_path() -> str:
@@ -78,6 +78,7 @@ def _with(params, tile, flags):
 
 def _name(tile, flags):
     loop = ("generic" if flags & PURSE_FLAG_GENERIC_LOOP else
+            "quad-lanes" if flags & PURSE_FLAG_QUAD_LANES else
             "pair-lanes" if flags & PURSE_FLAG_PAIR_LANES else "unrolled")
     return "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first", loop)
 

@@ -29,6 +29,11 @@ __device__ __forceinline__ int launch_group(const InstRec &I, int flags) {
   return (I.n_kp <= kSmallN && !(flags & PURSE_FLAG_GENERIC_LOOP)) ? 2 : 1;
 }
 
+// Lanes per trajectory of launch group 2.
+__host__ __device__ inline int group_lanes(int flags) {
+  return (flags & PURSE_FLAG_QUAD_LANES) ? 4 : ((flags & PURSE_FLAG_PAIR_LANES) ? 2 : 1);
+}
+
 template <int KIND, int NMAX>
 constexpr int group_of() {
   return KIND == PURSE_KIND_3D3D ? 0 : (NMAX > 0 ? 2 : 1);
@@ -46,8 +51,8 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
   const int tid = threadIdx.x;
   const bool sorted = n <= kMaxSorted && !(flags & PURSE_FLAG_INSTANCE_ORDER);
   for (int kind = 0; kind < kSchedGroups; ++kind) {
-    // samples per tile: one per lane, or one per lane pair in pair mode
-    const int tile = (kind == 2 && (flags & PURSE_FLAG_PAIR_LANES)) ? tile_lanes / 2 : tile_lanes;
+    // samples per tile: one per lane, or one per lane group in the lane-group modes
+    const int tile = kind == 2 ? tile_lanes / group_lanes(flags) : tile_lanes;
     int32_t *order = sched + (size_t)kind * sched_ints(n);
     int32_t *tstart = order + n;
     if (sorted) {
@@ -135,14 +140,15 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   mask[g] = m;
 }
 
-// Pair mode of the unrolled 2D-3D group (PURSE_FLAG_PAIR_LANES): a workgroup
-// of blockDim lanes runs blockDim / 2 trajectories, two lanes each; the
-// instance's keypoint records are staged in LDS first.
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_sample2d_pair(const InstRec *__restrict__ inst,
-                                                       const KpRec *__restrict__ kprec,
-                                                       const int32_t *__restrict__ sched, int n_inst, DevParams p,
-                                                       float *__restrict__ poses, uint8_t *__restrict__ mask) {
+// Lane-group modes of the unrolled 2D-3D group (PURSE_FLAG_PAIR_LANES: G = 2,
+// PURSE_FLAG_QUAD_LANES: G = 4): a workgroup of blockDim lanes runs blockDim / G
+// trajectories, G lanes each; the instance's keypoint records are staged in
+// LDS first.
+template <int NMAX, int G>
+__global__ void __launch_bounds__(256, G == 4 ? 4 : 1) k_sample2d_lanes(const InstRec *__restrict__ inst,
+                                                        const KpRec *__restrict__ kprec,
+                                                        const int32_t *__restrict__ sched, int n_inst, DevParams p,
+                                                        float *__restrict__ poses, uint8_t *__restrict__ mask) {
   __shared__ KpRec kp_s[NMAX];
   const int32_t *order = sched + (size_t)2 * sched_ints(n_inst);
   const int32_t *tstart = order + n_inst;
@@ -162,9 +168,9 @@ __global__ void __launch_bounds__(256) k_sample2d_pair(const InstRec *__restrict
   const bool valid = (I.status & 0xFF) == PURSE_INST_OK;
   if (valid && (int)threadIdx.x < I.n_kp) kp_s[threadIdx.x] = kprec[I.kp_off + threadIdx.x];
   __syncthreads();
-  const int64_t s = (int64_t)(b - tstart[lo]) * (blockDim.x / 2) + (threadIdx.x >> 1);
-  const int q = threadIdx.x & 1;
-  if (s >= I.n_samples) return;  // both lanes of a pair leave together
+  const int64_t s = (int64_t)(b - tstart[lo]) * (blockDim.x / G) + (threadIdx.x / G);
+  const int q = threadIdx.x % G;
+  if (s >= I.n_samples) return;  // the lanes of a group leave together
   const int64_t g = I.sample_off + s;
   float4 *out = reinterpret_cast<float4 *>(poses + 12 * g);
   if (!valid) {
@@ -178,7 +184,7 @@ __global__ void __launch_bounds__(256) k_sample2d_pair(const InstRec *__restrict
   }
   const FrameRef F = frame_ref(I);
   Pose x = initial_pose<float>(F, I.seed, (uint64_t)s, p);
-  const uint8_t m = run_trajectory_pair<NMAX>(I, F, kp_s, q, x, p);
+  const uint8_t m = run_trajectory_lanes<NMAX, G>(I, F, kp_s, q, x, p);
   if (q == 0) {
     out[0] = make_float4(x.R[0], x.R[1], x.R[2], x.R[3]);
     out[1] = make_float4(x.R[4], x.R[5], x.R[6], x.R[7]);
@@ -196,10 +202,14 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
                    float *poses, uint8_t *mask, int tile, hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
   const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
-  if (p.flags & PURSE_FLAG_PAIR_LANES) {
+  if (p.flags & PURSE_FLAG_QUAD_LANES) {
+    const dim3 grid4((unsigned)sample_grid(b.total_samples, b.n_inst, tile / 4));
+    hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 4>), grid4, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                       poses, mask);
+  } else if (p.flags & PURSE_FLAG_PAIR_LANES) {
     const dim3 grid2((unsigned)sample_grid(b.total_samples, b.n_inst, tile / 2));
-    hipLaunchKernelGGL((k_sample2d_pair<kSmallN>), grid2, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p, poses,
-                       mask);
+    hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 2>), grid2, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
+                       poses, mask);
   } else {
     hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst,
                        p, poses, mask);

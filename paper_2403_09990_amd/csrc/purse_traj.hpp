@@ -478,25 +478,33 @@ __device__ __forceinline__ uint8_t run_trajectory(const InstRec &I, const FR &F,
 }
 
 // ---------------------------------------------------------------------------
-// Pair mode (2D-3D, at most NMAX keypoints): the two lanes 2k and 2k + 1 of a
-// wavefront run one trajectory together.  Lane parity q takes the keypoints
-// i = q, q + 2, ...; the normal equations (and the feasibility and depth
-// tests) are combined across the pair by a DPP quad permutation, so both lanes
-// then hold the same sums (addition commutes) and compute the same step.  This
-// halves the keypoint work per lane and doubles the wavefronts of a batch.
-// Keypoint records come from LDS, where each lane reads its own.
-__device__ __forceinline__ float pair_sum(float x) {
-  return x + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+// Lane-group modes (2D-3D, at most NMAX keypoints): G = 2 or 4 adjacent lanes
+// of a wavefront run one trajectory together.  Lane q of the group takes the
+// keypoints i = q, q + G, ...; the normal equations (and the feasibility and
+// depth tests) are combined across the group by DPP quad permutations
+// (butterfly sums), so every lane then holds the same sums (addition commutes)
+// and computes the same step.  This divides the keypoint work per lane by G
+// and multiplies the wavefronts of a batch by G.  Keypoint records come from
+// LDS, where each lane reads its own.
+template <int G>
+__device__ __forceinline__ float lanes_sum(float x) {
+  static_assert(G == 2 || G == 4, "groups within a quad");
+  x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));  // quad_perm [1,0,3,2]
+  if (G == 4) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+  return x;
 }
 
-__device__ __forceinline__ bool pair_and(bool b) {
-  const int v = b ? 1 : 0;
-  return (v & __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false)) != 0;
+template <int G>
+__device__ __forceinline__ bool lanes_and(bool b) {
+  int v = b ? 1 : 0;
+  v &= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if (G == 4) v &= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  return v != 0;
 }
 
-template <bool FIRST, int NMAX>
-__device__ __forceinline__ bool gn_pass2d_pair(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
-                                               float z_min, float tq[NMAX / 2][2], Pose &x) {
+template <bool FIRST, int NMAX, int G>
+__device__ __forceinline__ bool gn_pass2d_lanes(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
+                                                float z_min, float tq[NMAX / G][2], Pose &x) {
   float A[21], g[6];
 #pragma unroll
   for (int k = 0; k < 21; ++k) A[k] = 0.f;
@@ -504,8 +512,8 @@ __device__ __forceinline__ bool gn_pass2d_pair(const KpRec *kp, int n, int q, co
   for (int k = 0; k < 6; ++k) g[k] = 0.f;
   bool ok = true;
 #pragma unroll
-  for (int ii = 0; ii < NMAX / 2; ++ii) {
-    const int i = 2 * ii + q;
+  for (int ii = 0; ii < NMAX / G; ++ii) {
+    const int i = G * ii + q;
     if (i < n) {
       const KpRec k = kp[i];
       float P[3], iz, u, v;
@@ -531,10 +539,10 @@ __device__ __forceinline__ bool gn_pass2d_pair(const KpRec *kp, int n, int q, co
     }
   }
 #pragma unroll
-  for (int k = 0; k < 21; ++k) A[k] = pair_sum(A[k]);
+  for (int k = 0; k < 21; ++k) A[k] = lanes_sum<G>(A[k]);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = pair_sum(g[k]);
-  ok = pair_and(ok);
+  for (int k = 0; k < 6; ++k) g[k] = lanes_sum<G>(g[k]);
+  ok = lanes_and<G>(ok);
   float d[6];
   ok = ok && chol6_solve<float>(A, g, d);
   if (!ok) return false;
@@ -542,25 +550,25 @@ __device__ __forceinline__ bool gn_pass2d_pair(const KpRec *kp, int n, int q, co
   return true;
 }
 
-template <int NMAX>
-__device__ __forceinline__ bool traj2d_pair(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
-                                            int n_iters, int n_gn, float z_min, Pose &x) {
+template <int NMAX, int G>
+__device__ __forceinline__ bool traj2d_lanes(const KpRec *kp, int n, int q, const float K[4], const float oc[3],
+                                             int n_iters, int n_gn, float z_min, Pose &x) {
   for (int it = 0; it < n_iters; ++it) {
-    float tq[NMAX / 2][2];
-    if (!gn_pass2d_pair<true, NMAX>(kp, n, q, K, oc, z_min, tq, x)) return false;
+    float tq[NMAX / G][2];
+    if (!gn_pass2d_lanes<true, NMAX, G>(kp, n, q, K, oc, z_min, tq, x)) return false;
     for (int gs = 1; gs < n_gn; ++gs)
-      if (!gn_pass2d_pair<false, NMAX>(kp, n, q, K, oc, z_min, tq, x)) return false;
+      if (!gn_pass2d_lanes<false, NMAX, G>(kp, n, q, K, oc, z_min, tq, x)) return false;
   }
   return true;
 }
 
-template <int NMAX>
-__device__ __forceinline__ bool feasible2d_pair(const KpRec *kp, int n, int q, const float K[4], const Pose &x,
-                                                float z_min) {
+template <int NMAX, int G>
+__device__ __forceinline__ bool feasible2d_lanes(const KpRec *kp, int n, int q, const float K[4], const Pose &x,
+                                                 float z_min) {
   bool ok = true;
 #pragma unroll
-  for (int ii = 0; ii < NMAX / 2; ++ii) {
-    const int i = 2 * ii + q;
+  for (int ii = 0; ii < NMAX / G; ++ii) {
+    const int i = G * ii + q;
     if (i < n) {
       const KpRec k = kp[i];
       float P[3], iz, u, v;
@@ -570,18 +578,18 @@ __device__ __forceinline__ bool feasible2d_pair(const KpRec *kp, int n, int q, c
       ok = ok && (P[2] > z_min) && (sqrtf(et0 * et0 + et1 * et1) <= k.bt);
     }
   }
-  return pair_and(ok);
+  return lanes_and<G>(ok);
 }
 
-// Pair-mode trajectory: iterations, feasibility test, bisection pull-in.
-template <int NMAX>
-__device__ __forceinline__ uint8_t run_trajectory_pair(const InstRec &I, const FrameRef &F, const KpRec *kp, int q,
-                                                       Pose &x, const DevParams &p) {
+// Lane-group trajectory: iterations, feasibility test, bisection pull-in.
+template <int NMAX, int G>
+__device__ __forceinline__ uint8_t run_trajectory_lanes(const InstRec &I, const FrameRef &F, const KpRec *kp, int q,
+                                                        Pose &x, const DevParams &p) {
   const float oc[3] = {F.oc[0], F.oc[1], F.oc[2]};
-  const bool ok = traj2d_pair<NMAX>(kp, I.n_kp, q, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
+  const bool ok = traj2d_lanes<NMAX, G>(kp, I.n_kp, q, I.K, oc, p.n_iters, p.n_gn, p.z_min, x);
   reorthonormalise(x.R);
   if (!ok) return PURSE_MASK_FAILED;
-  if (feasible2d_pair<NMAX>(kp, I.n_kp, q, I.K, x, p.z_min)) return PURSE_MASK_FEASIBLE;
+  if (feasible2d_lanes<NMAX, G>(kp, I.n_kp, q, I.K, x, p.z_min)) return PURSE_MASK_FEASIBLE;
   if (!I.has_anchor) return 0;
   float Ra[9], ta[3], RtR[9], RaT[9], w[3];
 #pragma unroll
@@ -603,7 +611,7 @@ __device__ __forceinline__ uint8_t run_trajectory_pair(const InstRec &I, const F
     matmul3(Ra, E, m.R);
 #pragma unroll
     for (int r = 0; r < 3; ++r) m.t[r] = ta[r] + mid * (x.t[r] - ta[r]);
-    if (feasible2d_pair<NMAX>(kp, I.n_kp, q, I.K, m, p.z_min))
+    if (feasible2d_lanes<NMAX, G>(kp, I.n_kp, q, I.K, m, p.z_min))
       lo = mid;
     else
       hi = mid;

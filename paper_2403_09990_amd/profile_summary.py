@@ -34,7 +34,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # every header it includes); other kernels: all of csrc/.
 _SAMPLER_SOURCES = ("csrc/purse_sample.hip", "csrc/purse_launch.hpp", "csrc/purse_traj.hpp", "csrc/purse_device.hpp",
                     "csrc/purse_dual.hpp", "csrc/purse_layout.hpp", "../include/purse.h")
-KERNEL_SOURCES = {"k_sample": _SAMPLER_SOURCES, "k_sample2d_pair": _SAMPLER_SOURCES}
+KERNEL_SOURCES = {"k_sample": _SAMPLER_SOURCES, "k_sample2d_lanes": _SAMPLER_SOURCES}
 
 
 def source_hash(kernel=None) -> str:

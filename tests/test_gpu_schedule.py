@@ -80,14 +80,15 @@ def test_unrolled_and_generic_keypoint_loops_agree():
     diff = (a[0] - g[0]).abs().max().item()
     _log("max pose difference", diff)
     assert diff <= 1e-5
-    # two lanes per trajectory: every sample written, the same values to rounding
-    for tile in (64, 256):
-        pr = _run(P, db, P.purse_default_params(n_iters=40, tile=tile, flags=P.PURSE_FLAG_PAIR_LANES))
-        assert not torch.isnan(pr[0]).any() and not (pr[1] == 0xEE).any()
-        assert torch.equal(a[1], pr[1]) and torch.equal(a[2], pr[2])
-        diff = (a[0] - pr[0]).abs().max().item()
-        _log("pair lanes, tile", tile, "max pose difference", diff)
-        assert diff <= 1e-5
+    # two or four lanes per trajectory: every sample written, the same values to rounding
+    for flag, name in ((P.PURSE_FLAG_PAIR_LANES, "pair"), (P.PURSE_FLAG_QUAD_LANES, "quad")):
+        for tile in (64, 256):
+            pr = _run(P, db, P.purse_default_params(n_iters=40, tile=tile, flags=flag))
+            assert not torch.isnan(pr[0]).any() and not (pr[1] == 0xEE).any()
+            assert torch.equal(a[1], pr[1]) and torch.equal(a[2], pr[2])
+            diff = (a[0] - pr[0]).abs().max().item()
+            _log(name, "lanes, tile", tile, "max pose difference", diff)
+            assert diff <= 1e-5
 
 
 def test_autotune_picks_and_caches(tmp_path):
