@@ -252,6 +252,60 @@ __device__ bool gn_centre_2d(const float *Z, const OBS &obs, int n, const float 
   return true;
 }
 
+// gn_centre_2d<double> on a whole wavefront, for up to 64 keypoints: lane i
+// takes keypoint i, the normal equations are summed over the wavefront by an
+// xor butterfly (a fixed order, every lane ends with the same sums) and every
+// lane then takes the same step, so the control flow stays wave-uniform.
+template <typename OBS>
+__device__ bool gn_centre_2d_wave(const float *Z, const OBS &obs, int n, const float K[4], int steps, double z_min,
+                                  double R[9], double t[3]) {
+  const int lane = threadIdx.x & 63;
+  double zb[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i)
+    for (int r = 0; r < 3; ++r) zb[r] += Z[3 * i + r];
+  for (int r = 0; r < 3; ++r) zb[r] /= n;
+  const double Kd[4] = {K[0], K[1], K[2], K[3]};
+  const bool mine = lane < n;
+  const int i = mine ? lane : 0;
+  const double Zi[3] = {Z[3 * i], Z[3 * i + 1], Z[3 * i + 2]};
+  double zi[2], wi[3];
+  obs(i, zi, wi);
+  for (int st = 0; st < steps; ++st) {
+    double o[3];
+    for (int r = 0; r < 3; ++r) o[r] = R[3 * r] * zb[0] + R[3 * r + 1] * zb[1] + R[3 * r + 2] * zb[2] + t[r];
+    double A[21], g[6];
+    for (int k = 0; k < 21; ++k) A[k] = 0.0;
+    for (int k = 0; k < 6; ++k) g[k] = 0.0;
+    double P[3];
+    for (int r = 0; r < 3; ++r) P[r] = R[3 * r] * Zi[0] + R[3 * r + 1] * Zi[1] + R[3 * r + 2] * Zi[2] + t[r];
+    if (__ballot(mine && !(P[2] > z_min)) != 0ull) return false;
+    if (mine) {
+      const double iz = 1.0 / P[2];
+      const double u = Kd[0] * (P[0] * iz) + Kd[2], v = Kd[1] * (P[1] * iz) + Kd[3];
+      const double r0 = zi[0] - u, r1 = zi[1] - v;
+      const double rt0 = wi[0] * r0 + wi[1] * r1, rt1 = wi[2] * r1;
+      const double pt[3] = {P[0] - o[0], P[1] - o[1], P[2] - o[2]};
+      gn_accumulate<double>(P, pt, iz, Kd[0], Kd[1], wi, rt0, rt1, A, g);
+    }
+    for (int m = 1; m < 64; m <<= 1) {
+      for (int k = 0; k < 21; ++k) A[k] += __shfl_xor(A[k], m, 64);
+      for (int k = 0; k < 6; ++k) g[k] += __shfl_xor(g[k], m, 64);
+    }
+    double d[6];
+    if (!chol6_solve<double>(A, g, d)) return false;
+    apply_update<double>(d, o, R, t);
+    double dw = 0.0, dv = 0.0, tm = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      dw = fmax(dw, fabs(d[k]));
+      dv = fmax(dv, fabs(d[3 + k]));
+      tm = fmax(tm, fabs(t[k]));
+    }
+    if (dw <= kCentreTol && dv <= kCentreTol * (1.0 + tm)) break;
+  }
+  const double pz = R[6] * Zi[0] + R[7] * Zi[1] + R[8] * Zi[2] + t[2];
+  return __ballot(mine && !(pz > z_min)) == 0ull;
+}
+
 // Observations of the plain fit: float inputs, whitening from Lambda in float64.
 struct ObsPlain {
   const float *z;

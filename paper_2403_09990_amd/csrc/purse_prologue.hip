@@ -1,8 +1,9 @@
 // Per-instance prologue: validation, keypoint records, centre fit (float64),
 // pivot and feasible anchor.  Two wavefronts per instance: the 2D-3D centre
-// fit is a serial float64 Gauss-Newton iteration from two starts, one start
-// per wavefront (lane 0 of each), so the two run on different SIMDs at once;
-// everything else is serial in lane 0 of wavefront 0.
+// fit is a float64 Gauss-Newton iteration from two starts, one start per
+// wavefront (formed by lane 0, iterated with one keypoint per lane), so the
+// two run on different SIMDs at once; everything else is serial in lane 0 of
+// wavefront 0.
 #include "purse_fit.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
@@ -95,23 +96,36 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
   }
   __syncthreads();
   const int st = stage;
-  if (st == 2 && (tid == 0 || tid == 64)) {
+  if (st == 2) {
     // Gauss-Newton from the DLT (wavefront 0) and from the weak-perspective
-    // fit (wavefront 1)
+    // fit (wavefront 1): lane 0 forms the start, the whole wavefront iterates
     const int f = tid >> 6;
     const int n = b.n_kp[j];
     const int64_t ko = b.kp_off[j];
     const float *a = b.model_pts + 3 * ko, *c = b.centres + 3 * ko;
     const float K[4] = {b.intrinsics[4 * j], b.intrinsics[4 * j + 1], b.intrinsics[4 * j + 2], b.intrinsics[4 * j + 3]};
     const ObsCached obs{c, w_s};
-    double R[9], t[3];
-    bool ok = f == 0 ? dlt_2d(a, c, n, K, R, t) : affine_2d(a, c, n, K, R, t);
-    if (ok) ok = gn_centre_2d<double>(a, obs, n, K, p.centre_gn, (double)p.z_min, R, t);
-    fit_good[f] = ok;
-    if (ok) {
+    if ((tid & 63) == 0) {
+      double R[9], t[3];
+      const bool ok = f == 0 ? dlt_2d(a, c, n, K, R, t) : affine_2d(a, c, n, K, R, t);
+      fit_good[f] = ok;
       for (int k = 0; k < 9; ++k) fit_R[f][k] = R[k];
       for (int k = 0; k < 3; ++k) fit_t[f][k] = t[k];
-      fit_cost[f] = cost_2d_obs(a, obs, n, K, R, t);
+    }
+    __syncthreads();
+    bool ok = fit_good[f] != 0;
+    double R[9], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = fit_R[f][k];
+    for (int k = 0; k < 3; ++k) t[k] = fit_t[f][k];
+    __syncthreads();
+    if (ok) ok = gn_centre_2d_wave(a, obs, n, K, p.centre_gn, (double)p.z_min, R, t);
+    if ((tid & 63) == 0) {
+      fit_good[f] = ok;
+      if (ok) {
+        for (int k = 0; k < 9; ++k) fit_R[f][k] = R[k];
+        for (int k = 0; k < 3; ++k) fit_t[f][k] = t[k];
+        fit_cost[f] = cost_2d_obs(a, obs, n, K, R, t);
+      }
     }
   }
   __syncthreads();
