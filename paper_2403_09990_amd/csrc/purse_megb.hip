@@ -1000,8 +1000,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
 
 // One workgroup of kChainBlock threads per (instance, chain): even blocks
 // run the rotation chain, odd blocks the translation chain.
+// The sequential variant is held to four waves per SIMD (128 VGPRs, a few
+// spills outside the step loop) so that two chains share each compute unit:
+// a chain's steps run in one wavefront, which leaves most issue slots free.
 template <bool PIPE>
-__global__ void __launch_bounds__(kChainBlock) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+__global__ void __launch_bounds__(kChainBlock, PIPE ? 1 : 4) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
                                                             const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
