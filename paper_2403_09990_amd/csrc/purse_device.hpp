@@ -355,8 +355,7 @@ __device__ __forceinline__ bool polar_so3(const T M[9], T R[9], int sweeps) {
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 template <typename T>
-__device__ __forceinline__ bool chol6_solve(const T A[21], const T g[6], T x[6]) {
-  T L[21], dinv[6];
+__device__ __forceinline__ bool chol6_factor(const T A[21], T L[21], T dinv[6]) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     T d = A[tri(j, j)];
@@ -374,6 +373,11 @@ __device__ __forceinline__ bool chol6_solve(const T A[21], const T g[6], T x[6])
       L[tri(i, j)] = v * r;
     }
   }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void chol6_subst(const T L[21], const T dinv[6], const T g[6], T x[6]) {
   T y[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -389,6 +393,38 @@ __device__ __forceinline__ bool chol6_solve(const T A[21], const T g[6], T x[6])
     for (int k = i + 1; k < 6; ++k) v -= L[tri(k, i)] * x[k];
     x[i] = v * dinv[i];
   }
+}
+
+template <typename T>
+__device__ __forceinline__ bool chol6_solve(const T A[21], const T g[6], T x[6]) {
+  T L[21], dinv[6];
+  if (!chol6_factor<T>(A, L, dinv)) return false;
+  chol6_subst<T>(L, dinv, g, x);
+  return true;
+}
+
+// The same solve in dual numbers: the values as above; the derivative of
+// x = A^{-1} g is A^{-1} (g' - A' x), solved with the same factor.
+template <typename T>
+__device__ __forceinline__ bool chol6_solve(const Dual<T> A[21], const Dual<T> g[6], Dual<T> x[6]) {
+  T Av[21], gv[6], xv[6], L[21], dinv[6];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) Av[k] = A[k].v;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) gv[k] = g[k].v;
+  if (!chol6_factor<T>(Av, L, dinv)) return false;
+  chol6_subst<T>(L, dinv, gv, xv);
+  T r[6], xd[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T v = g[i].d;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v -= A[i >= j ? tri(i, j) : tri(j, i)].d * xv[j];
+    r[i] = v;
+  }
+  chol6_subst<T>(L, dinv, r, xd);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) x[k] = Dual<T>(xv[k], xd[k]);
   return true;
 }
 
