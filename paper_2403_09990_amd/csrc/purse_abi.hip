@@ -214,11 +214,12 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
   const purse::WsLayout L = layout_for(b, p);
   const purse::DevBatch db = dev_batch(b);
   const purse::DevParams dp = dev_params(p);
-  purse::launch_backward(db, dp, poses, mask, trace, g_radii, g_centre, at<purse::InstRec>(ws, L.inst),
+  const hipError_t e = purse::launch_backward(db, dp, poses, mask, trace, g_radii, g_centre, at<purse::InstRec>(ws, L.inst),
                          at<purse::KpRec>(ws, L.kp), at<purse::MegbRec>(ws, L.megb), at<purse::BwdRec>(ws, L.bwd),
                          at<float4>(ws, L.ckpt),
                          at<float>(ws, L.tan), at<float>(ws, L.contrib), g_centres, g_shapes, g_bounds,
                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_check(e, "backward stream join");
   return hip_check(hipGetLastError(), "backward launch");
 }
 

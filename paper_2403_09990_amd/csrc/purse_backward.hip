@@ -36,13 +36,6 @@ static_assert(kMaxActive <= 256, "active-set slots are bytes");
 
 using D = double;
 
-__device__ __forceinline__ void mat_t(const D A[9], D B[9]) {
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) B[3 * r + c] = A[3 * c + r];
-}
-
 // C = A^T B
 __device__ __forceinline__ void matmul_tn(const D A[9], const D B[9], D C[9]) {
 #pragma unroll
@@ -1265,8 +1258,8 @@ Aux *aux_stream() {
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
     if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&jn, hipEventDisableTiming) != hipSuccess) {
-      if (f) hipEventDestroy(f);
-      hipStreamDestroy(s);
+      if (f) (void)hipEventDestroy(f);
+      (void)hipStreamDestroy(s);
       return nullptr;
     }
     a.s = s;
@@ -1278,10 +1271,10 @@ Aux *aux_stream() {
 
 }  // namespace
 
-void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
-                     const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
-                     const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
-                     float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream) {
+hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
+                           const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
+                           const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
+                           float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream) {
   const int n = b.n_inst;
   const int ck = ckpt_spacing(p.ckpt_every);
   const int max_dirs = 6 * b.max_kp;
@@ -1293,10 +1286,11 @@ void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, 
     Aux *a = aux_stream();
     if (a && hipEventRecord(a->fork, stream) == hipSuccess && hipStreamWaitEvent(a->s, a->fork, 0) == hipSuccess) {
       hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, a->s, b, p, inst, kp, tan, max_dirs);
-      hipEventRecord(a->join, a->s);
+      hipError_t e = hipEventRecord(a->join, a->s);
       hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
                          g_centre, megb, recs, ckpt, ck);
-      hipStreamWaitEvent(stream, a->join, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, a->join, 0);
+      if (e != hipSuccess) return e;  // no join: nothing that reads the frame tangents is launched
     } else {
       hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
                          g_centre, megb, recs, ckpt, ck);
@@ -1313,6 +1307,7 @@ void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, 
                      max_dirs);
   hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
                      g_shapes, g_bounds);
+  return hipSuccess;
 }
 
 }  // namespace purse

@@ -28,9 +28,11 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
 // megb / ckpt: the records and checkpoints purse_megb left in the workspace,
 // used when the signature matches the given trace; otherwise the descent is
 // replayed from the trace and the checkpoints (and signature) rewritten.
-void launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
-                     const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
-                     const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
-                     float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream);
+// Returns an error (after launching part of the work) if the auxiliary
+// stream's join could not be recorded; launch errors are left to hipGetLastError.
+hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
+                           const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
+                           const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
+                           float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream);
 
 }  // namespace purse
