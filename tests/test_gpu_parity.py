@@ -246,6 +246,23 @@ def test_megb_full_descent_is_exact(cfg):
     assert torch.equal(full["radii"], res["radii"])
 
 
+def test_megb_sequential_variant_is_exact():
+    """A batch with more chains than compute units runs the sequential shell
+    steps (two chains per compute unit): bitwise the trace, centre and radii
+    of scanning every sample at every step."""
+    _log("case: sequential variant, 160 instances")
+    import paper_2403_09990_amd as P
+    b = W.config_c3(4, n_inst=160, m_range=(1024, 4096), n_range=(6, 16))
+    gp = _params(n_iters=20)
+    res = PT.run_gpu(b, gp)
+    gp2 = _params(n_iters=20, flags=P.PURSE_FLAG_NO_PRUNING)
+    full = P.megb(res["db"], gp2, res["poses"], res["mask"], res["inst_status"].clone())
+    torch.cuda.synchronize()
+    assert torch.equal(full["trace"], res["trace"])
+    assert torch.equal(full["centre"], res["centre"])
+    assert torch.equal(full["radii"], res["radii"])
+
+
 def test_fp64_polar_path_agrees():
     """Forcing the float64 polar step changes 3D-3D samples by rounding only."""
     _log("case: fp64 polar")
