@@ -30,8 +30,15 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBins = 256;
 constexpr int kGlobalSteps = 64;
-constexpr int kChainBlock = 512;
+constexpr int kChainBlock = 512;  // threads of a pipelined chain workgroup (the larger variant)
 constexpr int kChainWaves = kChainBlock / 64;
+// Sequential chains run in workgroups of 256 threads with a shell of 1536
+// entries, so that four of them share a compute unit (LDS and 128 VGPRs);
+// pipelined ones need the eight waves and keep the larger shell.
+template <bool PIPE>
+constexpr int chain_block() { return PIPE ? kChainBlock : 256; }
+template <bool PIPE>
+constexpr int chain_cap() { return PIPE ? 3072 : 1536; }
 constexpr int kUnroll = 8;
 constexpr int kCap = 3072;
 constexpr int kMaxChunks = kCap / 64;
@@ -130,28 +137,28 @@ __device__ __forceinline__ void accumulate_iterate(float4 C, int chain, float ac
 __device__ __forceinline__ float wave_max(float v) { return wave_max_key(v); }
 
 // Streams elements [0, M) of src to the workgroup in rounds of
-// kChainBlock * kUnroll elements (element s0 + u * kChainBlock + tid to thread
+// BLOCK * kUnroll elements (element s0 + u * BLOCK + tid to thread
 // tid, past M the pad value).  The loads of the next round are issued before
 // the current round is handed to f(vals, s0), so two rounds are in flight.
 // Loads are unconditional at an index clamped to M - 1 (vector loads, and no
 // branch that would make the wait counts conservative); the pad is selected
 // afterwards.
-template <typename T, typename F>
+template <int BLOCK, typename T, typename F>
 __device__ __forceinline__ void stream_rounds(const T *__restrict__ src, int M, T pad, F &&f) {
-  constexpr int R = kChainBlock * kUnroll;
+  constexpr int R = BLOCK * kUnroll;
   if (M <= 0) return;
   const int tid = threadIdx.x;
   const int last = M - 1;
   T cur[kUnroll];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) cur[u] = src[min(u * kChainBlock + tid, last)];
+  for (int u = 0; u < kUnroll; ++u) cur[u] = src[min(u * BLOCK + tid, last)];
   for (int s0 = 0; s0 < M; s0 += R) {
     T nxt[kUnroll];  // (the last round reloads in-range elements it does not use)
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) nxt[u] = src[min(s0 + R + u * kChainBlock + tid, last)];
+    for (int u = 0; u < kUnroll; ++u) nxt[u] = src[min(s0 + R + u * BLOCK + tid, last)];
     T v[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = s0 + u * kChainBlock + tid < M ? cur[u] : pad;
+    for (int u = 0; u < kUnroll; ++u) v[u] = s0 + u * BLOCK + tid < M ? cur[u] : pad;
     f(v, s0);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
@@ -367,6 +374,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   __shared__ int pl_go;
 
   constexpr int chain = CHAIN;
+  constexpr int BLK = chain_block<PIPE>(), NW = BLK / 64;
   const int j = blockIdx.x >> 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
@@ -380,7 +388,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   float4 *ckq = ckpt_all + (int64_t)j * ckpt_count(T, ck);
   const int first = rec[j].first;
   if (first == INT32_MAX) {
-    for (int k = tid; k < T; k += kChainBlock) tr[2 * k] = -1;
+    for (int k = tid; k < T; k += BLK) tr[2 * k] = -1;
     return;
   }
   const int n_feas = (int)rec[j].n_feasible;
@@ -409,10 +417,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       // -------------------------------------------------------------- rescan
       ++n_rescan;
       float mx = 0.f;
-      stream_rounds(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
+      stream_rounds<BLK>(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          int s = s0 + u * kChainBlock + tid;
+          int s = s0 + u * BLK + tid;
           if (s < M) {
             float d = -1.f;
             if (feasible_pt(a[u], chain)) {
@@ -428,7 +436,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       __syncthreads();
       float rref = 0.f;
 #pragma unroll
-      for (int k = 0; k < kChainWaves; ++k) rref = fmaxf(rref, S.red_k[0][k]);
+      for (int k = 0; k < NW; ++k) rref = fmaxf(rref, S.red_k[0][k]);
       // Shell membership: d >= theta and (coarse) bin >= bstar of the
       // histogram (lo, w); theta = -1 when every feasible sample fits.
       if (tid == 0) {
@@ -448,9 +456,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             __syncthreads();
             break;
           }
-          for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
+          for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
           __syncthreads();
-          stream_rounds(dref, M, -1.f, [&](const float *dd, int) {
+          stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
               if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, wdt)], 1u);
@@ -491,9 +499,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           return d >= 0.f && d >= theta && (theta < 0.f || (d >= lo && bin_of(d, lo, wdt) >= bstar));
         };
         auto fbin = [&](float d) { return fine ? bin_of(d, flo, fw) : kBins - 1; };
-        for (int k = tid; k < kBins; k += kChainBlock) S.hist[k] = 0u;
+        for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
         __syncthreads();
-        stream_rounds(dref, M, -1.f, [&](const float *dd, int) {
+        stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u)
             if (member(dd[u])) atomicAdd(&S.hist[fbin(dd[u])], 1u);
@@ -511,10 +519,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         }
         __syncthreads();
         if (st_mode == 0) {
-          stream_rounds(dref, M, -1.f, [&](const float *dd, int s0) {
+          stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int s0) {
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-              int s = s0 + u * kChainBlock + tid;
+              int s = s0 + u * BLK + tid;
               if (member(dd[u])) {
                 unsigned int pos = atomicAdd(&S.cursor[fbin(dd[u])], 1u);
                 if (pos < (unsigned)cap) {
@@ -528,7 +536,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           // upper bound of d_ref over each chunk of 64 entries: the upper edge
           // of the fine bin holding its first entry (the top bin's is rref)
           const int K = (int)sh_n;
-          for (int c = tid; c * 64 < K && c < kMaxChunks; c += kChainBlock) {
+          for (int c = tid; c * 64 < K && c < kMaxChunks; c += BLK) {
             const unsigned int e = (unsigned)c * 64u;
             unsigned int acc_n = 0;
             int bb = kBins - 1;
@@ -553,10 +561,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       while (i <= i_end) {
         float bk = -1.f;
         int bi = INT32_MAX;
-        stream_rounds(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
+        stream_rounds<BLK>(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            int s = s0 + u * kChainBlock + tid;
+            int s = s0 + u * BLK + tid;
             if (s < M && feasible_pt(a[u], chain)) {
               float k = sqdist(C, a[u], chain);
               if (better(k, s, bk, bi)) {
@@ -577,7 +585,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         bk = S.red_k[par][0];
         bi = S.red_i[par][0];
 #pragma unroll
-        for (int w = 1; w < kChainWaves; ++w)
+        for (int w = 1; w < NW; ++w)
           if (better(S.red_k[par][w], S.red_i[par][w], bk, bi)) {
             bk = S.red_k[par][w];
             bi = S.red_i[par][w];
@@ -904,7 +912,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             const int s_p = s_r - kPipeSteps, n_p = min(kPipeSteps, pend - s_p + 1);
             const int pslot = (r + 2) % 3;
             const int vw = wave < kVerifySkip ? wave - 1 : wave - 2;
-            for (int k = vw; k < n_p; k += kChainWaves - 2) {
+            for (int k = vw; k < n_p; k += NW - 2) {
               const float4 Cv = pl_C[pslot][k];
               const int pid = pl_W[pslot][k];
               const float dC = drift(Cv);
@@ -998,13 +1006,13 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   }
 }
 
-// One workgroup of kChainBlock threads per (instance, chain): even blocks
+// One workgroup of chain_block<PIPE>() threads per (instance, chain): even blocks
 // run the rotation chain, odd blocks the translation chain.
-// The sequential variant is held to four waves per SIMD (128 VGPRs, a few
-// spills outside the step loop) so that two chains share each compute unit:
-// a chain's steps run in one wavefront, which leaves most issue slots free.
+// The sequential variant (four waves, 128 VGPRs, a few spills outside the
+// step loop) lets four chains share each compute unit: a chain's steps run in
+// one wavefront, which leaves most issue slots free.
 template <bool PIPE>
-__global__ void __launch_bounds__(kChainBlock, PIPE ? 1 : 4) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+__global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
                                                             const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
@@ -1125,7 +1133,16 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
   hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      mask, rec, quat, trans);
-  const int cap = kCap;
+  // Pipelined shell steps trade extra work (every step's argmax checked on
+  // other wavefronts) for a shorter chain; they pay while the chains leave
+  // compute units idle, i.e. while there are at most as many chain
+  // workgroups as compute units.  The two variants keep shells of different
+  // capacities, which the first-phase kernel must know.
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    n_cu = 0;
+  const bool pipe = 2 * n <= n_cu;
+  const int cap = pipe ? chain_cap<true>() : chain_cap<false>();
   const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
   const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
   if (early_phase_applies(max_samples, p.megb_iters, p.megb_avg, no_prune)) {
@@ -1134,20 +1151,14 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
       hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
                          quat, trans, rec, dref, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
   }
-  // Pipelined shell steps trade extra work (every step's argmax checked on
-  // other wavefronts) for a shorter chain; they pay while the chains leave
-  // compute units idle, i.e. while there are at most as many chain
-  // workgroups as compute units.
-  int dev = 0, n_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    n_cu = 0;
-  if (2 * n <= n_cu)
-    hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples, quat,
-                       trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune);
+  if (pipe)
+    hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(chain_block<true>()), lds, stream, b.sample_off,
+                       max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
+                       cap, no_prune);
   else
-    hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(kChainBlock), lds, stream, b.sample_off, max_samples,
-                       quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap,
-                       no_prune);
+    hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(chain_block<false>()), lds, stream, b.sample_off,
+                       max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
+                       cap, no_prune);
   hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, trace, rec, p.megb_iters, ck);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                      poses, mask, rec);
