@@ -55,6 +55,10 @@ struct MegbRec {
   // the trace whose signature is ck_hash (ck_T = 0: none)
   unsigned long long ck_hash;
   int32_t ck_T, ck_every;
+  // best (key, id) of the current first-phase step per chain, packed as
+  // key bits << 32 | ~id so that an unsigned max keeps the larger key and,
+  // on equal keys, the lower id (0: none yet)
+  unsigned long long early_best[2];
 };
 
 // Per-step term of the signature that ties the stored iterates to the

@@ -175,6 +175,7 @@ __global__ void k_megb_init(int n_inst, MegbRec *rec) {
   rec[j].max_rot = 0ull;
   rec[j].max_trans = 0ull;
   rec[j].early_arrive[0] = rec[j].early_arrive[1] = 0;
+  rec[j].early_best[0] = rec[j].early_best[1] = 0ull;
   rec[j].ck_hash = 0ull;
   rec[j].ck_T = 0;
   rec[j].ck_every = 0;
@@ -198,31 +199,33 @@ __host__ __device__ inline bool early_phase_applies(int64_t M, int T, int avg, i
 // feasible samples outnumber the shell capacity (else the shell holds them
 // all and the chain's workgroup needs no full scans).  Workgroup b of
 // (instance j, chain c) finds the farthest of its kEarlySpan samples from the
-// current centre and leaves (key, id) in the scratch of the chain's d_ref
-// array; the last workgroup to finish (arrival counter) reduces those, takes
-// the geodesic step and records the trace, and resets the counter.
+// current centre and folds (key, id) into the chain's packed maximum with one
+// 64-bit atomic; the last workgroup to finish (arrival counter) takes the
+// maximum and clears it, takes the geodesic step, records the trace and
+// resets the counter.  The sample loads are issued before the per-instance
+// record is read, so their latency overlaps that read.
 __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__restrict__ sample_off, int64_t total,
                                                             int64_t max_m, const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
-                                                            float *dref_all, int32_t *trace, float4 *ckpt, int ck,
+                                                            int32_t *trace, float4 *ckpt, int ck,
                                                             int T, int avg, int cap, int no_prune, int i) {
   const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
   sample_range(sample_off, j, total, max_m, off, M64);
   if (!early_phase_applies(M64, T, avg, no_prune)) return;
-  const int M = (int)M64;
-  const int first = rec[j].first;
-  if (first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
+  const int M = (int)M64;  // >= kBigInstance here
   const int nb = (M + kEarlySpan - 1) / kEarlySpan;
   if (b >= nb) return;
   const float4 *D = (chain ? trans : quat) + off;
-  const float4 C = i == 1 ? D[first] : rec[j].early_c[chain];
-  float bk = -1.f;
-  int bi = INT32_MAX;
   float4 a[kEarlyPer];
 #pragma unroll
   for (int u = 0; u < kEarlyPer; ++u) a[u] = D[min(b * kEarlySpan + u * kEarlyBlock + tid, M - 1)];
+  const int first = rec[j].first;
+  if (first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
+  const float4 C = i == 1 ? D[first] : rec[j].early_c[chain];
+  float bk = -1.f;
+  int bi = INT32_MAX;
 #pragma unroll
   for (int u = 0; u < kEarlyPer; ++u) {
     const int s = b * kEarlySpan + u * kEarlyBlock + tid;
@@ -235,7 +238,6 @@ __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__res
   }
   __shared__ float red_k[kEarlyBlock / 64];
   __shared__ int red_i[kEarlyBlock / 64];
-  __shared__ int last;
   auto block_argmax = [&]() {
     float wk;
     int wi;
@@ -255,34 +257,21 @@ __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__res
       }
   };
   block_argmax();
-  float *part = dref_all + (int64_t)chain * total + off;  // 2 nb floats <= M
-  if (tid == 0) {
-    part[2 * b] = bk;
-    part[2 * b + 1] = __int_as_float(bi);
-    __threadfence();
-    last = atomicAdd(&rec[j].early_arrive[chain], 1) == nb - 1;
-  }
-  __syncthreads();
-  if (!last) return;
+  if (tid != 0) return;
+  // keys are >= 0 (no NaN is ever selected; a -0 is taken as +0, which it
+  // equals), so their bit patterns order as the values do
+  if (bi != INT32_MAX)
+    atomicMax(&rec[j].early_best[chain], ((unsigned long long)(__float_as_uint(bk) & 0x7fffffffu) << 32) |
+                                             (unsigned long long)(~(unsigned)bi));
   __threadfence();
-  bk = -1.f;
-  bi = INT32_MAX;
-  for (int k = tid; k < nb; k += kEarlyBlock) {
-    const float pk = part[2 * k];
-    const int pi = __float_as_int(part[2 * k + 1]);
-    if (better(pk, pi, bk, bi)) {
-      bk = pk;
-      bi = pi;
-    }
-  }
-  __syncthreads();  // red_k / red_i reused
-  block_argmax();
-  if (tid == 0) {
-    if (chain == 0 && (i - 1) % ck == 0) ckpt[(int64_t)j * ckpt_count(T, ck) + (i - 1) / ck] = C;
-    if (bi < M) rec[j].early_c[chain] = geodesic_step(C, D[bi], i, chain);
-    trace[((int64_t)j * T + i - 1) * 2 + chain] = bi;
-    rec[j].early_arrive[chain] = 0;
-  }
+  if (atomicAdd(&rec[j].early_arrive[chain], 1) != nb - 1) return;
+  __threadfence();
+  const unsigned long long best = atomicExch(&rec[j].early_best[chain], 0ull);
+  bi = best ? (int)~(unsigned)(best & 0xffffffffull) : INT32_MAX;
+  if (chain == 0 && (i - 1) % ck == 0) ckpt[(int64_t)j * ckpt_count(T, ck) + (i - 1) / ck] = C;
+  if (bi < M) rec[j].early_c[chain] = geodesic_step(C, D[bi], i, chain);
+  trace[((int64_t)j * T + i - 1) * 2 + chain] = bi;
+  rec[j].early_arrive[chain] = 0;
 }
 
 // Per sample: quaternion (w >= 0; w = -2 marks an infeasible sample) and
@@ -1149,7 +1138,7 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
     const dim3 eg((unsigned)((max_samples + kEarlySpan - 1) / kEarlySpan), 2u, (unsigned)n);
     for (int i = 1; i <= kEarlySteps; ++i)
       hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
-                         quat, trans, rec, dref, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
+                         quat, trans, rec, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
   }
   if (pipe)
     hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(chain_block<true>()), lds, stream, b.sample_off,

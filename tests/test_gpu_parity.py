@@ -246,9 +246,36 @@ def test_megb_full_descent_is_exact(cfg):
     assert torch.equal(full["radii"], res["radii"])
 
 
+def test_megb_ties_take_the_lowest_id():
+    """Every sample of a 40,000-sample instance copied to id + 20,000 (another
+    workgroup of the first phase): each step's farthest sample is tied with
+    its copy, and the first phase (packed maximum), the shell steps and the
+    full scan all take the lower id, with bitwise the same trace, centre and
+    radii."""
+    _log("case: ties, 40000 samples")
+    import paper_2403_09990_amd as P
+    m, h = 40000, 20000
+    b = W.config_c2(1, n_samples=m)
+    gp = _params(n_iters=40, megb_iters=1024)
+    res = PT.run_gpu(b, gp, with_megb=False)
+    poses, mask = res["poses"].clone(), res["mask"].clone()
+    poses[h:] = poses[:h]
+    mask[h:] = mask[:h]
+    assert int((mask[:h] & 1).sum()) > 2 * 3072  # the first phase applies
+    pr = P.megb(res["db"], gp, poses, mask, res["inst_status"].clone())
+    gp2 = _params(n_iters=40, megb_iters=1024, flags=P.PURSE_FLAG_NO_PRUNING)
+    full = P.megb(res["db"], gp2, poses, mask, res["inst_status"].clone())
+    torch.cuda.synchronize()
+    tr = pr["trace"][0].cpu().numpy()
+    assert (tr >= 0).all() and (tr < h).all()
+    assert torch.equal(full["trace"], pr["trace"])
+    assert torch.equal(full["centre"], pr["centre"])
+    assert torch.equal(full["radii"], pr["radii"])
+
+
 def test_megb_sequential_variant_is_exact():
     """A batch with more chains than compute units runs the sequential shell
-    steps (two chains per compute unit): bitwise the trace, centre and radii
+    steps (four chains per compute unit): bitwise the trace, centre and radii
     of scanning every sample at every step."""
     _log("case: sequential variant, 160 instances")
     import paper_2403_09990_amd as P
