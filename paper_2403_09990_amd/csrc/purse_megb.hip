@@ -861,6 +861,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 // 0..7) with the keys and tie rule of the full argmax, near
                 // convergence the candidates being almost equidistant
                 const float u = sqdist(Cs, cand_p, chain);
+                // the step toward every candidate, one per lane, in parallel
+                // with the argmax (and sharing the chords of the keys): the
+                // winner's lane holds bitwise the step toward the winner
+                const float4 Cn = geodesic_step_inv<true>(Cs, cand_p, inv, chain);
                 int ub = __float_as_int(u);
                 ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
                 ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
@@ -878,12 +882,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 }
                 const int wl = (int)__ffsll((long long)tie) - 1;
                 const int pid = __builtin_amdgcn_readlane(cand_id, wl);
-                const float4 pp = make_float4(readlane_f(cand_p.x, wl), readlane_f(cand_p.y, wl),
-                                              readlane_f(cand_p.z, wl), readlane_f(cand_p.w, wl));
                 const bool mine = lane == k;
                 cv = make_float4(mine ? Cs.x : cv.x, mine ? Cs.y : cv.y, mine ? Cs.z : cv.z, mine ? Cs.w : cv.w);
                 pv = mine ? pid : pv;
-                Cs = geodesic_step_inv<true>(Cs, pp, inv, chain);
+                Cs = make_float4(readlane_f(Cn.x, wl), readlane_f(Cn.y, wl), readlane_f(Cn.z, wl), readlane_f(Cn.w, wl));
               }
               if (lane < n_r) {
                 pl_C[slot][lane] = cv;
