@@ -77,34 +77,62 @@ __device__ __forceinline__ float atan_eighth(float w) {
 // sin(h/i) = 0 and no move (sin h is clamped away from 0 for that case).
 // inv is 1/i, correctly rounded; SMALL (i >= kShortSeriesStep) selects the
 // short sin/cos series.
+// The rotation step in three stages, which geodesic_step_inv composes and
+// which a caller may interleave with other work: the chords' lengths from
+// x = |a - b|^2 and y = |a + b|^2 ...
+struct RotChords {
+  float xs, rx, ry;  // |a - b'|^2, |a - b'|, |a + b'|
+  bool flip;         // a . b < 0: b' = -b
+};
+__device__ __forceinline__ RotChords rot_chords(float x, float y) {
+  RotChords c;
+  c.flip = x > y;
+  c.xs = c.flip ? y : x;
+  const float ys = c.flip ? x : y;
+  c.rx = __builtin_amdgcn_sqrtf(c.xs);
+  c.ry = __builtin_amdgcn_sqrtf(ys);
+  return c;
+}
+// ... the angle h / i of the step ...
+__device__ __forceinline__ float rot_step_angle(const RotChords &c, float inv) {
+  const float quarter = atan_eighth(c.rx * __builtin_amdgcn_rcpf(2.f + c.ry));  // h / 4
+  return (4.f * quarter) * inv;
+}
+// ... and the interpolation itself, renormalised.
 template <bool SMALL>
-__device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int chain) {
-  // (explicit fused multiply-adds: every caller rounds the step the same way)
-  if (chain == 1) return make_float4(fmaf(b.x - a.x, inv, a.x), fmaf(b.y - a.y, inv, a.y), fmaf(b.z - a.z, inv, a.z), 1.f);
-  const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
-  const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
-  const float x = fmaf(m3, m3, fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));  // |a - b|^2
-  const float y = fmaf(p3, p3, fmaf(p2, p2, fmaf(p1, p1, p0 * p0)));  // |a + b|^2
-  const bool flip = x > y;                                // a . b < 0: use b' = -b
-  const float xs = flip ? y : x;                          // |a - b'|^2
-  const float ys = flip ? x : y;                          // |a + b'|^2
-  const float rx = __builtin_amdgcn_sqrtf(xs), ry = __builtin_amdgcn_sqrtf(ys);
-  const float quarter = atan_eighth(rx * __builtin_amdgcn_rcpf(2.f + ry));  // h / 4
-  const float th = (4.f * quarter) * inv;
+__device__ __forceinline__ float4 rot_interp(const RotChords &c, float th, float4 a, float4 b) {
   float st, ct;
   if (SMALL)
     sincos_small(th, st, ct);  // sin, cos of h / i
   else
     sincos_quadrant(th, st, ct);
-  const float sh = (0.5f * rx) * ry;                      // sin h
-  const float chh = fmaf(-0.5f, xs, 1.f);                 // cos h
+  const float sh = (0.5f * c.rx) * c.ry;                  // sin h
+  const float chh = fmaf(-0.5f, c.xs, 1.f);               // cos h
   const float cb = st * __builtin_amdgcn_rcpf(fmaxf(sh, 1e-30f));
   const float ca = fmaf(-chh, cb, ct);
-  const float cbs = flip ? -cb : cb;
+  const float cbs = c.flip ? -cb : cb;
   const float4 q = make_float4(fmaf(cbs, b.x, ca * a.x), fmaf(cbs, b.y, ca * a.y), fmaf(cbs, b.z, ca * a.z),
                                fmaf(cbs, b.w, ca * a.w));
   const float nn = __builtin_amdgcn_rsqf(fmaf(q.w, q.w, fmaf(q.z, q.z, fmaf(q.y, q.y, q.x * q.x))));  // |q| ~ 1
   return make_float4(q.x * nn, q.y * nn, q.z * nn, q.w * nn);
+}
+
+// |a - b|^2 and |a + b|^2 of two quaternions, formed directly.
+__device__ __forceinline__ void rot_chord_sq(float4 a, float4 b, float &x, float &y) {
+  const float m0 = a.x - b.x, m1 = a.y - b.y, m2 = a.z - b.z, m3 = a.w - b.w;
+  const float p0 = a.x + b.x, p1 = a.y + b.y, p2 = a.z + b.z, p3 = a.w + b.w;
+  x = fmaf(m3, m3, fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));
+  y = fmaf(p3, p3, fmaf(p2, p2, fmaf(p1, p1, p0 * p0)));
+}
+
+template <bool SMALL>
+__device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int chain) {
+  // (explicit fused multiply-adds: every caller rounds the step the same way)
+  if (chain == 1) return make_float4(fmaf(b.x - a.x, inv, a.x), fmaf(b.y - a.y, inv, a.y), fmaf(b.z - a.z, inv, a.z), 1.f);
+  float x, y;
+  rot_chord_sq(a, b, x, y);
+  const RotChords c = rot_chords(x, y);
+  return rot_interp<SMALL>(c, rot_step_angle(c, inv), a, b);
 }
 
 __device__ __forceinline__ float4 geodesic_step_inv(float4 a, float4 b, float inv, int i, int chain) {

@@ -860,15 +860,42 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 // predicted winner: the argmax over the candidates (lanes
                 // 0..7) with the keys and tie rule of the full argmax, near
                 // convergence the candidates being almost equidistant
-                const float u = sqdist(Cs, cand_p, chain);
-                // the step toward every candidate, one per lane, in parallel
-                // with the argmax (and sharing the chords of the keys): the
-                // winner's lane holds bitwise the step toward the winner
-                const float4 Cn = geodesic_step_inv<true>(Cs, cand_p, inv, chain);
-                int ub = __float_as_int(u);
-                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-                ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x141, 0xF, 0xF, false));  // row_half_mirror
+                // The step toward every candidate, one per lane, alongside
+                // the argmax (sharing the chords of the keys): the winner's
+                // lane holds bitwise the step toward the winner.  For the
+                // rotation chain the stages of the step are placed between
+                // those of the argmax's reduction (scheduling barriers), so
+                // that the two dependent chains overlap in the one wave.
+                float u;
+                float4 Cn;
+                int ub;
+                if constexpr (CHAIN == 0) {
+                  float x, y;
+                  rot_chord_sq(Cs, cand_p, x, y);
+                  u = (2.f * x) * y;  // the key of sqdist
+                  ub = __float_as_int(u);
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+                  // (the empty asm statements keep each stage where it is
+                  // written: without them the compiler moves the step's
+                  // stages below the argmax, to their first use)
+                  RotChords rc = rot_chords(x, y);
+                  __asm__ volatile("" : "+v"(rc.xs), "+v"(rc.rx), "+v"(rc.ry));
+                  __builtin_amdgcn_sched_barrier(0);
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+                  float th = rot_step_angle(rc, inv);
+                  __asm__ volatile("" : "+v"(th));
+                  __builtin_amdgcn_sched_barrier(0);
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x141, 0xF, 0xF, false));  // row_half_mirror
+                  Cn = rot_interp<true>(rc, th, Cs, cand_p);
+                  __asm__ volatile("" : "+v"(Cn.x), "+v"(Cn.y), "+v"(Cn.z), "+v"(Cn.w));
+                } else {
+                  u = sqdist(Cs, cand_p, chain);
+                  Cn = geodesic_step_inv<true>(Cs, cand_p, inv, chain);
+                  ub = __float_as_int(u);
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0xB1, 0xF, 0xF, false));
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x4E, 0xF, 0xF, false));
+                  ub = max(ub, __builtin_amdgcn_update_dpp(INT32_MIN, ub, 0x141, 0xF, 0xF, false));
+                }
                 const int umax = __builtin_amdgcn_readlane(ub, 0);
                 const bool at_max = __float_as_int(u) == umax;
                 unsigned long long tie = __ballot(at_max) & 0xFFull;
