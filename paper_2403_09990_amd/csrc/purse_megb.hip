@@ -143,25 +143,25 @@ __device__ __forceinline__ float wave_max(float v) { return wave_max_key(v); }
 // Loads are unconditional at an index clamped to M - 1 (vector loads, and no
 // branch that would make the wait counts conservative); the pad is selected
 // afterwards.
-template <int BLOCK, typename T, typename F>
+template <int BLOCK, int U = kUnroll, typename T, typename F>
 __device__ __forceinline__ void stream_rounds(const T *__restrict__ src, int M, T pad, F &&f) {
-  constexpr int R = BLOCK * kUnroll;
+  constexpr int R = BLOCK * U;
   if (M <= 0) return;
   const int tid = threadIdx.x;
   const int last = M - 1;
-  T cur[kUnroll];
+  T cur[U];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) cur[u] = src[min(u * BLOCK + tid, last)];
+  for (int u = 0; u < U; ++u) cur[u] = src[min(u * BLOCK + tid, last)];
   for (int s0 = 0; s0 < M; s0 += R) {
-    T nxt[kUnroll];  // (the last round reloads in-range elements it does not use)
+    T nxt[U];  // (the last round reloads in-range elements it does not use)
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) nxt[u] = src[min(s0 + R + u * BLOCK + tid, last)];
-    T v[kUnroll];
+    for (int u = 0; u < U; ++u) nxt[u] = src[min(s0 + R + u * BLOCK + tid, last)];
+    T v[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = s0 + u * BLOCK + tid < M ? cur[u] : pad;
+    for (int u = 0; u < U; ++u) v[u] = s0 + u * BLOCK + tid < M ? cur[u] : pad;
     f(v, s0);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
   }
 }
 
@@ -364,6 +364,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
 
   constexpr int chain = CHAIN;
   constexpr int BLK = chain_block<PIPE>(), NW = BLK / 64;
+  // elements per thread and round in the passes over d_ref: the pipelined
+  // variant has the registers to keep more loads in flight, which these
+  // latency-bound passes of one workgroup need
+  constexpr int UF = PIPE ? 32 : kUnroll;
   const int j = blockIdx.x >> 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
@@ -447,9 +451,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           }
           for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
           __syncthreads();
-          stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int) {
+          stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
+            for (int u = 0; u < UF; ++u)
               if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, wdt)], 1u);
           });
           __syncthreads();
@@ -490,9 +494,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         auto fbin = [&](float d) { return fine ? bin_of(d, flo, fw) : kBins - 1; };
         for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
         __syncthreads();
-        stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int) {
+        stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u)
+          for (int u = 0; u < UF; ++u)
             if (member(dd[u])) atomicAdd(&S.hist[fbin(dd[u])], 1u);
         });
         __syncthreads();
@@ -508,19 +512,20 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         }
         __syncthreads();
         if (st_mode == 0) {
-          stream_rounds<BLK>(dref, M, -1.f, [&](const float *dd, int s0) {
+          // the ids first; the points are gathered afterwards in one pass
+          // over the shell, all loads in flight at once
+          stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int s0) {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < UF; ++u) {
               int s = s0 + u * BLK + tid;
               if (member(dd[u])) {
                 unsigned int pos = atomicAdd(&S.cursor[fbin(dd[u])], 1u);
-                if (pos < (unsigned)cap) {
-                  S.pt[pos] = D[s];
-                  S.id[pos] = s;
-                }
+                if (pos < (unsigned)cap) S.id[pos] = s;
               }
             }
           });
+          __syncthreads();
+          for (int e = tid; e < (int)sh_n; e += BLK) S.pt[e] = D[S.id[e]];
           __syncthreads();
           // upper bound of d_ref over each chunk of 64 entries: the upper edge
           // of the fine bin holding its first entry (the top bin's is rref)
