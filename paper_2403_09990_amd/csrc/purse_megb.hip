@@ -339,8 +339,14 @@ struct ChainShared {
 };
 
 // Bin of distance d in a histogram of kBins bins of width w from lo.
-__device__ __forceinline__ int bin_of(float d, float lo, float w) {
-  int b = (int)((d - lo) / w);
+// Bin of d among kBins bins of width 1 / rw from lo (rw the reciprocal of
+// the width, so a pass over every sample takes no division).  The rounding of
+// the product can move d by one bin near an edge, which shifts the bins'
+// edges as bounds by about 1e-7 of the distance, far inside the shell
+// checks' slack; every pass uses this same function, so counts and members
+// agree.
+__device__ __forceinline__ int bin_of(float d, float lo, float rw) {
+  int b = (int)((d - lo) * rw);
   return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
 }
 
@@ -451,10 +457,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           }
           for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
           __syncthreads();
+          const float rw = 1.f / wdt;
           stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
 #pragma unroll
             for (int u = 0; u < UF; ++u)
-              if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, wdt)], 1u);
+              if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, rw)], 1u);
           });
           __syncthreads();
           if (tid == 0) {
@@ -488,10 +495,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         const float flo = fmaxf(theta, 0.f);
         const float fw = (rref - flo) / (float)kBins;
         const bool fine = fw > 0.f;
+        const float rw = wdt > 0.f ? 1.f / wdt : 0.f, rfw = fine ? 1.f / fw : 0.f;
         auto member = [&](float d) {
-          return d >= 0.f && d >= theta && (theta < 0.f || (d >= lo && bin_of(d, lo, wdt) >= bstar));
+          return d >= 0.f && d >= theta && (theta < 0.f || (d >= lo && bin_of(d, lo, rw) >= bstar));
         };
-        auto fbin = [&](float d) { return fine ? bin_of(d, flo, fw) : kBins - 1; };
+        auto fbin = [&](float d) { return fine ? bin_of(d, flo, rfw) : kBins - 1; };
         for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
         __syncthreads();
         stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
