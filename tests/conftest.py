@@ -27,3 +27,21 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _single_threaded_oracle(request):
+    """CPU tests run the float64 oracle on one thread, so that its reductions
+    and LAPACK calls round the same way on every run (with several threads
+    the split of a reduction, and so its rounding, may vary between runs).
+    GPU tests keep every host thread: they compare within tolerances."""
+    if "gpu" in request.node.keywords:
+        yield
+        return
+    import torch
+    n = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        yield
+    finally:
+        torch.set_num_threads(n)
