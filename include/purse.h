@@ -93,6 +93,9 @@ typedef int32_t purse_status;
 #define PURSE_FLAG_REPLAY_DESCENT 64  /* purse_megb_backward: replay the MEGB descent from the trace even
                                          when purse_megb left its checkpoints for this trace in the
                                          workspace (same results; for testing) */
+#define PURSE_FLAG_MATRIX_COTANGENT 256 /* purse_megb_backward: g_centre is [n_inst][12], the cotangent of the
+                                           centre's entries as purse_megb returns them (R* row-major, then
+                                           t*); its rotation part is taken along SO(3) at R* */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints
@@ -206,14 +209,29 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
  * every ckpt_every iterations and swept backwards, then through the centre
  * fit.
  *
- * The descent's iterates come from the checkpoints purse_megb left in the
- * workspace when their signature matches `trace` (same batch, params and
- * workspace); otherwise the descent is replayed from `trace`.
+ * Workspace contract: `ws` must be the workspace that purse_sample used to
+ * produce `poses` and `mask` for this batch (its per-instance records: the
+ * centre fit, anchor and keypoint records the trajectories are re-run from).
+ * Each instance record is checked against the batch (kind, keypoint and
+ * sample ranges, Philox key) and against a fingerprint of the instance's
+ * inputs (model points, centres, shapes, bounds, intrinsics); an instance
+ * whose record does not match gets NaN gradients instead of being re-run
+ * from another batch's records.  The descent's iterates come from the
+ * checkpoints purse_megb left in the workspace when their signature (the
+ * steps, the winners and the bits of the start's and the winners'
+ * rotations) matches `trace` and `poses`; otherwise the descent is replayed
+ * from `trace` and the checkpoints are rewritten.
+ *
+ * Per-instance outcomes (no host synchronisation): an instance without
+ * feasible samples gets zero gradients; NaN gradients mark a record of
+ * another batch or data, a trace entry that is not a feasible sample, a
+ * descent touching more than 256 distinct samples, or a non-finite centre.
  *
  * Inputs: poses, mask, trace as produced by the forward calls;
  *   g_radii  [n_inst][2] double: cotangents of D_hat and d_hat;
  *   g_centre [n_inst][6] float: cotangent of the centre as a left so(3)
- *            3-vector at R* followed by the R^3 cotangent of t*.
+ *            3-vector at R* followed by the R^3 cotangent of t*
+ *            ([n_inst][12] with PURSE_FLAG_MATRIX_COTANGENT).
  * Outputs (overwritten):
  *   g_centres [total_kp][3] float: d/d centres (b_i, or z_i in x, y; third unused = 0)
  *   g_shapes  [total_kp][4] float: d/d Lambda_i, symmetrised (zeros for 3D-3D)

@@ -12,7 +12,8 @@ from typing import Optional
 
 from . import _native
 from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
-                      PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES,
+                      PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_MATRIX_COTANGENT, PURSE_FLAG_PAIR_LANES,
+                      PURSE_FLAG_QUAD_LANES,
                       PURSE_FLAG_REPLAY_DESCENT,
                       PURSE_FLAG_REUSE_PROLOGUE,
                       PURSE_INST_ANCHOR_ITERATED, PURSE_INST_BAD_SHAPE, PURSE_INST_BAD_SIZE,

@@ -32,6 +32,7 @@ PURSE_FLAG_GENERIC_LOOP = 16
 PURSE_FLAG_PAIR_LANES = 32
 PURSE_FLAG_REPLAY_DESCENT = 64
 PURSE_FLAG_QUAD_LANES = 128
+PURSE_FLAG_MATRIX_COTANGENT = 256
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_megb",
             "purse_megb_backward", "purse_status_string", "purse_last_error")

@@ -19,6 +19,7 @@
 //    order, scattered into the gradient arrays.
 #include <mutex>
 
+#include "purse_bwd_check.hpp"
 #include "purse_fit.hpp"
 #include "purse_geodesic.hpp"
 #include "purse_launch.hpp"
@@ -105,18 +106,7 @@ __device__ __forceinline__ void load_R(const float *poses, int64_t g, D R[9]) {
   for (int k = 0; k < 9; ++k) R[k] = (D)P[k];
 }
 
-__device__ __forceinline__ int find_active(const int *act, int n, int s) {
-  int lo = 0, hi = n - 1;
-  while (lo <= hi) {
-    int mid = (lo + hi) >> 1;
-    if (act[mid] == s) return mid;
-    if (act[mid] < s)
-      lo = mid + 1;
-    else
-      hi = mid - 1;
-  }
-  return -1;
-}
+__device__ __forceinline__ int find_active(const int *act, int n, int s) { return find_sorted(act, n, s); }
 
 }  // namespace
 
@@ -125,10 +115,10 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
                                                         const int32_t *__restrict__ trace,
                                                         const double *__restrict__ g_radii,
                                                         const float *__restrict__ g_centre,
-                                                        MegbRec *megb, BwdRec *recs,
-                                                        float4 *ckpt_all, int ck) {
+                                                        const InstRec *__restrict__ inst, MegbRec *megb,
+                                                        BwdRec *recs, float4 *ckpt_all, int ck) {
   __shared__ int act[kMaxActive];
-  __shared__ int n_act_s, overflow_s;
+  __shared__ int n_act_s, err_s;  // err_s: a BwdRec status (kBwdOk while the sweep may run)
   __shared__ double cot[kMaxActive][12];
   __shared__ float pact[kMaxActive][12];       // poses of the active samples
   __shared__ float4 qact[kMaxActive];          // their rotations as quaternions
@@ -156,10 +146,41 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   sample_range(b.sample_off, j, b.total_samples, b.max_samples, off, M64);
   const int M = (int)M64;
   BwdRec *rec = recs + j;
+  // ---- the prologue's records must belong to this batch and its data (else
+  // they would index keypoints of another batch): the instance record's
+  // ranges and key, and the fingerprint of the inputs, recomputed here
+  if (tid == 0) {
+    s0_s = INT32_MAX;
+    err_s = inst_record_ok(inst[j], inst_view(b, j)) ? kBwdOk : kBwdStale;
+  }
+  __syncthreads();
+  if (wave == 0 && err_s == kBwdOk) {
+    const int n = b.n_kp[j];
+    const int64_t ko = b.kp_off[j];
+    unsigned long long h = 0ull;
+    if (lane < n) {
+      const int64_t k = ko + lane;
+      uint32_t w[11];
+      kp_words(b.kind[j], b.model_pts + 3 * k, b.centres + 3 * k, b.shapes + 4 * k, b.bounds[k], w);
+      h = kp_data_term(lane, w);
+    }
+    for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+    if (lane == 0) {
+      const InstRec &I = inst[j];
+      h += I.kind == PURSE_KIND_2D3D ? intrinsics_term(I.K) : 0ull;
+      if (h != I.data_fp) err_s = kBwdStale;
+    }
+  }
+  __syncthreads();
+  if (err_s != kBwdOk) {
+    if (tid == 0) {
+      rec->n_act = 0;
+      rec->status = err_s;
+    }
+    return;
+  }
   // ---- first feasible sample: rounds of 8 masks per thread (loads issued
   // together), stopping at the first round that holds one
-  if (tid == 0) s0_s = INT32_MAX;
-  __syncthreads();
   for (int r0 = 0; r0 < M; r0 += 8 * kBwdBlock) {
     uint8_t m8[8];
 #pragma unroll
@@ -181,7 +202,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   if (s0 == INT32_MAX) {
     if (tid == 0) {
       rec->n_act = 0;
-      rec->status = 1;
+      rec->status = kBwdEmpty;
     }
     return;
   }
@@ -198,16 +219,23 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     if (bad) {
       if (tid == 0) {
         rec->n_act = 0;
-        rec->status = 3;
+        rec->status = kBwdBadTrace;
       }
       return;
     }
   }
   // ---- the rotation checkpoints purse_megb left are used when their
-  // signature matches this trace (else the descent is replayed below)
+  // signature (steps, winners, the bits of the start's and the winners'
+  // rotations) matches this descent (else it is replayed below)
   {
     unsigned long long h = 0ull;
-    for (int i = 1 + tid; i <= T; i += kBwdBlock) h += trace_mix(i, tr[2 * (i - 1)]);
+    for (int i = tid; i <= T; i += kBwdBlock) {
+      const int id = i == 0 ? s0 : tr[2 * (i - 1)];  // (checked above: samples of the instance)
+      uint32_t R[9];
+      const float *P = poses + 12 * (off + id);
+      for (int k = 0; k < 9; ++k) R[k] = __float_as_uint(P[k]);
+      h += step_sig_term(i, id, R);
+    }
     for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
     if (lane == 0) red_h[wave] = h;
     __syncthreads();
@@ -223,7 +251,6 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         megb[j].ck_every = ck;
       }
       n_act_s = 0;
-      overflow_s = 0;
     }
   }
   __syncthreads();
@@ -245,23 +272,41 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       if (n_act_s < kMaxActive)
         act[n_act_s++] = mn;
       else
-        overflow_s = 1;
+        err_s = kBwdOverflow;
     }
     last = mn;
   }
   __syncthreads();
   // ---- stage the active samples' poses and the trace (as slots) in LDS: the
   // serial sweeps below then read nothing from global memory per step
-  const bool lds_trace = T <= kLdsTrace && !overflow_s;
-  if (!overflow_s) {
-    for (int k = tid; k < n_act_s * 12; k += kBwdBlock) pact[k / 12][k % 12] = poses[12 * (off + act[k / 12]) + k % 12];
-    if (lds_trace)
-      for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act_s, tr[k]);
-  }
-  __syncthreads();
-  for (int a = tid; a < n_act_s && !overflow_s; a += kBwdBlock) qact[a] = quat_from_rot(pact[a]);
-  __syncthreads();
-  auto slot_of = [&](int k) { return lds_trace ? (int)tslot[k] : find_active(act, n_act_s, tr[k]); };
+  // (every active id is a sample of the instance: the trace was checked and
+  // s0 was found in range; a trace entry missing from the set would be a
+  // bookkeeping error, reported instead of used as a slot)
+  const bool lds_trace = T <= kLdsTrace;
+  auto stage_active = [&](int n_act_now) {
+    int miss = 0;
+    if (err_s == kBwdOk) {
+      for (int k = tid; k < n_act_now * 12; k += kBwdBlock)
+        pact[k / 12][k % 12] = poses[12 * (off + act[k / 12]) + k % 12];
+      if (lds_trace)
+        for (int k = tid; k < 2 * T; k += kBwdBlock) {
+          const int sl = find_active(act, n_act_now, tr[k]);
+          miss |= sl < 0;
+          tslot[k] = (uint8_t)(sl < 0 ? 0 : sl);
+        }
+    }
+    const bool stop = err_s != kBwdOk;  // (last written before the barrier that ended the previous step)
+    miss = __syncthreads_or(miss);
+    if (miss && tid == 0) err_s = kBwdBadTrace;
+    for (int a = tid; a < n_act_now && !miss && !stop; a += kBwdBlock) qact[a] = quat_from_rot(pact[a]);
+    __syncthreads();
+  };
+  stage_active(n_act_s);
+  auto slot_of = [&](int k) {
+    if (lds_trace) return (int)tslot[k];
+    const int sl = find_active(act, n_act_s, tr[k]);
+    return sl < 0 ? 0 : sl;  // (staging checked that every entry has a slot)
+  };
   auto load_act = [&](int a, D R[9]) {
     for (int q = 0; q < 9; ++q) R[q] = (D)pact[a][q];
   };
@@ -274,7 +319,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   // per-lane tables of the next 64 steps) and writes the checkpoints.
   float4 *ckq = ckpt_all + (int64_t)j * ckpt_count(T, ck);
   const bool stored = stored_s != 0;
-  if (wave == 0 && !overflow_s) {
+  if (wave == 0 && err_s == kBwdOk) {
     D S[9];
     for (int k = 0; k < 9; ++k) S[k] = 0;
     if (stored) {
@@ -289,7 +334,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         }
       }
     } else {
-      float4 C = qact[find_active(act, n_act_s, s0)];
+      float4 C = qact[max(find_active(act, n_act_s, s0), 0)];  // (s0 is in the set)
       int ib = 1, kc = 0, q = 0;
       float inv_tab = 1.f / (float)(ib + lane);
       float4 B_tab = qact[slot_of(2 * min(ib - 1 + lane, T - 1))];
@@ -331,7 +376,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   // - c_{i-1}) / i, c_1 = t_{s_1}) is the mean of the first i winners: winner
   // k carries (1/avg) sum_{i >= max(k, T - avg + 1)} 1/i.  All threads, in
   // float64, summed in a fixed order.
-  if (!overflow_s) {
+  if (err_s == kBwdOk) {
     D hs = 0;
     for (int k = T - avg + 1; k <= T; ++k) hs += 1.0 / (D)k;
     D ta[3] = {0.0, 0.0, 0.0};
@@ -350,12 +395,18 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       for (int r = 0; r < 3; ++r) gstep[wave][r] = ta[r];
   }
   __syncthreads();
-  if (tid == 0 && !overflow_s)
+  if (tid == 0 && err_s == kBwdOk) {
     for (int r = 0; r < 3; ++r) {
       D t = 0;
       for (int w = 0; w < kBwdWaves; ++w) t += gstep[w][r];
       tstar[r] = t / avg;
     }
+    // a non-finite centre has no radius samples
+    bool fin = true;
+    for (int k = 0; k < 9; ++k) fin = fin && isfinite(Rstar[k]);
+    for (int k = 0; k < 3; ++k) fin = fin && isfinite(tstar[k]);
+    if (!fin) err_s = kBwdNonFinite;
+  }
   __syncthreads();
   // ---- samples realising the radii about (R*, t*)
   D br = -1, bt = -1;
@@ -394,25 +445,12 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
           ft += d * d;
         }
         // increasing s per thread: a strictly larger value replaces the best
-        if (fr > br) {
-          br = fr;
-          ir = s;
-        }
-        if (ft > bt) {
-          bt = ft;
-          it = s;
-        }
+        radius_take(fr, s, br, ir);
+        radius_take(ft, s, bt, it);
       }
     }
   }
-  for (int o = 32; o >= 1; o >>= 1) {
-    D v2 = __shfl_xor(br, o, 64);
-    int i2 = __shfl_xor(ir, o, 64);
-    if (v2 > br || (v2 == br && i2 < ir)) {
-      br = v2;
-      ir = i2;
-    }
-  }
+  for (int o = 32; o >= 1; o >>= 1) radius_merge(__shfl_xor(br, o, 64), __shfl_xor(ir, o, 64), br, ir);
   if (lane == 0) {
     red_v[wave] = br;
     red_i[wave] = ir;
@@ -421,22 +459,11 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   if (tid == 0) {
     D v = red_v[0];
     int ii = red_i[0];
-    for (int w = 1; w < kBwdWaves; ++w)
-      if (red_v[w] > v || (red_v[w] == v && red_i[w] < ii)) {
-        v = red_v[w];
-        ii = red_i[w];
-      }
+    for (int w = 1; w < kBwdWaves; ++w) radius_merge(red_v[w], red_i[w], v, ii);
     sD_s = ii;
   }
   __syncthreads();
-  for (int o = 32; o >= 1; o >>= 1) {
-    D v2 = __shfl_xor(bt, o, 64);
-    int i2 = __shfl_xor(it, o, 64);
-    if (v2 > bt || (v2 == bt && i2 < it)) {
-      bt = v2;
-      it = i2;
-    }
-  }
+  for (int o = 32; o >= 1; o >>= 1) radius_merge(__shfl_xor(bt, o, 64), __shfl_xor(it, o, 64), bt, it);
   if (lane == 0) {
     red_v[wave] = bt;
     red_i[wave] = it;
@@ -445,27 +472,17 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   if (tid == 0) {
     D v = red_v[0];
     int ii = red_i[0];
-    for (int w = 1; w < kBwdWaves; ++w)
-      if (red_v[w] > v || (red_v[w] == v && red_i[w] < ii)) {
-        v = red_v[w];
-        ii = red_i[w];
-      }
+    for (int w = 1; w < kBwdWaves; ++w) radius_merge(red_v[w], red_i[w], v, ii);
     sd_s = ii;
-    // insert the radius samples into the sorted active set
-    int extra[2] = {sD_s, sd_s};
-    for (int e = 0; e < 2; ++e) {
-      int s = extra[e];
-      if (find_active(act, n_act_s, s) >= 0) continue;
-      if (n_act_s >= kMaxActive) {
-        overflow_s = 1;
-        continue;
-      }
-      int k = n_act_s++;
-      while (k > 0 && act[k - 1] > s) {
-        act[k] = act[k - 1];
-        --k;
-      }
-      act[k] = s;
+    // insert the radius samples into the sorted active set; an id that is no
+    // sample of the instance (the search's sentinel, left when no distance
+    // compared) ends the backward of this instance instead of indexing poses
+    if (err_s == kBwdOk) {
+      int32_t st = radius_sample_status(sD_s, M);
+      if (st == kBwdOk) st = radius_sample_status(sd_s, M);
+      if (st == kBwdOk) st = active_insert(act, n_act_s, kMaxActive, sD_s, M);
+      if (st == kBwdOk) st = active_insert(act, n_act_s, kMaxActive, sd_s, M);
+      if (st != kBwdOk) err_s = st;
     }
   }
   for (int k = tid; k < kMaxActive * 12; k += kBwdBlock) cot[k / 12][k % 12] = 0.0;
@@ -473,14 +490,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   const int n_act = n_act_s;
   // a radius sample outside the trace shifts the active set: stage the poses
   // and the trace slots again for the new positions
-  if (!overflow_s) {
-    for (int k = tid; k < n_act * 12; k += kBwdBlock) pact[k / 12][k % 12] = poses[12 * (off + act[k / 12]) + k % 12];
-    if (lds_trace)
-      for (int k = tid; k < 2 * T; k += kBwdBlock) tslot[k] = (uint8_t)find_active(act, n_act, tr[k]);
-  }
-  __syncthreads();
-  for (int a = tid; a < n_act && !overflow_s; a += kBwdBlock) qact[a] = quat_from_rot(pact[a]);
-  __syncthreads();
+  stage_active(n_act);
   // ---- reverse sweeps
   // Rotation chain.  Thread 0 turns the cotangents of R* and the rotation
   // radius into S_bar = dL/dS (S = sum of the last iterates).  Then the T
@@ -494,11 +504,21 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   // so the serial part is 3x3 products only.  g_0 belongs to the first
   // sample (C_0 = R_{s0}); a sample's tangent cotangent rho becomes the
   // ambient cotangent R [rho]x / 2 of its rotation.
-  if (tid == 0 && !overflow_s) {
+  if (tid == 0 && err_s == kBwdOk) {
     // cotangent of R*: (g_w . left tangent) and the rotation radius
     D G[9], W[9];
-    const float *gc = g_centre + 6 * j;
+    // the left so(3) cotangent at R*; a cotangent of R*'s entries G gives
+    // vskew(G R*^T) (the pairing <G, [w]x R*> = w . vskew(G R*^T))
+    const bool mat = (p.flags & PURSE_FLAG_MATRIX_COTANGENT) != 0;
+    const float *gc = g_centre + (mat ? 12 : 6) * j;
     D gw[3] = {gc[0], gc[1], gc[2]};
+    if (mat) {
+      D X[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          X[3 * r + c] = (D)gc[3 * r] * Rstar[3 * c] + (D)gc[3 * r + 1] * Rstar[3 * c + 1] + (D)gc[3 * r + 2] * Rstar[3 * c + 2];
+      vskew(X, gw);
+    }
     hat_d(gw, W);
     matmul3<D>(W, Rstar, G);
     for (int k = 0; k < 9; ++k) G[k] *= 0.5;
@@ -511,7 +531,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       D f = sqrt(f2);
       D x = f / (2.0 * sqrt(2.0));
       D kD = gD / (sqrt(2.0) * sqrt(fmax(1e-30, 1.0 - x * x)) * f);
-      int pD = find_active(act, n_act, sD_s);
+      const int pD = max(find_active(act, n_act, sD_s), 0);  // (inserted above)
       for (int k = 0; k < 9; ++k) {
         D v = kD * (Rstar[k] - RD[k]);
         G[k] += v;
@@ -545,17 +565,18 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   // its reverse is a scalar recurrence per coordinate, swept by thread 64 over
   // each chunk while thread 0 sweeps the rotation chain.
   D tb[3] = {0, 0, 0};
-  if (tid == 64 && !overflow_s) {
-    const float *gc = g_centre + 6 * j;
-    tb[0] = gc[3];
-    tb[1] = gc[4];
-    tb[2] = gc[5];
+  if (tid == 64 && err_s == kBwdOk) {
+    const bool mat = (p.flags & PURSE_FLAG_MATRIX_COTANGENT) != 0;
+    const float *gc = g_centre + (mat ? 12 : 6) * j + (mat ? 9 : 3);
+    tb[0] = gc[0];
+    tb[1] = gc[1];
+    tb[2] = gc[2];
     const D gd = g_radii[2 * j + 1];
     const float *Pd = poses + 12 * (off + sd_s);
     D dv[3] = {tstar[0] - Pd[9], tstar[1] - Pd[10], tstar[2] - Pd[11]};
     D dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
     if (dn > 0 && gd != 0) {
-      const int pd = find_active(act, n_act, sd_s);
+      const int pd = max(find_active(act, n_act, sd_s), 0);  // (inserted above)
       for (int r = 0; r < 3; ++r) {
         tb[r] += gd * dv[r] / dn;
         cot[pd][9 + r] -= gd * dv[r] / dn;
@@ -570,7 +591,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   D hsum = 0;
   for (int k = T - avg + 1; k <= T; ++k) hsum += 1.0 / (D)k;
   __syncthreads();
-  if (!overflow_s) {
+  if (err_s == kBwdOk) {
     for (int i_hi = T; i_hi >= 1; i_hi -= kBwdBlock) {
       const int i_lo = max(1, i_hi - kBwdBlock + 1);
       const int i = i_lo + tid;
@@ -728,7 +749,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
       __syncthreads();
     }
     if (tid == 0) {
-      const int p0 = find_active(act, n_act, s0);
+      const int p0 = max(find_active(act, n_act, s0), 0);  // (s0 is in the set)
       for (int k = 0; k < 3; ++k) rho[p0][k] += gvec[k];
     }
     __syncthreads();
@@ -743,14 +764,15 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   }
   __syncthreads();
   if (tid == 0) {
-    rec->n_act = overflow_s ? 0 : n_act;
-    rec->status = overflow_s ? 2 : 0;
+    rec->n_act = err_s != kBwdOk ? 0 : n_act;
+    rec->status = err_s;
     rec->s0 = s0;
     rec->sD = sD_s;
     rec->sd = sd_s;
   }
-  for (int k = tid; k < n_act * 12; k += kBwdBlock) rec->cot[k / 12][k % 12] = cot[k / 12][k % 12];
-  for (int k = tid; k < n_act; k += kBwdBlock) rec->active[k] = act[k];
+  const int n_out = err_s != kBwdOk ? 0 : n_act;
+  for (int k = tid; k < n_out * 12; k += kBwdBlock) rec->cot[k / 12][k % 12] = cot[k / 12][k % 12];
+  for (int k = tid; k < n_out; k += kBwdBlock) rec->active[k] = act[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -853,7 +875,9 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p,
   const int j = blockIdx.x;
   const int d = threadIdx.x;
   const InstRec I = inst[j];
-  if ((I.status & 0xFF) != PURSE_INST_OK) return;  // (whole workgroup)
+  // (whole workgroup) a record of another batch is not used: k_bwd_megb
+  // reports it and no tangent is read for that instance
+  if (!inst_record_ok(I, inst_view(b, j)) || (I.status & 0xFF) != PURSE_INST_OK) return;
   const bool is2d = I.kind == PURSE_KIND_2D3D;
   const int dpk = dirs_per_kp(I.kind);
   const int n = I.n_kp;
@@ -958,10 +982,12 @@ __global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const 
                                                  const float *__restrict__ tan_all, float *contrib, int max_dirs) {
   const int a = blockIdx.x, j = blockIdx.y;
   const int d = blockIdx.z * 64 + threadIdx.x;
-  const InstRec I = inst[j];
-  if (I.kind != KIND || (I.status & 0xFF) != PURSE_INST_OK) return;
   const BwdRec *rec = recs + j;
-  if (a >= rec->n_act) return;
+  // k_bwd_megb of this call checked the instance record against the batch
+  // and its data; only then is the status ok and the active set non-empty
+  if (rec->status != kBwdOk || a >= min(rec->n_act, kMaxActive)) return;
+  const InstRec I = inst[j];
+  if (I.kind != KIND || (I.status & 0xFF) != PURSE_INST_OK || !inst_record_ok(I, inst_view(b, j))) return;
   const int dpk = dirs_per_kp(KIND);
   if (d >= I.n_kp * dpk) return;
   const int i_d = d / dpk, c = d % dpk;
@@ -1149,10 +1175,11 @@ __global__ void __launch_bounds__(64) k_bwd_traj2d_group(DevBatch b, DevParams p
   const int a = blockIdx.x, j = blockIdx.y;
   const int q = threadIdx.x % G;
   const int d = blockIdx.z * (64 / G) + threadIdx.x / G;
-  const InstRec I = inst[j];
-  if (I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK) return;
   const BwdRec *rec = recs + j;
-  if (a >= rec->n_act) return;
+  // (see k_bwd_traj)
+  if (rec->status != kBwdOk || a >= min(rec->n_act, kMaxActive)) return;
+  const InstRec I = inst[j];
+  if (I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK || !inst_record_ok(I, inst_view(b, j))) return;
   const int dpk = dirs_per_kp(PURSE_KIND_2D3D);
   if (d >= I.n_kp * dpk) return;  // (whole lane groups)
   const int i_d = d / dpk, c = d % dpk;
@@ -1191,20 +1218,22 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstR
                                                         float *g_bounds) {
   const int j = blockIdx.x;
   const int d = threadIdx.x;
-  const InstRec I = inst[j];
-  const int64_t ko = b.kp_off[j];
-  const int n = b.n_kp[j];
-  const bool kp_ok = ko >= 0 && n >= 0 && n <= PURSE_MAX_KP && ko + n <= b.total_kp && b.kp_off[j + 1] - ko == n;
-  if (!kp_ok) return;
-  const bool is2d = I.kind == PURSE_KIND_2D3D;
-  const int dpk = dirs_per_kp(I.kind);
+  const InstView v = inst_view(b, j);
+  if (!inst_view_ok(v)) return;  // (the batch's own ranges: nothing can be addressed)
+  const int64_t ko = v.kp_off;
+  const int n = v.n_kp;
+  const bool is2d = v.kind == PURSE_KIND_2D3D;
+  const int dpk = dirs_per_kp(v.kind);
   if (d >= n * dpk) return;
   const int i = d / dpk, c = d % dpk;
+  const InstRec I = inst[j];
   const BwdRec *rec = recs + j;
   float g = 0.f;
-  if ((I.status & 0xFF) == PURSE_INST_OK && rec->status == 2) {
-    g = __int_as_float(0x7fc00000);  // active set beyond capacity: no gradient
-  } else if ((I.status & 0xFF) == PURSE_INST_OK) {
+  if (bwd_status_is_error(rec->status) || !inst_record_ok(I, v)) {
+    // a stale workspace, an active set beyond capacity, a trace that does not
+    // fit the mask, or a non-finite centre: no gradient
+    g = __int_as_float(0x7fc00000);
+  } else if ((I.status & 0xFF) == PURSE_INST_OK && rec->status == kBwdOk) {
     double acc = 0.0;
     const int n_act = min(max(rec->n_act, 0), kMaxActive);  // (the record's capacity)
     for (int a = 0; a < n_act; ++a) acc += (double)contrib[((int64_t)j * kMaxActive + a) * max_dirs + d];
@@ -1288,12 +1317,12 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
       hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, a->s, b, p, inst, kp, tan, max_dirs);
       hipError_t e = hipEventRecord(a->join, a->s);
       hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
-                         g_centre, megb, recs, ckpt, ck);
+                         g_centre, inst, megb, recs, ckpt, ck);
       if (e == hipSuccess) e = hipStreamWaitEvent(stream, a->join, 0);
       if (e != hipSuccess) return e;  // no join: nothing that reads the frame tangents is launched
     } else {
       hipLaunchKernelGGL(k_bwd_megb, dim3(n), dim3(kBwdBlock), 0, stream, b, p, poses, mask, trace, g_radii,
-                         g_centre, megb, recs, ckpt, ck);
+                         g_centre, inst, megb, recs, ckpt, ck);
       hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, tan, max_dirs);
     }
   }

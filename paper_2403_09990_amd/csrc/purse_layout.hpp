@@ -34,8 +34,9 @@ struct InstRec {
   float Ra[9], ta[3];   // feasible anchor
   float abar[3];        // model centroid
   float K[4];           // fx, fy, cx, cy
-  float pad[2];
+  unsigned long long data_fp;  // fingerprint of the instance's inputs (inst_data_fp)
 };
+static_assert(sizeof(InstRec) == 192, "InstRec layout");
 
 // MEGB per-instance scratch.
 struct MegbRec {

@@ -18,6 +18,7 @@
 
 #include <type_traits>
 
+#include "purse_bwd_check.hpp"
 #include "purse_geodesic.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
@@ -1112,13 +1113,31 @@ __global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict
   }
 }
 
-// Signature of each instance's rotation trace, stored with the checkpoints
-// the descent left, so that the backward uses them only for this trace.
-__global__ void __launch_bounds__(kBlock) k_megb_sign(const int32_t *__restrict__ trace, MegbRec *rec, int T, int ck) {
+// Signature of each instance's descent, stored with the checkpoints it left,
+// so that the backward uses them only for this descent: the sum of a term
+// per step of (step, winner, the bits of the winner's rotation), and one for
+// the start (the first feasible sample), which determine the iterates.
+__global__ void __launch_bounds__(kBlock) k_megb_sign(const int64_t *__restrict__ sample_off, int64_t total,
+                                                      int64_t max_m, const float *__restrict__ poses,
+                                                      const int32_t *__restrict__ trace, MegbRec *rec, int T, int ck) {
   const int j = blockIdx.x;
+  int64_t off, M;
+  sample_range(sample_off, j, total, max_m, off, M);
+  const int first = rec[j].first;
   const int32_t *tr = trace + (int64_t)j * T * 2;
   unsigned long long h = 0ull;
-  for (int i = 1 + (int)threadIdx.x; i <= T; i += kBlock) h += trace_mix(i, tr[2 * (i - 1)]);
+  if (first != INT32_MAX)
+    for (int i = (int)threadIdx.x; i <= T; i += kBlock) {
+      const int id = i == 0 ? first : tr[2 * (i - 1)];
+      if (id >= 0 && id < M) {
+        uint32_t R[9];
+        const float *P = poses + 12 * (off + id);
+        for (int k = 0; k < 9; ++k) R[k] = __float_as_uint(P[k]);
+        h += step_sig_term(i, id, R);
+      } else {
+        h += trace_mix(i, id);
+      }
+    }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
   __shared__ unsigned long long part[kWaves];
@@ -1128,7 +1147,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_sign(const int32_t *__restrict_
     unsigned long long t = 0ull;
     for (int w = 0; w < kWaves; ++w) t += part[w];
     rec[j].ck_hash = t;
-    rec[j].ck_T = rec[j].first != INT32_MAX ? T : 0;
+    rec[j].ck_T = first != INT32_MAX ? T : 0;
     rec[j].ck_every = ck;
   }
 }
@@ -1190,7 +1209,8 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
     hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(chain_block<false>()), lds, stream, b.sample_off,
                        max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
                        cap, no_prune);
-  hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, trace, rec, p.megb_iters, ck);
+  hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
+                     trace, rec, p.megb_iters, ck);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                      poses, mask, rec);
   hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,

@@ -4,6 +4,7 @@
 // wavefront (formed by lane 0, iterated with one keypoint per lane), so the
 // two run on different SIMDs at once; everything else is serial in lane 0 of
 // wavefront 0.
+#include "purse_bwd_check.hpp"
 #include "purse_fit.hpp"
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
@@ -19,6 +20,8 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
   __shared__ double w_s[3 * PURSE_MAX_KP];  // whitening factors of the keypoints
   __shared__ double fit_R[2][9], fit_t[2][3], fit_cost[2];
   __shared__ int fit_good[2], stage;         // stage: 0 invalid, 1 valid 3D-3D, 2 valid 2D-3D
+  __shared__ int fp_n;                       // keypoints the data fingerprint covers
+  __shared__ int64_t fp_ko;
   InstRec I;                                 // (lane 0 of wavefront 0)
   double ab[3] = {0, 0, 0};
   if (tid == 0) {
@@ -37,10 +40,12 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
     for (int k = 0; k < 4; ++k) I.K[k] = (I.kind == PURSE_KIND_2D3D) ? b.intrinsics[4 * j + k] : 0.f;
     for (int k = 0; k < 9; ++k) I.Rc[k] = I.Ra[k] = (k % 4 == 0) ? 1.f : 0.f;
     for (int k = 0; k < 3; ++k) I.tc[k] = I.ta[k] = I.oc[k] = I.abar[k] = 0.f;
-    I.pad[0] = I.pad[1] = 0.f;
+    I.data_fp = 0ull;
     const int n = I.n_kp;
     const bool is2d = I.kind == PURSE_KIND_2D3D;
     const int64_t ko = kp_ok ? I.kp_off : 0;
+    fp_n = (kp_ok && n >= 0 && n <= PURSE_MAX_KP) ? n : 0;
+    fp_ko = ko;
     const float *a = b.model_pts + 3 * ko;
     const float *c = b.centres + 3 * ko;
     const float *L = b.shapes + 4 * ko;
@@ -96,6 +101,19 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
   }
   __syncthreads();
   const int st = stage;
+  // fingerprint of the instance's inputs (one keypoint per lane of
+  // wavefront 0), which the backward compares with the batch it is given
+  if (tid < 64) {
+    unsigned long long h = 0ull;
+    if (tid < fp_n) {
+      const int64_t k = fp_ko + tid;
+      uint32_t w[11];
+      kp_words(b.kind[j], b.model_pts + 3 * k, b.centres + 3 * k, b.shapes + 4 * k, b.bounds[k], w);
+      h = kp_data_term(tid, w);
+    }
+    for (int o = 32; o >= 1; o >>= 1) h += __shfl_xor(h, o, 64);
+    if (tid == 0) I.data_fp = h + (I.kind == PURSE_KIND_2D3D ? intrinsics_term(I.K) : 0ull);
+  }
   if (st == 2) {
     // Gauss-Newton from the DLT (wavefront 0) and from the weak-perspective
     // fit (wavefront 1): lane 0 forms the start, the whole wavefront iterates

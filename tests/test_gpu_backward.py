@@ -140,11 +140,17 @@ def test_backward_checkpoints_from_the_forward():
         np.testing.assert_array_equal(a, r)
 
 
+def _vskew(X):
+    return np.array([X[2, 1] - X[1, 2], X[0, 2] - X[2, 0], X[1, 0] - X[0, 1]])
+
+
 def test_autograd_function():
-    """PurseMEGB inside torch.autograd: loss.backward() reproduces the ABI call."""
+    """PurseMEGB inside torch.autograd: loss.backward() reproduces the ABI call
+    with the so(3) cotangent v(G R*^T) of the centre's rotation entries G
+    (the library takes the matrix cotangent itself)."""
     _log("case: autograd")
     import paper_2403_09990_amd as P
-    from paper_2403_09990_amd.autograd import PurseMEGB, left_cotangent
+    from paper_2403_09990_amd.autograd import PurseMEGB
     rng = np.random.default_rng(6)
     b = W.Batch([W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 512)])
     gp = P.purse_default_params(n_iters=30, megb_iters=256)
@@ -152,15 +158,79 @@ def test_autograd_function():
     centres = db.centres.clone().requires_grad_(True)
     shapes = db.shapes.clone().requires_grad_(True)
     bounds = db.bounds.clone().requires_grad_(True)
+    Gm = rng.normal(size=(3, 3))
     centre, radii = PurseMEGB.apply(centres, shapes, bounds, db, gp)
-    loss = 0.7 * radii[0, 0] - 0.3 * radii[0, 1] + centre[0, 9:].sum()
+    loss = (0.7 * radii[0, 0] - 0.3 * radii[0, 1] + centre[0, 9:].sum()
+            + (centre[0, :9] * torch.as_tensor(Gm.ravel(), dtype=torch.float32, device=centre.device)).sum())
     loss.backward()
     res = PT.run_gpu(b, gp)
+    Rs = res["centre"][0, :9].cpu().numpy().astype(np.float64).reshape(3, 3)
     g_centre = np.zeros((1, 6))
+    g_centre[0, :3] = _vskew(Gm @ Rs.T)
     g_centre[0, 3:] = 1.0
     gpu = _gpu_backward(res, gp, np.array([[0.7, -0.3]]), g_centre)
-    np.testing.assert_allclose(centres.grad.cpu().numpy(), gpu[0], rtol=1e-5, atol=1e-7)
-    np.testing.assert_allclose(bounds.grad.cpu().numpy(), gpu[2], rtol=1e-5, atol=1e-7)
-    R = torch.eye(3, dtype=torch.float64)[None]
-    assert torch.allclose(left_cotangent(R, torch.zeros(1, 3, 3, dtype=torch.float64)), torch.zeros(1, 3,
-                                                                                                   dtype=torch.float64))
+    np.testing.assert_allclose(centres.grad.cpu().numpy(), gpu[0], rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(shapes.grad.cpu().numpy(), gpu[1], rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(bounds.grad.cpu().numpy(), gpu[2], rtol=1e-4, atol=1e-6)
+
+
+def test_autograd_two_forwards_on_one_batch():
+    """Two forwards on the same DeviceBatch before either backward (as in
+    gradient accumulation): each backward sees its own forward's measurements,
+    so A's gradients equal those of A alone."""
+    _log("case: autograd two forwards")
+    import paper_2403_09990_amd as P
+    from paper_2403_09990_amd.autograd import PurseMEGB
+    rng = np.random.default_rng(16)
+    b = W.Batch([W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 512), W.make_3d3d(rng, 8, 0.01, 0.05, 512)])
+    gp = P.purse_default_params(n_iters=30, megb_iters=256)
+
+    def run(db, shift):
+        c = (db.centres.clone() + shift).requires_grad_(True)
+        L = db.shapes.clone().requires_grad_(True)
+        be = db.bounds.clone().requires_grad_(True)
+        centre, radii = PurseMEGB.apply(c, L, be, db, gp)
+        return (c, L, be), (radii[:, 0].sum() + 0.5 * radii[:, 1].sum() + centre[:, 9:].sum())
+
+    db = P.DeviceBatch(b)
+    shift_b = torch.zeros_like(db.centres)
+    shift_b[:10, :2] = 0.5   # moves the 2D-3D instance's ellipse centres by half a pixel
+    shift_b[10:] = 0.002     # and the 3D-3D ball centres by 2 mm
+    leaves_a, loss_a = run(db, torch.zeros_like(db.centres))
+    leaves_b, loss_b = run(db, shift_b)
+    loss_b.backward()
+    loss_a.backward()
+    alone, loss_alone = run(P.DeviceBatch(b), torch.zeros_like(db.centres))
+    loss_alone.backward()
+    for x, y in zip(leaves_a, alone):
+        np.testing.assert_array_equal(x.grad.cpu().numpy(), y.grad.cpu().numpy())
+    assert not np.array_equal(leaves_a[0].grad.cpu().numpy(), leaves_b[0].grad.cpu().numpy())
+
+
+def test_backward_rejects_a_workspace_of_other_data():
+    """The backward's workspace contract: records written by purse_sample for
+    other measurements (same batch layout) are detected by their fingerprint
+    and give NaN gradients for the instances concerned, not gradients of the
+    wrong data; the instance whose data did not change is unaffected."""
+    _log("case: backward stale workspace")
+    import paper_2403_09990_amd as P
+    rng = np.random.default_rng(21)
+    b = W.Batch([W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 512), W.make_3d3d(rng, 8, 0.01, 0.05, 512)])
+    gp = P.purse_default_params(n_iters=30, megb_iters=256)
+    res = PT.run_gpu(b, gp)
+    g_radii = rng.normal(size=(2, 2))
+    g_centre = rng.normal(size=(2, 6))
+    good = _gpu_backward(res, gp, g_radii, g_centre)
+    assert all(np.isfinite(x).all() for x in good)
+    # a second purse_sample into the same workspace with instance 1's ball
+    # centres moved overwrites its records
+    db2 = P.DeviceBatch(b)
+    db2.centres[10:] += 0.002
+    P.sample(db2, gp, ws=res["ws"])
+    torch.cuda.synchronize()
+    stale = _gpu_backward(res, gp, g_radii, g_centre)
+    k0, k1 = res["db"].kp_off_host[1], res["db"].kp_off_host[2]
+    for x in stale:
+        assert np.isnan(x[k0:k1]).all()
+    for g, x in zip(good, stale):
+        np.testing.assert_array_equal(g[:k0], x[:k0])
