@@ -1,20 +1,23 @@
 """Benchmark of the PURSE hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5]
 
-A step is one pass of the whole forward hot path over one batch: the sampler
-(prologue + trajectories, purse_sample) followed by the MEGB (purse_megb),
-through the C ABI, on inputs already resident in HBM.  The default workload is
-the 2D-3D single instance: N = 12 keypoints, 65,536 trajectories, 100
-alternating iterations.  Prints one JSON line.
+A step is one pass of the whole hot path over one batch: the sampler
+(prologue + trajectories, purse_sample), the MEGB (purse_megb) and the
+backward of the radii and centre (purse_megb_backward of fixed random
+cotangents), through the C ABI, on inputs already resident in HBM.  The
+default workload is the largest one that fits one GPU: 64 instances of
+2D-3D with N = 48 keypoints and 2^20 trajectories each (67,108,864
+trajectories, 50 alternating iterations), every instance differentiated in one
+backward call.  Prints one JSON line; `value` is samples/s of the whole step,
+the forward alone is reported beside it.
 
-Also reported: the sampler and MEGB times separately, forward + backward
-(purse_megb_backward of random cotangents) time, the roofline of the dominant
-kernel (the trajectory kernel; algorithmic float32 FLOPs per launch over its
-average duration, measured with HIP events on the launch stream) and the
-FP64 oracle timed on this host on a bounded sample.  After the timed region
-one device copy of COPY_BYTES runs as the calibration kernel for HBM traffic
-counters read by rocprofv3 on this same command.
+Also reported: the sampler and MEGB times separately, the roofline of the
+dominant kernel (the trajectory kernel; algorithmic float32 FLOPs per launch
+over its average duration, measured with HIP events on the launch stream) and
+the FP64 oracle timed on this host on a bounded sample.  After the timed
+region one device copy of COPY_BYTES runs as the calibration kernel for HBM
+traffic counters read by rocprofv3 on this same command.
 """
 import argparse
 import json
@@ -76,8 +79,8 @@ def time_events(fn, reps, stream):
 
 def cpu_baseline(batch, iters, megb_iters, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload: its first
-    trajectories (count chosen to take roughly budget_s) plus the MEGB of
-    those samples; scaled to samples/s."""
+    trajectories of instance 0 (count chosen to take roughly budget_s) plus
+    the MEGB of those samples; scaled to samples/s."""
     import torch
 
     from oracle.megb import megb_from_poses
@@ -98,24 +101,22 @@ def cpu_baseline(batch, iters, megb_iters, budget_s=20.0):
     t0 = time.perf_counter()
     megb_from_poses(out["poses"], out["mask"], megb_iters, 10)
     t_m = time.perf_counter() - t0
-    return dict(value=m / (t_s + t_m), unit="samples/s", cores=torch.get_num_threads(), kind="oracle",
+    return dict(value=m / (t_s + t_m), unit="samples/s", cores=torch.get_num_threads(),
+                host_nproc=os.cpu_count(), kind="oracle",
                 sample="first %d of %d trajectories of instance 0 (%d iterations) + MEGB (T=%d) of "
                        "those samples; sampler %.2f s, MEGB %.2f s" % (m, inst.n_samples, iters,
                                                                        megb_iters, t_s, t_m))
 
 
-BWD_MAX_INST = 8
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--roofline-reps", type=int, default=10)
-    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--roofline-reps", type=int, default=5)
+    ap.add_argument("--no-backward", action="store_true", help="time the forward alone as the step")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -143,12 +144,19 @@ def main():
         # the sampler's launch schedule (tile size, tile order, keypoint loop),
         # picked by timing the candidates on this batch before the timed region
         from paper_2403_09990_amd import autotune
-        gp, rep = autotune.tune(db, gp, ws, poses, mask, status)
+        reps = 1 if db.total_samples > (1 << 23) else 3
+        gp, rep = autotune.tune(db, gp, ws, poses, mask, status, reps=reps)
         schedule = rep["choice"] if "choice" in rep else "tuned"
     centre = torch.empty(db.n_inst, 12, dtype=torch.float32, device=dev)
     radii = torch.empty(db.n_inst, 2, dtype=torch.float64, device=dev)
     nfeas = torch.empty(db.n_inst, dtype=torch.int64, device=dev)
     trace = torch.empty(db.n_inst, gp.megb_iters, 2, dtype=torch.int32, device=dev)
+    rng = np.random.default_rng(0)
+    g_radii = torch.as_tensor(rng.normal(size=(db.n_inst, 2)), dtype=torch.float64, device=dev)
+    g_centre = torch.as_tensor(rng.normal(size=(db.n_inst, 6)), dtype=torch.float32, device=dev)
+    g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
+    g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
+    g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
     def do_sample(params=gp):
@@ -157,9 +165,17 @@ def main():
     def do_megb():
         P.purse_megb(db, gp, poses, mask, centre, radii, nfeas, trace, status, ws, stream)
 
-    def step():
+    def do_backward():
+        P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream)
+
+    def fwd():
         do_sample()
         do_megb()
+
+    def step():
+        fwd()
+        if not args.no_backward:
+            do_backward()
 
     for _ in range(args.warmup):
         step()
@@ -170,37 +186,29 @@ def main():
 
     # breakdown and roofline of the trajectory kernel (prologue reused so the
     # events bracket the trajectory launches alone)
+    ms_fwd = time_events(fwd, args.roofline_reps, stream)
     ms_sample = time_events(do_sample, args.roofline_reps, stream)
     ms_megb = time_events(do_megb, args.roofline_reps, stream)
+    ms_bwd = None if args.no_backward else time_events(do_backward, args.roofline_reps, stream)
     gp_reuse = P.purse_default_params(n_iters=cfg["iters"], tile=gp.tile, flags=gp.flags | P.PURSE_FLAG_REUSE_PROLOGUE)
     ms_traj = time_events(lambda: do_sample(gp_reuse), args.roofline_reps, stream)
-    flops = F.batch_flops(batch, cfg["iters"], gp.n_gn)
+    torch.cuda.synchronize()
+    m = mask.cpu().numpy()
+    st = status.cpu().numpy()
+    rad = radii.cpu().numpy()
+    grads_finite = bool(torch.isfinite(g_c).all() and torch.isfinite(g_L).all() and torch.isfinite(g_b).all()) \
+        if not args.no_backward else None
+    pulled = [int(((m[a:b] & 2) != 0).sum()) for a, b in zip(db.sample_off_host[:-1], db.sample_off_host[1:])]
+    # the method's algorithmic count (per-keypoint model) and the count of the
+    # kernels' own formulation, both per trajectory launch
+    flops = F.model_batch_flops(batch, cfg["iters"], gp.n_gn, gp.n_bis, pulled)
+    flops_kernel = F.batch_flops(batch, cfg["iters"], gp.n_gn)
     achieved = flops / (ms_traj * 1e-3) / 1e12
     # the trajectory kernel that carries the workload: the lane-group variant
     # when the schedule runs 2D-3D trajectories on two or four lanes each
     traj_kernel = ("k_sample2d_lanes" if gp.flags & (P.PURSE_FLAG_PAIR_LANES | P.PURSE_FLAG_QUAD_LANES)
                    else "k_sample")
     traffic = read_traffic(traj_kernel, args.config)
-    # forward + backward: the step followed by the gradients of random
-    # cotangents of the radii and the centre
-    ms_fwd_bwd = None
-    # the backward of large batches is not timed: a backward run on such a
-    # batch once ended in a GPU fault whose cause is not identified
-    bwd_skipped = db.n_inst > BWD_MAX_INST
-    if not args.no_backward and not bwd_skipped:
-        rng = np.random.default_rng(0)
-        g_radii = torch.as_tensor(rng.normal(size=(db.n_inst, 2)), dtype=torch.float64, device=dev)
-        g_centre = torch.as_tensor(rng.normal(size=(db.n_inst, 6)), dtype=torch.float32, device=dev)
-        g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
-        g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
-        g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
-
-        def fwd_bwd():
-            step()
-            P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream)
-
-        fwd_bwd()
-        ms_fwd_bwd = time_events(fwd_bwd, max(1, min(args.steps, 5)), stream)
 
     # calibration kernel for the traffic counters: a copy of known size
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -208,10 +216,6 @@ def main():
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-
-    m = mask.cpu().numpy()
-    st = status.cpu().numpy()
-    rad = radii.cpu().numpy()
 
     out = {
         "metric": METRIC,
@@ -227,16 +231,20 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator shaped like the paper's 2D-3D / 3D-3D workloads)",
         "config": {"workload": "%s: %s" % (args.config, cfg["desc"]), "n_inst": db.n_inst,
-                   "samples": total_m, "megb_iters": gp.megb_iters, "parallelism": "single GPU"},
+                   "samples": total_m, "megb_iters": gp.megb_iters,
+                   "step": "sample + MEGB" + ("" if args.no_backward else " + backward (all instances, one call)"),
+                   "parallelism": "single GPU"},
         "sampler_schedule": schedule,
+        "fwd_ms": ms_fwd,
+        "fwd_samples_per_s": total_m / (ms_fwd * 1e-3),
+        "fwd_bwd_ms": None if args.no_backward else ms_step,
+        "backward_ms": ms_bwd,
+        "gradients_finite": grads_finite,
         "sampler_ms": ms_sample,
         "trajectory_kernel_ms": ms_traj,
         "megb_ms": ms_megb,
         "megb_ms_per_instance": ms_megb / db.n_inst,
-        "fwd_ms": ms_step,
-        "fwd_bwd_ms": ms_fwd_bwd,
-        **({"fwd_bwd_skipped": "batch of %d instances (backward timed up to %d)" % (db.n_inst, BWD_MAX_INST)}
-           if bwd_skipped and not args.no_backward else {}),
+        "megb_us_per_descent_step": ms_megb * 1e3 / gp.megb_iters,
         "sampler_samples_per_s": total_m / (ms_sample * 1e-3),
         "sample_iters_per_s": total_m * cfg["iters"] / (ms_sample * 1e-3),
         "feasible_fraction": float((m & 1).mean()),
@@ -246,10 +254,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": traj_kernel + " (trajectory kernels of the launch)",
-                     "flops_per_launch": flops},
-        "hbm_write_gbs": total_m * 13 / (ms_traj * 1e-3) / 1e9,
+                     "flops_per_launch": flops,
+                     "frac_nonpacked_ceiling": achieved / (FP32_VECTOR_PEAK_TFLOPS / 2),
+                     "flops_per_launch_kernel_formulation": flops_kernel,
+                     "frac_kernel_formulation": flops_kernel / (ms_traj * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS},
+        # write-out: 12 float32 of pose and one mask byte per sample
+        "hbm_write_gbs": total_m * 49 / (ms_traj * 1e-3) / 1e9,
     }
-    if not args.no_cpu_baseline and args.config in ("c1", "c2", "c4"):
+    if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, cfg["iters"], gp.megb_iters)
     print(json.dumps(out), flush=True)
 

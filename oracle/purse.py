@@ -125,6 +125,17 @@ def feasible(prob: Problem, R, t, p: OracleParams, margin: float = 1.0):
     return ok
 
 
+def feasibility_ratio(prob: Problem, R, t, p: OracleParams):
+    """Diagnostic only (no decision uses it): max_i r_i / (beta_i + tau_abs),
+    +inf where a 2D-3D depth is <= z_min.  The in_purse decision is ratio <= 1;
+    how close the ratio is to 1 says how near a pose is to flipping it."""
+    e, r, depth = residual(prob, R, t)
+    ratio = (r / (prob.beta + prob.tau(p))).max(-1).values
+    if depth is not None:
+        ratio = torch.where((depth > p.z_min).all(-1), ratio, torch.full_like(ratio, math.inf))
+    return ratio
+
+
 DERIV_EPS = 1e-5
 
 
@@ -375,34 +386,45 @@ def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams, deriv_convention
     return R, t, failed
 
 
-def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None):
+def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None, margins=None):
     """Bisection on the geodesic segment x(l) = (R_a Exp(l Log(R_a^T R)),
     t_a + l (t - t_a)) from the feasible anchor (l = 0) to the infeasible end
     (l = 1); returns x(lo) after n_bis steps, which is in S, and lo.  With
-    lo_fixed the bisection's outcome is taken as given (frozen decisions)."""
+    lo_fixed the bisection's outcome is taken as given (frozen decisions).
+    margins (a list): receives, per trajectory, the smallest |ratio - 1| of
+    the bisection's feasibility tests (diagnostic)."""
     w = log_so3(Ra.transpose(-1, -2) @ R)
     M = R.shape[0]
     if lo_fixed is None:
         lo = torch.zeros(M, dtype=DT)
         hi = torch.ones(M, dtype=DT)
+        closest = torch.full((M,), math.inf, dtype=DT)
         with torch.no_grad():
             for _ in range(p.n_bis):
                 mid = 0.5 * (lo + hi)
                 Rm = Ra @ exp_so3(mid[:, None] * w)
                 tm = ta + mid[:, None] * (t - ta)
                 f = feasible(prob, Rm, tm, p)
+                if margins is not None:
+                    closest = torch.minimum(closest, (feasibility_ratio(prob, Rm, tm, p) - 1.0).abs())
                 lo = torch.where(f, mid, lo)
                 hi = torch.where(f, hi, mid)
+        if margins is not None:
+            margins.append(closest)
     else:
         lo = torch.as_tensor(np.asarray(lo_fixed), dtype=DT)
     return Ra @ exp_so3(lo[:, None] * w), ta + lo[:, None] * (t - ta), lo
 
 
 def sample(prob: Problem, p: OracleParams, seed: int, n_samples: int,
-           sample_ids: Optional[np.ndarray] = None, pro: Optional[dict] = None) -> dict:
+           sample_ids: Optional[np.ndarray] = None, pro: Optional[dict] = None,
+           diagnostics: bool = False) -> dict:
     """All trajectories of one instance.  Returns poses (M,12) as
     [R row-major | t], mask bits (feasible 1, pulled-in 2, failed 4) and the
-    prologue record."""
+    prologue record.  With diagnostics, also how close each trajectory's
+    decisions were to flipping: end_margin = |ratio - 1| of the final in_purse
+    test and bis_margin = the smallest |ratio - 1| of its bisection tests
+    (inf where it was not pulled in), ratio being max_i r_i / (beta_i + tau)."""
     ids = np.arange(n_samples, dtype=np.uint64) if sample_ids is None else \
         np.asarray(sample_ids, dtype=np.uint64)
     M = len(ids)
@@ -415,13 +437,20 @@ def sample(prob: Problem, p: OracleParams, seed: int, n_samples: int,
     R0, t0 = initial_poses(pro, p, seed, ids)
     R, t, failed = run_trajectories(prob, R0, t0, pro["o_c"], p)
     feas = feasible(prob, R, t, p) & ~failed
+    diag = {}
+    if diagnostics:
+        diag["end_margin"] = (feasibility_ratio(prob, R, t, p) - 1.0).abs()
+        diag["bis_margin"] = torch.full((M,), math.inf, dtype=DT)
     mask = torch.where(feas, MASK_FEASIBLE, 0)
     mask = torch.where(failed, MASK_FAILED, mask)
     need = ~feas & ~failed
     lo_out = torch.full((M,), -1.0, dtype=DT)
     if pro["R_a"] is not None and bool(need.any()):
         idx = torch.nonzero(need)[:, 0]
-        Rb, tb, lo = pull_in(prob, pro["R_a"], pro["t_a"], R[idx], t[idx], p)
+        margins = [] if diagnostics else None
+        Rb, tb, lo = pull_in(prob, pro["R_a"], pro["t_a"], R[idx], t[idx], p, margins=margins)
+        if diagnostics:
+            diag["bis_margin"][idx] = margins[0]
         R = R.clone()
         t = t.clone()
         R[idx] = Rb
@@ -430,4 +459,4 @@ def sample(prob: Problem, p: OracleParams, seed: int, n_samples: int,
         mask[idx] = MASK_FEASIBLE | MASK_PULLED_IN
     poses = torch.cat([R.reshape(M, 9), t], 1)
     return dict(poses=poses, mask=mask.to(torch.uint8), prologue=pro,
-                status=pro["status"], lo=lo_out)
+                status=pro["status"], lo=lo_out, **diag)

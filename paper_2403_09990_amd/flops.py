@@ -45,3 +45,32 @@ def per_trajectory(kind: int, n_kp: int, n_iters: int, n_gn: int = 2) -> int:
 def batch_flops(batch, n_iters: int, n_gn: int = 2) -> int:
     return sum(ins.n_samples * per_trajectory(ins.kind, ins.n_kp, n_iters, n_gn)
                for ins in batch.instances)
+
+
+# ---------------------------------------------------------------------------
+# The method's algorithmic count by the rough per-keypoint model of the
+# method's arithmetic (fused multiply-add = 2, other operations = 1): per
+# sample-iteration 56 N + 650 (3D-3D: transform, projection onto the ball,
+# accumulation; polar step about 550 and composition about 100) and
+# 40 N + n_gn (190 N + 400) (2D-3D: projection onto the ellipse, then per
+# Gauss-Newton step the Jacobian, whitening and normal equations per keypoint
+# and the 6x6 Cholesky, solves, Exp and composition); per sample a final
+# feasibility pass of 25 N, and n_bis (25 N + 60) for each sample pulled in by
+# bisection.  This is the count the roofline fraction is reported against;
+# per_trajectory above is the count of the kernels' own formulation.
+
+def model_per_iteration(kind: int, n_kp: int, n_gn: int = 2) -> int:
+    if kind == 1:
+        return 40 * n_kp + n_gn * (190 * n_kp + 400)
+    return 56 * n_kp + 650
+
+
+def model_batch_flops(batch, n_iters: int, n_gn: int = 2, n_bis: int = 16, pulled=None) -> int:
+    """pulled: per instance, the number of samples pulled in (None: 0)."""
+    tot = 0
+    for j, ins in enumerate(batch.instances):
+        n = ins.n_kp
+        tot += ins.n_samples * (n_iters * model_per_iteration(ins.kind, n, n_gn) + 25 * n)
+        if pulled is not None:
+            tot += int(pulled[j]) * n_bis * (25 * n + 60)
+    return tot

@@ -57,15 +57,27 @@ def rot_angle(Ra, Rb):
     return 2 * np.arcsin(np.minimum(1.0, f / (2 * math.sqrt(2))))
 
 
-def compare_samples(gpu_poses, gpu_mask, ora_poses, ora_mask, max_flip_frac=2e-3):
-    """Per-sample agreement.  Returns stats; asserts the bar: feasibility bits
-    equal except for a few decision flips, and every sample whose bits agree
-    within ROT_TOL / TRANS_TOL except for a few bisection-decision flips."""
+# A decision (a final in_purse test or a bisection step) counts as a hazard
+# when the oracle's ratio max_i r_i / (beta_i + tau) is within this band of 1:
+# a float32 pose differs from the float64 one by up to about 1e-5 (relative)
+# after a hundred iterations, which moves a 2D-3D residual by up to
+# f * 1e-5 / a = 600 * 1e-5 / 3 = 2e-3 of the smallest ellipse's semi-axis a.
+HAZARD_BAND = 2e-3
+
+
+def compare_samples(gpu_poses, gpu_mask, ora_poses, ora_mask, end_margin=None, bis_margin=None,
+                    max_flip_frac=0.0):
+    """Per-sample agreement.  Returns stats; asserts the bar: every mask equal
+    and every pose within ROT_TOL / TRANS_TOL, except where the oracle shows a
+    decision hazard (end_margin / bis_margin within HAZARD_BAND): a mask
+    mismatch needs a hazardous final test, a pose outside tolerance a
+    hazardous final test or bisection step.  Without margins (two GPU runs
+    compared) at most max_flip_frac of the samples may differ."""
     gp = np.asarray(gpu_poses, dtype=np.float64)
     op = np.asarray(ora_poses, dtype=np.float64)
     gm = np.asarray(gpu_mask).astype(np.int64)
     om = np.asarray(ora_mask).astype(np.int64)
-    same = (gm & 1) == (om & 1)
+    same = gm == om
     ang = rot_angle(gp[:, :9].reshape(-1, 3, 3), op[:, :9].reshape(-1, 3, 3))
     dt = np.linalg.norm(gp[:, 9:] - op[:, 9:], axis=1)
     bad = same & ((ang > ROT_TOL) | (dt > TRANS_TOL))
@@ -75,14 +87,40 @@ def compare_samples(gpu_poses, gpu_mask, ora_poses, ora_mask, max_flip_frac=2e-3
                  median_rot=float(np.median(ang[same])) if same.any() else 0.0,
                  pulled=int(((om & 2) != 0).sum()))
     n = len(gm)
-    assert stats["mask_flips"] <= max(1, int(max_flip_frac * n)), stats
-    assert stats["pose_out"] <= max(1, int(max_flip_frac * n)), stats
+    if end_margin is None:
+        allowed = int(max_flip_frac * n)
+        assert stats["mask_flips"] <= allowed, stats
+        assert stats["pose_out"] <= allowed, stats
+        return stats
+    em = np.asarray(end_margin, dtype=np.float64)
+    bm = np.full(n, np.inf) if bis_margin is None else np.asarray(bis_margin, dtype=np.float64)
+    end_hz = em <= HAZARD_BAND
+    bis_hz = bm <= HAZARD_BAND
+    flip_bad = ~same & ~end_hz
+    out_bad = bad & ~(end_hz | bis_hz)
+    stats.update(hazard_end=int(end_hz.sum()), hazard_bis=int(bis_hz.sum()),
+                 forgiven=int((~same | bad).sum() - flip_bad.sum() - out_bad.sum()),
+                 min_end_margin=float(em.min()) if n else float("inf"))
+    assert not flip_bad.any(), dict(stats, ids=np.nonzero(flip_bad)[0][:10].tolist())
+    assert not out_bad.any(), dict(stats, ids=np.nonzero(out_bad)[0][:10].tolist(),
+                                   rot=ang[out_bad][:10].tolist(), trans=dt[out_bad][:10].tolist())
     return stats
+
+
+def compare_with_oracle(gpu_poses, gpu_mask, ora):
+    """compare_samples against an oracle result computed with diagnostics."""
+    return compare_samples(gpu_poses, gpu_mask, ora["poses"].numpy(), ora["mask"].numpy(),
+                           ora.get("end_margin"), ora.get("bis_margin"))
 
 
 def oracle_for_instance(inst, gp, sample_ids):
     prob = Problem.from_instance(as_f32_instance(inst))
-    return oracle_sample(prob, oracle_params(gp), inst.seed, len(sample_ids), sample_ids=sample_ids)
+    ora = oracle_sample(prob, oracle_params(gp), inst.seed, len(sample_ids), sample_ids=sample_ids,
+                        diagnostics=True)
+    if "end_margin" not in ora:  # an instance the prologue rejects: no trajectory ran
+        ora["end_margin"] = torch.full((len(sample_ids),), float("inf"), dtype=torch.float64)
+        ora["bis_margin"] = torch.full((len(sample_ids),), float("inf"), dtype=torch.float64)
+    return ora
 
 
 def oracle_megb(poses, mask, T, avg):

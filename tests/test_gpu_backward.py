@@ -97,6 +97,8 @@ def test_backward_batched_equals_single():
     g_centre = rng.normal(size=(4, 6))
     full = _gpu_backward(res, gp, g_radii, g_centre)
     for j in range(4):
+        # the batched gradients of each instance against the oracle's reverse pass
+        assert _compare(b, res, gp, j, g_radii, g_centre, full) <= 1e-3
         single = PT.run_gpu(W.sub_batch(b, [j]), gp)
         gs = _gpu_backward(single, gp, g_radii[j:j + 1], g_centre[j:j + 1])
         k0, k1 = res["db"].kp_off_host[j], res["db"].kp_off_host[j + 1]
