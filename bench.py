@@ -64,6 +64,10 @@ def read_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def _progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def time_events(fn, reps, stream):
     import torch
     s = torch.cuda.Event(enable_timing=True)
@@ -140,6 +144,7 @@ def main():
     mask = torch.empty(db.total_samples, dtype=torch.uint8, device=dev)
     status = torch.empty(db.n_inst, dtype=torch.int32, device=dev)
     schedule = "default"
+    _progress("workload", args.config, "samples", db.total_samples)
     if not args.no_tune:
         # the sampler's launch schedule (tile size, tile order, keypoint loop),
         # picked by timing the candidates on this batch before the timed region
@@ -177,10 +182,13 @@ def main():
         if not args.no_backward:
             do_backward()
 
+    _progress("schedule", schedule, "; warm-up")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    _progress("timed steps")
     ms_step = time_events(step, args.steps, stream)
+    _progress("step %.3f ms; breakdown" % ms_step)
     total_m = db.total_samples
     value = total_m / (ms_step * 1e-3)
 
@@ -262,6 +270,7 @@ def main():
         "hbm_write_gbs": total_m * 49 / (ms_traj * 1e-3) / 1e9,
     }
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(batch, cfg["iters"], gp.megb_iters)
     print(json.dumps(out), flush=True)
 
