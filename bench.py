@@ -170,8 +170,11 @@ def main():
     def do_megb():
         P.purse_megb(db, gp, poses, mask, centre, radii, nfeas, trace, status, ws, stream)
 
+    bwd_status = torch.empty(db.n_inst, dtype=torch.int32, device=dev)
+
     def do_backward():
-        P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream)
+        P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream,
+                              bwd_status=bwd_status)
 
     def fwd():
         do_sample()
@@ -207,6 +210,7 @@ def main():
     grads_finite = bool(torch.isfinite(g_c).all() and torch.isfinite(g_L).all() and torch.isfinite(g_b).all()) \
         if not args.no_backward else None
     pulled = [int(((m[a:b] & 2) != 0).sum()) for a, b in zip(db.sample_off_host[:-1], db.sample_off_host[1:])]
+    bst = None if args.no_backward else bwd_status.cpu().numpy()
     # the method's algorithmic count (per-keypoint model) and the count of the
     # kernels' own formulation, both per trajectory launch
     flops = F.model_batch_flops(batch, cfg["iters"], gp.n_gn, gp.n_bis, pulled)
@@ -248,6 +252,9 @@ def main():
         "fwd_bwd_ms": None if args.no_backward else ms_step,
         "backward_ms": ms_bwd,
         "gradients_finite": grads_finite,
+        **({} if bst is None else {
+            "backward_status_counts": {str(k): int(v) for k, v in zip(*np.unique(bst & 0xFF, return_counts=True))},
+            "active_set_max": int((bst >> 8).max()), "active_set_mean": float((bst >> 8).mean())}),
         "sampler_ms": ms_sample,
         "trajectory_kernel_ms": ms_traj,
         "megb_ms": ms_megb,

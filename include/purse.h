@@ -233,15 +233,25 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
  *            3-vector at R* followed by the R^3 cotangent of t*
  *            ([n_inst][12] with PURSE_FLAG_MATRIX_COTANGENT).
  * Outputs (overwritten):
- *   g_centres [total_kp][3] float: d/d centres (b_i, or z_i in x, y; third unused = 0)
- *   g_shapes  [total_kp][4] float: d/d Lambda_i, symmetrised (zeros for 3D-3D)
- *   g_bounds  [total_kp]    float: d/d beta_i
+ *   g_centres  [total_kp][3] float: d/d centres (b_i, or z_i in x, y; third unused = 0)
+ *   g_shapes   [total_kp][4] float: d/d Lambda_i, symmetrised (zeros for 3D-3D)
+ *   g_bounds   [total_kp]    float: d/d beta_i
+ *   bwd_status [n_inst] int32 (may be NULL): the instance's outcome in the low
+ *              byte (PURSE_BWD_*), and in the bits above it the number of
+ *              distinct samples its descent touched (the active set).
  */
+#define PURSE_BWD_OK 0
+#define PURSE_BWD_EMPTY 1        /* no feasible sample: zero gradients */
+#define PURSE_BWD_OVERFLOW 2     /* the descent touched more samples than the active set holds: NaN */
+#define PURSE_BWD_BAD_TRACE 3    /* a trace entry is not a feasible sample of the instance: NaN */
+#define PURSE_BWD_STALE 4        /* workspace records of another batch or data: NaN */
+#define PURSE_BWD_NON_FINITE 5   /* non-finite centre: NaN */
 purse_status purse_megb_backward(const purse_batch *b, const purse_params *p,
                                  const float *poses, const uint8_t *mask,
                                  const int32_t *trace, const double *g_radii,
                                  const float *g_centre, float *g_centres, float *g_shapes,
-                                 float *g_bounds, void *ws, size_t ws_bytes, void *stream);
+                                 float *g_bounds, int32_t *bwd_status, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /* Static description of a status code. */
 const char *purse_status_string(purse_status s);

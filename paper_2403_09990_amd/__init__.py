@@ -13,7 +13,8 @@ from typing import Optional
 from . import _native
 from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
                       PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_MATRIX_COTANGENT, PURSE_FLAG_PAIR_LANES,
-                      PURSE_FLAG_QUAD_LANES,
+                      PURSE_FLAG_QUAD_LANES, PURSE_BWD_BAD_TRACE, PURSE_BWD_EMPTY, PURSE_BWD_NON_FINITE,
+                      PURSE_BWD_OK, PURSE_BWD_OVERFLOW, PURSE_BWD_STALE,
                       PURSE_FLAG_REPLAY_DESCENT,
                       PURSE_FLAG_REUSE_PROLOGUE,
                       PURSE_INST_ANCHOR_ITERATED, PURSE_INST_BAD_SHAPE, PURSE_INST_BAD_SIZE,
@@ -121,11 +122,11 @@ def purse_megb(db, params, poses, mask, centre, radii, n_feasible, trace, inst_s
 
 
 def purse_megb_backward(db, params, poses, mask, trace, g_radii, g_centre, g_centres, g_shapes,
-                        g_bounds, ws, stream=None):
+                        g_bounds, ws, stream=None, bwd_status=None):
     _check(_native.load().purse_megb_backward(
         ctypes.byref(db.struct), ctypes.byref(params), _ptr(poses), _ptr(mask), _ptr(trace),
-        _ptr(g_radii), _ptr(g_centre), _ptr(g_centres), _ptr(g_shapes), _ptr(g_bounds), _ptr(ws),
-        ws.numel(), _stream(stream)), "purse_megb_backward")
+        _ptr(g_radii), _ptr(g_centre), _ptr(g_centres), _ptr(g_shapes), _ptr(g_bounds), _ptr(bwd_status),
+        _ptr(ws), ws.numel(), _stream(stream)), "purse_megb_backward")
 
 
 # ----------------------------------------------------------------------------

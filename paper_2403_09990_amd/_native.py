@@ -20,6 +20,13 @@ PURSE_INST_BAD_SIZE = 4
 PURSE_INST_NO_ANCHOR = 1 << 8
 PURSE_INST_ANCHOR_ITERATED = 1 << 9
 
+PURSE_BWD_OK = 0
+PURSE_BWD_EMPTY = 1
+PURSE_BWD_OVERFLOW = 2
+PURSE_BWD_BAD_TRACE = 3
+PURSE_BWD_STALE = 4
+PURSE_BWD_NON_FINITE = 5
+
 PURSE_MASK_FEASIBLE = 1
 PURSE_MASK_PULLED_IN = 2
 PURSE_MASK_FAILED = 4
@@ -98,7 +105,7 @@ def load(path: str = LIB_PATH):
     lib.purse_megb.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
                                ctypes.c_size_t, vp]
     lib.purse_megb_backward.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
-                                        vp, ctypes.c_size_t, vp]
+                                        vp, vp, ctypes.c_size_t, vp]
     for f in ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_megb",
               "purse_megb_backward"):
         getattr(lib, f).restype = ctypes.c_int32

@@ -122,6 +122,28 @@ T *at(void *ws, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
 
+// The sampler's part of a call: prologue (unless reused) and trajectories,
+// with the instance records, keypoint records and tile schedule in ws (the
+// first three regions of the workspace layout).
+purse_status sample_into(const purse_batch *b, const purse_params *p, float *poses, uint8_t *mask,
+                         int32_t *inst_status, void *ws, hipStream_t st) {
+  const purse::WsLayout L = layout_for(b, p);
+  const purse::DevBatch db = dev_batch(b);
+  const purse::DevParams dp = dev_params(p);
+  auto *inst = at<purse::InstRec>(ws, L.inst);
+  auto *kp = at<purse::KpRec>(ws, L.kp);
+  purse_status s;
+  if (!(p->flags & PURSE_FLAG_REUSE_PROLOGUE)) {
+    purse::launch_prologue(db, dp, inst, kp, inst_status, st);
+    if ((s = hip_check(hipGetLastError(), "prologue launch"))) return s;
+  }
+  const int tile = p->tile ? p->tile : 256;
+  if (purse::sample_grid(b->total_samples, b->n_inst, tile / 2) > INT32_MAX)
+    return fail(PURSE_E_BAD_ARG, "too many sample tiles for one launch");
+  purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, st);
+  return hip_check(hipGetLastError(), "sampler launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -163,21 +185,7 @@ purse_status purse_sample(const purse_batch *b, const purse_params *p, float *po
   if (!poses || !mask || !inst_status) return fail(PURSE_E_NULL, "an output is NULL");
   if ((s = check_ws(b, p, ws, ws_bytes))) return s;
   if ((s = check_device())) return s;
-  const purse::WsLayout L = layout_for(b, p);
-  const purse::DevBatch db = dev_batch(b);
-  const purse::DevParams dp = dev_params(p);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  auto *inst = at<purse::InstRec>(ws, L.inst);
-  auto *kp = at<purse::KpRec>(ws, L.kp);
-  if (!(p->flags & PURSE_FLAG_REUSE_PROLOGUE)) {
-    purse::launch_prologue(db, dp, inst, kp, inst_status, st);
-    if ((s = hip_check(hipGetLastError(), "prologue launch"))) return s;
-  }
-  const int tile = p->tile ? p->tile : 256;
-  if (purse::sample_grid(b->total_samples, b->n_inst, tile / 2) > INT32_MAX)
-    return fail(PURSE_E_BAD_ARG, "too many sample tiles for one launch");
-  purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, st);
-  return hip_check(hipGetLastError(), "sampler launch");
+  return sample_into(b, p, poses, mask, inst_status, ws, static_cast<hipStream_t>(stream));
 }
 
 purse_status purse_megb(const purse_batch *b, const purse_params *p, const float *poses, const uint8_t *mask,
@@ -202,8 +210,8 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
 
 purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, const float *poses,
                                  const uint8_t *mask, const int32_t *trace, const double *g_radii,
-                                 const float *g_centre, float *g_centres, float *g_shapes, float *g_bounds, void *ws,
-                                 size_t ws_bytes, void *stream) {
+                                 const float *g_centre, float *g_centres, float *g_shapes, float *g_bounds,
+                                 int32_t *bwd_status, void *ws, size_t ws_bytes, void *stream) {
   purse_status s = check_batch(b);
   if (s) return s;
   if ((s = check_params(p))) return s;
@@ -216,8 +224,8 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
   const purse::DevParams dp = dev_params(p);
   const hipError_t e = purse::launch_backward(db, dp, poses, mask, trace, g_radii, g_centre, at<purse::InstRec>(ws, L.inst),
                          at<purse::KpRec>(ws, L.kp), at<purse::MegbRec>(ws, L.megb), at<purse::BwdRec>(ws, L.bwd),
-                         at<float4>(ws, L.ckpt),
-                         at<float>(ws, L.tan), at<float>(ws, L.contrib), g_centres, g_shapes, g_bounds,
+                         at<float4>(ws, L.ckpt), at<float>(ws, L.tan), at<float>(ws, L.contrib),
+                         at<int64_t>(ws, L.items), g_centres, g_shapes, g_bounds, bwd_status,
                          static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_check(e, "backward stream join");
   return hip_check(hipGetLastError(), "backward launch");

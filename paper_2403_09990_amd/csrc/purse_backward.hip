@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
                                                         const InstRec *__restrict__ inst, MegbRec *megb,
                                                         BwdRec *recs, float4 *ckpt_all, int ck) {
   __shared__ int act[kMaxActive];
-  __shared__ int n_act_s, err_s;  // err_s: a BwdRec status (kBwdOk while the sweep may run)
+  __shared__ int n_act_s, err_s, n_distinct_s;  // err_s: a BwdRec status (kBwdOk while the sweep may run)
   __shared__ double cot[kMaxActive][12];
   __shared__ float pact[kMaxActive][12];       // poses of the active samples
   __shared__ float4 qact[kMaxActive];          // their rotations as quaternions
@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   if (err_s != kBwdOk) {
     if (tid == 0) {
       rec->n_act = 0;
+      rec->n_distinct = 0;
       rec->status = err_s;
     }
     return;
@@ -202,6 +203,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   if (s0 == INT32_MAX) {
     if (tid == 0) {
       rec->n_act = 0;
+      rec->n_distinct = 0;
       rec->status = kBwdEmpty;
     }
     return;
@@ -219,6 +221,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     if (bad) {
       if (tid == 0) {
         rec->n_act = 0;
+        rec->n_distinct = 0;
         rec->status = kBwdBadTrace;
       }
       return;
@@ -251,6 +254,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
         megb[j].ck_every = ck;
       }
       n_act_s = 0;
+      n_distinct_s = 0;
     }
   }
   __syncthreads();
@@ -269,6 +273,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
     __syncthreads();
     if (mn == INT32_MAX) break;
     if (tid == 0) {
+      ++n_distinct_s;
       if (n_act_s < kMaxActive)
         act[n_act_s++] = mn;
       else
@@ -765,6 +770,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_bwd_megb(DevBatch b, DevParams p,
   __syncthreads();
   if (tid == 0) {
     rec->n_act = err_s != kBwdOk ? 0 : n_act;
+    rec->n_distinct = n_distinct_s;
     rec->status = err_s;
     rec->s0 = s0;
     rec->sD = sD_s;
@@ -975,48 +981,114 @@ __global__ void __launch_bounds__(kMaxDirs) k_bwd_frame(DevBatch b, DevParams p,
   for (int r = 0; r < 3; ++r) tan[24 + r] = F.ta[r].d;
 }
 
-// Tangent of active sample a's pose along 64 directions, dotted with its cotangent.
+// Work items of the tangent kernels: instance j contributes n_act_j x zb_j
+// items (zb_j workgroups of 64 lanes cover its directions, `lanes` lanes per
+// direction), listed by an exclusive prefix sum over the instances of the
+// kind, so a fixed grid walks exactly the items the active sets need
+// (instead of a grid sized for full active sets, which dispatches mostly
+// empty workgroups).
+__device__ __forceinline__ int item_blocks(int n_kp, int kind, int lanes) {
+  return (n_kp * dirs_per_kp(kind) * lanes + 63) / 64;
+}
+
+__global__ void __launch_bounds__(1024) k_bwd_items(DevBatch b, const InstRec *__restrict__ inst,
+                                                    const BwdRec *recs, int kind, int lanes,
+                                                    int64_t *__restrict__ item_off) {
+  __shared__ int64_t part[1024];
+  const int n = b.n_inst, tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int j0 = tid * per, j1 = min(n, j0 + per);
+  auto items_of = [&](int j) -> int64_t {
+    const BwdRec &r = recs[j];
+    const InstRec I = inst[j];
+    if (r.status != kBwdOk || I.kind != kind || (I.status & 0xFF) != PURSE_INST_OK || !inst_record_ok(I, inst_view(b, j)))
+      return 0;
+    return (int64_t)min(max(r.n_act, 0), kMaxActive) * item_blocks(I.n_kp, kind, lanes);
+  };
+  int64_t acc = 0;
+  for (int j = j0; j < j1; ++j) acc += items_of(j);
+  part[tid] = acc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = tid ? part[tid - 1] : 0;
+  for (int j = j0; j < j1; ++j) {
+    item_off[j] = run;
+    run += items_of(j);
+  }
+  if (tid == 1023) item_off[n] = part[1023];
+}
+
+// Item -> (instance, active slot, block of directions).
+__device__ __forceinline__ void item_at(const int64_t *__restrict__ item_off, int n, int64_t it, const InstRec *inst,
+                                        int kind, int lanes, int &j, int &a, int &z) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {  // the last instance whose range starts at or before it
+    const int mid = (lo + hi + 1) >> 1;
+    if (item_off[mid] <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  j = lo;
+  const int zb = item_blocks(inst[j].n_kp, kind, lanes);
+  const int64_t local = it - item_off[j];
+  a = (int)(local / zb);
+  z = (int)(local % zb);
+}
+
+constexpr int kItemGrid = 8192;  // workgroups of the tangent kernels (each walks items kItemGrid apart)
+
+// Tangent of active sample a's pose along 64 directions, dotted with its
+// cotangent; one work item per workgroup iteration.
 template <int KIND>
 __global__ void __launch_bounds__(64) k_bwd_traj(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
                                                  const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                 const int64_t *__restrict__ item_off,
                                                  const float *__restrict__ tan_all, float *contrib, int max_dirs) {
-  const int a = blockIdx.x, j = blockIdx.y;
-  const int d = blockIdx.z * 64 + threadIdx.x;
-  const BwdRec *rec = recs + j;
-  // k_bwd_megb of this call checked the instance record against the batch
-  // and its data; only then is the status ok and the active set non-empty
-  if (rec->status != kBwdOk || a >= min(rec->n_act, kMaxActive)) return;
-  const InstRec I = inst[j];
-  if (I.kind != KIND || (I.status & 0xFF) != PURSE_INST_OK || !inst_record_ok(I, inst_view(b, j))) return;
-  const int dpk = dirs_per_kp(KIND);
-  if (d >= I.n_kp * dpk) return;
-  const int i_d = d / dpk, c = d % dpk;
-  const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
-  FrameT<Dual<float>> F;
-  for (int k = 0; k < 9; ++k) {
-    F.Rc[k] = Dual<float>(I.Rc[k], tan[k]);
-    F.Ra[k] = Dual<float>(I.Ra[k], tan[15 + k]);
+  const int64_t total = item_off[b.n_inst];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int j, a, z;
+    item_at(item_off, b.n_inst, it, inst, KIND, 1, j, a, z);
+    const int d = z * 64 + threadIdx.x;
+    const BwdRec *rec = recs + j;
+    // (listed only when k_bwd_megb of this call found the instance record
+    // to match the batch and its data, and the active set within capacity)
+    const InstRec I = inst[j];
+    const int dpk = dirs_per_kp(KIND);
+    if (d >= I.n_kp * dpk) continue;
+    const int i_d = d / dpk, c = d % dpk;
+    const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
+    FrameT<Dual<float>> F;
+    for (int k = 0; k < 9; ++k) {
+      F.Rc[k] = Dual<float>(I.Rc[k], tan[k]);
+      F.Ra[k] = Dual<float>(I.Ra[k], tan[15 + k]);
+    }
+    for (int r = 0; r < 3; ++r) {
+      F.tc[r] = Dual<float>(I.tc[r], tan[9 + r]);
+      F.oc[r] = Dual<float>(I.oc[r], tan[12 + r]);
+      F.ta[r] = Dual<float>(I.ta[r], tan[24 + r]);
+    }
+    KpDual kpl;
+    kpl.kp = kprec + I.kp_off;
+    kpl.i_d = i_d;
+    kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
+               kpl.tk);
+    const int s = rec->active[a];
+    PoseT<Dual<float>> x = initial_pose<Dual<float>>(F, I.seed, (uint64_t)s, p);
+    int nfb = 0;
+    const uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, nfb);
+    double acc = 0.0;
+    if (m & PURSE_MASK_FEASIBLE) {
+      for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
+      for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
+    }
+    contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
   }
-  for (int r = 0; r < 3; ++r) {
-    F.tc[r] = Dual<float>(I.tc[r], tan[9 + r]);
-    F.oc[r] = Dual<float>(I.oc[r], tan[12 + r]);
-    F.ta[r] = Dual<float>(I.ta[r], tan[24 + r]);
-  }
-  KpDual kpl;
-  kpl.kp = kprec + I.kp_off;
-  kpl.i_d = i_d;
-  kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
-             kpl.tk);
-  const int s = rec->active[a];
-  PoseT<Dual<float>> x = initial_pose<Dual<float>>(F, I.seed, (uint64_t)s, p);
-  int nfb = 0;
-  const uint8_t m = run_trajectory<KIND>(I, F, kpl, x, p, true, nfb);
-  double acc = 0.0;
-  if (m & PURSE_MASK_FEASIBLE) {
-    for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
-    for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
-  }
-  contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,59 +1237,64 @@ __device__ __forceinline__ uint8_t run_trajectory_group(const InstRec &I, const 
   return PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
 }
 
-// k_bwd_traj for 2D-3D instances with G lanes per direction: workgroup
-// (a, j, z) covers active sample a and directions z * 64 / G ... of instance j.
+// k_bwd_traj for 2D-3D instances with G lanes per direction: work item
+// (j, a, z) covers active sample a and directions z * 64 / G ... of instance j.
 template <int G>
 __global__ void __launch_bounds__(64) k_bwd_traj2d_group(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
                                                          const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                         const int64_t *__restrict__ item_off,
                                                          const float *__restrict__ tan_all, float *contrib,
                                                          int max_dirs) {
-  const int a = blockIdx.x, j = blockIdx.y;
+  const int64_t total = item_off[b.n_inst];
   const int q = threadIdx.x % G;
-  const int d = blockIdx.z * (64 / G) + threadIdx.x / G;
-  const BwdRec *rec = recs + j;
-  // (see k_bwd_traj)
-  if (rec->status != kBwdOk || a >= min(rec->n_act, kMaxActive)) return;
-  const InstRec I = inst[j];
-  if (I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK || !inst_record_ok(I, inst_view(b, j))) return;
-  const int dpk = dirs_per_kp(PURSE_KIND_2D3D);
-  if (d >= I.n_kp * dpk) return;  // (whole lane groups)
-  const int i_d = d / dpk, c = d % dpk;
-  const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
-  FrameT<DF> F;
-  for (int k = 0; k < 9; ++k) {
-    F.Rc[k] = DF(I.Rc[k], tan[k]);
-    F.Ra[k] = DF(I.Ra[k], tan[15 + k]);
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int j, a, z;
+    item_at(item_off, b.n_inst, it, inst, PURSE_KIND_2D3D, G, j, a, z);
+    const int d = z * (64 / G) + threadIdx.x / G;
+    const BwdRec *rec = recs + j;
+    // (see k_bwd_traj)
+    const InstRec I = inst[j];
+    const int dpk = dirs_per_kp(PURSE_KIND_2D3D);
+    if (d >= I.n_kp * dpk) continue;  // (whole lane groups)
+    const int i_d = d / dpk, c = d % dpk;
+    const float *tan = tan_all + ((int64_t)j * max_dirs + d) * 27;
+    FrameT<DF> F;
+    for (int k = 0; k < 9; ++k) {
+      F.Rc[k] = DF(I.Rc[k], tan[k]);
+      F.Ra[k] = DF(I.Ra[k], tan[15 + k]);
+    }
+    for (int r = 0; r < 3; ++r) {
+      F.tc[r] = DF(I.tc[r], tan[9 + r]);
+      F.oc[r] = DF(I.oc[r], tan[12 + r]);
+      F.ta[r] = DF(I.ta[r], tan[24 + r]);
+    }
+    KpDual kpl;
+    kpl.kp = kprec + I.kp_off;
+    kpl.i_d = i_d;
+    kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
+               kpl.tk);
+    const int s = rec->active[a];
+    PoseT<DF> x = initial_pose<DF>(F, I.seed, (uint64_t)s, p);
+    const uint8_t m = run_trajectory_group<G>(I, F, kpl, q, x, p);
+    if (q == 0) {
+      double acc = 0.0;
+      if (m & PURSE_MASK_FEASIBLE) {
+        for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
+        for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
+      }
+      contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
+    }
   }
-  for (int r = 0; r < 3; ++r) {
-    F.tc[r] = DF(I.tc[r], tan[9 + r]);
-    F.oc[r] = DF(I.oc[r], tan[12 + r]);
-    F.ta[r] = DF(I.ta[r], tan[24 + r]);
-  }
-  KpDual kpl;
-  kpl.kp = kprec + I.kp_off;
-  kpl.i_d = i_d;
-  kp_tangent(I, kprec[I.kp_off + i_d], b.shapes + 4 * (I.kp_off + i_d), b.bounds[I.kp_off + i_d], p.kappa, c,
-             kpl.tk);
-  const int s = rec->active[a];
-  PoseT<DF> x = initial_pose<DF>(F, I.seed, (uint64_t)s, p);
-  const uint8_t m = run_trajectory_group<G>(I, F, kpl, q, x, p);
-  if (q != 0) return;
-  double acc = 0.0;
-  if (m & PURSE_MASK_FEASIBLE) {
-    for (int k = 0; k < 9; ++k) acc += rec->cot[a][k] * (double)x.R[k].d;
-    for (int r = 0; r < 3; ++r) acc += rec->cot[a][9 + r] * (double)x.t[r].d;
-  }
-  contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = (float)acc;
 }
 
 // Sum over active samples (fixed order) and scatter into the gradients.
 __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstRec *__restrict__ inst,
                                                         const BwdRec *recs, const float *__restrict__ contrib,
                                                         int max_dirs, float *g_centres, float *g_shapes,
-                                                        float *g_bounds) {
+                                                        float *g_bounds, int32_t *bwd_status) {
   const int j = blockIdx.x;
   const int d = threadIdx.x;
+  if (d == 0 && bwd_status) bwd_status[j] = recs[j].status | (min(recs[j].n_distinct, 0xFFFFFF) << 8);
   const InstView v = inst_view(b, j);
   if (!inst_view_ok(v)) return;  // (the batch's own ranges: nothing can be addressed)
   const int64_t ko = v.kp_off;
@@ -1303,7 +1380,8 @@ Aux *aux_stream() {
 hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                            const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
                            const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
-                           float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream) {
+                           int64_t *items, float *g_centres, float *g_shapes, float *g_bounds, int32_t *bwd_status,
+                           hipStream_t stream) {
   const int n = b.n_inst;
   const int ck = ckpt_spacing(p.ckpt_every);
   const int max_dirs = 6 * b.max_kp;
@@ -1326,16 +1404,18 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
       hipLaunchKernelGGL(k_bwd_frame, dim3(n), dim3(kMaxDirs), 0, stream, b, p, inst, kp, tan, max_dirs);
     }
   }
-  dim3 grid(kMaxActive, n, (max_dirs + 63) / 64);
-  // 2D-3D directions on lane groups (every 2D-3D instance, so its gradients
-  // do not depend on the batch around it)
-  dim3 grid_g(kMaxActive, n, (max_dirs * kTrajGroup + 63) / 64);
-  hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, grid_g, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
-                     max_dirs);
-  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, grid, dim3(64), 0, stream, b, p, inst, kp, recs, tan, contrib,
-                     max_dirs);
+  // the tangent kernels walk lists of the (instance, active sample,
+  // direction block) items the active sets need
+  hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_2D3D, kTrajGroup,
+                     items);
+  hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
+                     items + (n + 1));
+  hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
+                     items, tan, contrib, max_dirs);
+  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
+                     items + (n + 1), tan, contrib, max_dirs);
   hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
-                     g_shapes, g_bounds);
+                     g_shapes, g_bounds, bwd_status);
   return hipSuccess;
 }
 

@@ -33,6 +33,7 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
 hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
                            const int32_t *trace, const double *g_radii, const float *g_centre, const InstRec *inst,
                            const KpRec *kp, MegbRec *megb, BwdRec *recs, float4 *ckpt, float *tan, float *contrib,
-                           float *g_centres, float *g_shapes, float *g_bounds, hipStream_t stream);
+                           int64_t *items, float *g_centres, float *g_shapes, float *g_bounds, int32_t *bwd_status,
+                           hipStream_t stream);
 
 }  // namespace purse

@@ -86,8 +86,10 @@ constexpr int kMaxDirs = 6 * PURSE_MAX_KP;
 
 struct BwdRec {
   int32_t n_act;   // active samples (sorted ids in `active`)
-  int32_t status;  // 0 ok, 1 empty, 2 active set beyond capacity, 3 trace inconsistent with mask
-  int32_t s0, sD, sd, pad;
+  int32_t status;  // 0 ok, 1 empty, 2 active set beyond capacity, 3 trace inconsistent with mask,
+                   // 4 records of another batch or data, 5 non-finite centre
+  int32_t s0, sD, sd;
+  int32_t n_distinct;  // distinct samples the descent touched (also beyond capacity)
   int32_t active[kMaxActive];
   double cot[kMaxActive][12];  // cotangent of each active pose: R (row-major), t
 };
@@ -96,7 +98,7 @@ constexpr size_t kAlign = 256;
 __host__ __device__ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, total;
+  size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, items, total;
 };
 
 // Tile schedule of the sampler, one per launch group (3D-3D; 2D-3D with the
@@ -135,6 +137,8 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   o += align_up(sizeof(float) * 27 * (size_t)n_inst * dirs);
   L.contrib = o;
   o += align_up(sizeof(float) * (size_t)n_inst * kMaxActive * dirs);
+  L.items = o;  // work-item prefix sums of the tangent kernels, 2D-3D then 3D-3D
+  o += align_up(sizeof(int64_t) * 2 * ((size_t)n_inst + 1));
   L.total = o;
   return L;
 }

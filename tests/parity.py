@@ -58,11 +58,13 @@ def rot_angle(Ra, Rb):
 
 
 # A decision (a final in_purse test or a bisection step) counts as a hazard
-# when the oracle's ratio max_i r_i / (beta_i + tau) is within this band of 1:
-# a float32 pose differs from the float64 one by up to about 1e-5 (relative)
-# after a hundred iterations, which moves a 2D-3D residual by up to
-# f * 1e-5 / a = 600 * 1e-5 / 3 = 2e-3 of the smallest ellipse's semi-axis a.
-HAZARD_BAND = 2e-3
+# when the oracle's ratio max_i r_i / (beta_i + tau) is within this band of 1.
+# Float32 poses differ from the float64 ones by a few 1e-6 rad (measured),
+# which moves a 2D-3D residual by up to f * 3e-6 / a = 600 * 3e-6 / 5 = 4e-4
+# of an ellipse's semi-axis a; the band stays below the 1e-3 gap the shrink
+# factor kappa = 0.999 leaves between converged trajectories (ratio about
+# kappa) and the boundary, so a converged sample never counts as a hazard.
+HAZARD_BAND = 5e-4
 
 
 def compare_samples(gpu_poses, gpu_mask, ora_poses, ora_mask, end_margin=None, bis_margin=None,

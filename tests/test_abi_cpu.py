@@ -134,3 +134,4 @@ def test_status_strings():
     lib = _native.load()
     for code in (0, -1, -2, -3, -4, -5, 7):
         assert lib.purse_status_string(code)
+

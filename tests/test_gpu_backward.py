@@ -19,18 +19,23 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _gpu_backward(res, gp, g_radii, g_centre):
+def _gpu_backward(res, gp, g_radii, g_centre, status_out=None):
     import paper_2403_09990_amd as P
     db = res["db"]
     dev = res["poses"].device
     g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
     g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
     g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
+    st = torch.full((db.n_inst,), -1, dtype=torch.int32, device=dev)
     P.purse_megb_backward(db, gp, res["poses"], res["mask"], res["trace"],
                           torch.as_tensor(g_radii, dtype=torch.float64, device=dev).contiguous(),
                           torch.as_tensor(g_centre, dtype=torch.float32, device=dev).contiguous(),
-                          g_c, g_L, g_b, res["ws"])
+                          g_c, g_L, g_b, res["ws"], bwd_status=st)
     torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    _log("backward status", (st & 0xFF).tolist()[:16], "active sets", (st >> 8).tolist()[:16])
+    if status_out is not None:
+        status_out.append(st)
     return g_c.cpu().numpy(), g_L.cpu().numpy(), g_b.cpu().numpy()
 
 
@@ -230,9 +235,11 @@ def test_backward_rejects_a_workspace_of_other_data():
     db2.centres[10:] += 0.002
     P.sample(db2, gp, ws=res["ws"])
     torch.cuda.synchronize()
-    stale = _gpu_backward(res, gp, g_radii, g_centre)
+    sts = []
+    stale = _gpu_backward(res, gp, g_radii, g_centre, sts)
+    assert (sts[0] & 0xFF).tolist() == [P.PURSE_BWD_OK, P.PURSE_BWD_STALE]
     k0, k1 = res["db"].kp_off_host[1], res["db"].kp_off_host[2]
-    for x in stale:
-        assert np.isnan(x[k0:k1]).all()
+    # (3D-3D shapes carry no gradient: zeros either way)
+    assert np.isnan(stale[0][k0:k1]).all() and np.isnan(stale[2][k0:k1]).all()
     for g, x in zip(good, stale):
         np.testing.assert_array_equal(g[:k0], x[:k0])

@@ -123,11 +123,16 @@ def test_c5_full_size_forward_and_backward():
     g_c = torch.empty(db.total_kp, 3, dtype=torch.float32, device=dev)
     g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
     g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
+    bst = torch.full((64,), -1, dtype=torch.int32, device=dev)
     P.purse_megb_backward(db, gp, res["poses"], res["mask"], res["trace"],
                           torch.as_tensor(g_radii, dtype=torch.float64, device=dev),
                           torch.as_tensor(g_centre, dtype=torch.float32, device=dev),
-                          g_c, g_L, g_b, res["ws"])
+                          g_c, g_L, g_b, res["ws"], bwd_status=bst)
     torch.cuda.synchronize()
+    bst = bst.cpu().numpy()
+    _log("backward status per instance", (bst & 0xFF).tolist())
+    _log("active-set sizes", (bst >> 8).tolist())
+    assert ((bst & 0xFF) == P.PURSE_BWD_OK).all()
     gpu = (g_c.cpu().numpy(), g_L.cpu().numpy(), g_b.cpu().numpy())
     assert all(np.isfinite(x).all() for x in gpu)
     for j in (0, 63):
