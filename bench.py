@@ -122,6 +122,7 @@ def main():
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--no-backward", action="store_true", help="time the forward alone as the step")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
+    ap.add_argument("--no-graph", action="store_true", help="time the eager step instead of its graph replay")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -163,17 +164,18 @@ def main():
     g_L = torch.empty(db.total_kp, 4, dtype=torch.float32, device=dev)
     g_b = torch.empty(db.total_kp, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
-
-    def do_sample(params=gp):
-        P.purse_sample(db, params, poses, mask, status, ws, stream)
-
-    def do_megb():
-        P.purse_megb(db, gp, poses, mask, centre, radii, nfeas, trace, status, ws, stream)
-
     bwd_status = torch.empty(db.n_inst, dtype=torch.int32, device=dev)
 
+    # every call goes to the stream current at call time (the capture stream
+    # while the step is being captured into a graph)
+    def do_sample(params=gp):
+        P.purse_sample(db, params, poses, mask, status, ws)
+
+    def do_megb():
+        P.purse_megb(db, gp, poses, mask, centre, radii, nfeas, trace, status, ws)
+
     def do_backward():
-        P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws, stream,
+        P.purse_megb_backward(db, gp, poses, mask, trace, g_radii, g_centre, g_c, g_L, g_b, ws,
                               bwd_status=bwd_status)
 
     def fwd():
@@ -189,9 +191,37 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # the whole step captured once into a HIP graph and replayed in the
+    # timed region; the first replay is checked against the eager step
+    graph = None
+    graph_check = None
+    if not args.no_graph:
+        ref = [x.clone() for x in (poses, mask, radii, trace, g_c, g_b)]
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+        for x in (poses, g_c, g_b):
+            x.fill_(float("nan"))
+        radii.fill_(float("nan"))
+        trace.fill_(-7)
+        graph.replay()
+        torch.cuda.synchronize()
+        graph_check = all(torch.equal(a, b) if a.dtype not in (torch.float32, torch.float64)
+                          else bool(torch.equal(torch.nan_to_num(a, 7.0), torch.nan_to_num(b, 7.0)))
+                          for a, b in zip(ref, (poses, mask, radii, trace, g_c, g_b)))
+        _progress("graph captured; replay equals the eager step:", graph_check)
+    run_step = graph.replay if graph is not None else step
     _progress("timed steps")
-    ms_step = time_events(step, args.steps, stream)
-    _progress("step %.3f ms; breakdown" % ms_step)
+    ms_step = time_events(run_step, args.steps, stream)
+    ms_step_eager = time_events(step, max(1, args.steps // 2), stream) if graph is not None else ms_step
+    _progress("step %.3f ms (eager %.3f ms); breakdown" % (ms_step, ms_step_eager))
     total_m = db.total_samples
     value = total_m / (ms_step * 1e-3)
 
@@ -247,6 +277,9 @@ def main():
                    "step": "sample + MEGB" + ("" if args.no_backward else " + backward (all instances, one call)"),
                    "parallelism": "single GPU"},
         "sampler_schedule": schedule,
+        "timed_as": "graph replay" if graph is not None else "eager launches",
+        "graph_replay_equals_eager": graph_check,
+        "ms_per_step_eager": ms_step_eager,
         "fwd_ms": ms_fwd,
         "fwd_samples_per_s": total_m / (ms_fwd * 1e-3),
         "fwd_bwd_ms": None if args.no_backward else ms_step,

@@ -34,46 +34,43 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 }
 
 // ---------------------------------------------------------------------------
-// precision-generic scalar helpers
-template <typename T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
-template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
-template <typename T> __device__ __forceinline__ T drsqrt(T x);
-template <> __device__ __forceinline__ float drsqrt<float>(float x) { return rsqrtf(x); }
-template <> __device__ __forceinline__ double drsqrt<double>(double x) { return 1.0 / sqrt(x); }
-template <typename T> __device__ __forceinline__ void dsincos(T x, T *s, T *c);
-template <> __device__ __forceinline__ void dsincos<float>(float x, float *s, float *c) { sincosf(x, s, c); }
-template <> __device__ __forceinline__ void dsincos<double>(double x, double *s, double *c) { sincos(x, s, c); }
-template <typename T> __device__ __forceinline__ T datan2(T y, T x);
-template <> __device__ __forceinline__ float datan2<float>(float y, float x) { return atan2f(y, x); }
-template <> __device__ __forceinline__ double datan2<double>(double y, double x) { return atan2(y, x); }
+// precision-generic scalar helpers (overloads per precision; the float64
+// ones are also host functions, so the host tests run the float64 paths)
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__host__ __device__ inline double dsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float drsqrt(float x) { return rsqrtf(x); }
+__host__ __device__ inline double drsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ void dsincos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float datan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double datan2(double y, double x) { return atan2(y, x); }
 
 // reciprocal: the hardware approximation (1 ulp) in float32, exact otherwise
-template <typename T> __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
-template <> __device__ __forceinline__ float drcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__host__ __device__ inline double drcp(double x) { return 1.0 / x; }
 
 // the same functions on dual numbers (value, derivative)
 template <typename T> __device__ __forceinline__ Dual<T> drcp(Dual<T> x) {
-  T r = drcp<T>(x.v);
+  T r = drcp(x.v);
   return {r, -x.d * r * r};
 }
 template <typename T> __device__ __forceinline__ Dual<T> dsqrt(Dual<T> x) {
-  T s = dsqrt<T>(x.v);
+  T s = dsqrt(x.v);
   return {s, x.d / (T(2) * s)};
 }
 template <typename T> __device__ __forceinline__ Dual<T> drsqrt(Dual<T> x) {
-  T r = drsqrt<T>(x.v);
+  T r = drsqrt(x.v);
   return {r, T(-0.5) * r * r * r * x.d};
 }
 template <typename T> __device__ __forceinline__ void dsincos(Dual<T> x, Dual<T> *s, Dual<T> *c) {
   T sv, cv;
-  dsincos<T>(x.v, &sv, &cv);
+  dsincos(x.v, &sv, &cv);
   *s = Dual<T>(sv, cv * x.d);
   *c = Dual<T>(cv, -sv * x.d);
 }
 template <typename T> __device__ __forceinline__ Dual<T> datan2(Dual<T> y, Dual<T> x) {
   T den = x.v * x.v + y.v * y.v;
-  return {datan2<T>(y.v, x.v), (x.v * y.d - y.v * x.d) / den};
+  return {datan2(y.v, x.v), (x.v * y.d - y.v * x.d) / den};
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +207,7 @@ __device__ __forceinline__ void log_so3(const T R[9], T w[3]) {
   w[2] = f * s2;
 }
 
-template <typename T> __device__ __forceinline__ bool is_zero(T x) { return x == T(0); }
+template <typename T> __host__ __device__ inline bool is_zero(T x) { return x == T(0); }
 template <typename T> __device__ __forceinline__ bool is_zero(Dual<T> x) { return x.v == T(0) && x.d == T(0); }
 
 // Rotation in the (p, q) plane that zeroes S[p][q]: t = tan(phi) is the root of
@@ -219,13 +216,21 @@ template <typename T> __device__ __forceinline__ bool is_zero(Dual<T> x) { retur
 // This form has no 1/apq, so it stays finite (and so do its derivatives) as
 // apq -> 0 in the sweeps after convergence.
 template <typename T>
-__device__ __forceinline__ void jacobi_rotate(T S[9], T V[9], int p, int q) {
+__host__ __device__ inline void jacobi_rotate(T S[9], T V[9], int p, int q) {
   T apq = S[3 * p + q];
   if (is_zero(apq)) return;
   T app = S[3 * p + p], aqq = S[3 * q + q];
   T dl = aqq - app;
   T rt = dsqrt(dl * dl + T(4) * apq * apq);
-  T tt = T(2) * apq * drcp(dl < T(0) ? dl - rt : dl + rt);
+  T den = dl < T(0) ? dl - rt : dl + rt;
+  // Equal diagonal entries (dl = 0) with apq^2 below the smallest normal
+  // number leave den = 0 (a 0 * inf in tt, and NaN eigenvectors): the root
+  // is then tan(pi/4) with the sign of apq.  Equal entries are what a
+  // degenerate pair of eigenvalues gives, e.g. M^T M for the sum of
+  // rotations about one axis (the MEGB's last iterates when its winners
+  // alternate between two samples), once the sweeps have driven apq to
+  // underflow.
+  T tt = value_of(den) == 0 ? (value_of(apq) > 0 ? T(1) : T(-1)) : T(2) * apq * drcp(den);
   T c = drsqrt(tt * tt + T(1));
   T s = tt * c;
   S[3 * p + p] = app - tt * apq;
@@ -251,7 +256,7 @@ __device__ __forceinline__ void jacobi_rotate(T S[9], T V[9], int p, int q) {
 // overwritten by its near-diagonal form); V accumulates the eigenvectors as
 // columns.
 template <typename T>
-__device__ __forceinline__ void jacobi3(T S[9], T V[9], int sweeps) {
+__host__ __device__ inline void jacobi3(T S[9], T V[9], int sweeps) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? T(1) : T(0);
   for (int sw = 0; sw < sweeps; ++sw) {

@@ -48,7 +48,7 @@ PURSE_DUAL_MIXED(>)
 PURSE_DUAL_MIXED(>=)
 #undef PURSE_DUAL_MIXED
 
-template <typename T> __device__ __forceinline__ T value_of(T x) { return x; }
+template <typename T> __host__ __device__ inline T value_of(T x) { return x; }
 template <typename T> __device__ __forceinline__ T value_of(Dual<T> x) { return x.v; }
 
 }  // namespace purse

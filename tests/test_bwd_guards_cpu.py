@@ -1,10 +1,17 @@
-"""The backward's index guards on the host (no GPU): tests/native/bwd_check_test.cpp
-is built with hipcc (host code only runs) and re-enacts, with the functions
-the kernels call, the per-instance index path of purse_megb_backward at the
-64 x 2^20 and 512-instance shapes, under stale or random instance records,
-out-of-range and infeasible trace entries, active-set overflow and a
-non-finite centre, checking that every global index formed lies inside its
-array or that the instance stops with an error status first."""
+"""Host runs (no GPU) of native checks built with hipcc from the library's own
+headers (host code only runs):
+
+- tests/native/bwd_check_test.cpp re-enacts, with the functions the kernels
+  call, the per-instance index path of purse_megb_backward at the 64 x 2^20
+  and 512-instance shapes, under stale or random instance records,
+  out-of-range and infeasible trace entries, active-set overflow and a
+  non-finite centre, checking that every global index formed lies inside its
+  array or that the instance stops with an error status first.
+- tests/native/jacobi_check_test.cpp runs the float64 Jacobi eigen-solver of
+  the polar decomposition on M^T M for sums of rotations about one axis (a
+  double eigenvalue, as the MEGB's last iterates give when the winners
+  alternate between two samples): every decomposition finite and diagonal.
+"""
 import os
 import shutil
 import subprocess
@@ -21,14 +28,14 @@ def _hipcc():
     return None
 
 
-def test_backward_index_guards_on_host():
+def _build_and_run(name):
     cc = _hipcc()
     if cc is None:
         pytest.skip("hipcc not available")
     out_dir = os.path.join(ROOT, "_build")
     os.makedirs(out_dir, exist_ok=True)
-    exe = os.path.join(out_dir, "bwd_check_test")
-    src = os.path.join(ROOT, "tests", "native", "bwd_check_test.cpp")
+    exe = os.path.join(out_dir, name)
+    src = os.path.join(ROOT, "tests", "native", name + ".cpp")
     r = subprocess.run([cc, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950", "-I",
                         os.path.join(ROOT, "include"), src, "-o", exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
@@ -36,5 +43,15 @@ def test_backward_index_guards_on_host():
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all checks passed" in r.stdout
+    return r.stdout
+
+
+def test_backward_index_guards_on_host():
+    out = _build_and_run("bwd_check_test")
     # the mechanism the guards close: the unguarded path indexes ~100 GB past the poses
-    assert "GB past the array" in r.stdout
+    assert "GB past the array" in out
+
+
+def test_jacobi_on_a_double_eigenvalue():
+    out = _build_and_run("jacobi_check_test")
+    assert " 0 of 200000 " in out
