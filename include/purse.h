@@ -172,6 +172,23 @@ purse_status purse_sample(const purse_batch *b, const purse_params *p, float *po
                           void *stream);
 
 /*
+ * purse_sample without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same prologue and trajectory kernels, with their
+ * scratch (instance records, keypoint records, tile schedule) in a static
+ * device array of the library (3.4 MB per device, held until the process
+ * ends).  Outputs and errors as purse_sample; PURSE_E_BAD_ARG for a batch of
+ * more than 1024 instances or 65536 keypoints in all.  Every call on a
+ * device shares that device's array: calls that overlap on one device race,
+ * and PURSE_FLAG_REUSE_PROLOGUE reuses whatever the last call on the device
+ * left there.  The array's device address is looked up on the first call on
+ * each device (make that first call outside graph capture).  No device
+ * memory is allocated or freed.
+ */
+purse_status purse_sample_noalloc(const purse_batch *b, const purse_params *p, float *poses,
+                                  uint8_t *mask, int32_t *inst_status, void *stream);
+
+/*
  * Minimum enclosing geodesic balls of the feasible samples of each instance
  * by geodesic gradient descent (Section "Minimum Enclosing Geodesic Ball",
  * paragraph "Geodesic Gradient Descent"; appendix "Geodesic Gradient

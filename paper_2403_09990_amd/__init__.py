@@ -23,7 +23,7 @@ from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURS
                       PurseParams)
 
 __all__ = ["PurseError", "DeviceBatch", "purse_default_params", "purse_workspace_size",
-           "purse_sample", "purse_megb", "purse_megb_backward", "sample", "megb", "workspace"]
+           "purse_sample", "purse_sample_noalloc", "purse_megb", "purse_megb_backward", "sample", "megb", "workspace"]
 
 
 class PurseError(RuntimeError):
@@ -112,6 +112,12 @@ def purse_sample(db, params, poses, mask, inst_status, ws, stream=None):
     _check(_native.load().purse_sample(ctypes.byref(db.struct), ctypes.byref(params), _ptr(poses),
                                        _ptr(mask), _ptr(inst_status), _ptr(ws), ws.numel(),
                                        _stream(stream)), "purse_sample")
+
+
+def purse_sample_noalloc(db, params, poses, mask, inst_status, stream=None):
+    _check(_native.load().purse_sample_noalloc(ctypes.byref(db.struct), ctypes.byref(params), _ptr(poses),
+                                               _ptr(mask), _ptr(inst_status), _stream(stream)),
+           "purse_sample_noalloc")
 
 
 def purse_megb(db, params, poses, mask, centre, radii, n_feasible, trace, inst_status, ws, stream=None):

@@ -41,8 +41,8 @@ PURSE_FLAG_REPLAY_DESCENT = 64
 PURSE_FLAG_QUAD_LANES = 128
 PURSE_FLAG_MATRIX_COTANGENT = 256
 
-EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_megb",
-            "purse_megb_backward", "purse_status_string", "purse_last_error")
+EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
+            "purse_megb", "purse_megb_backward", "purse_status_string", "purse_last_error")
 
 
 class PurseBatch(ctypes.Structure):
@@ -102,12 +102,13 @@ def load(path: str = LIB_PATH):
     lib.purse_default_params.argtypes = [P(PurseParams)]
     lib.purse_workspace_size.argtypes = [P(PurseBatch), P(PurseParams), P(ctypes.c_size_t)]
     lib.purse_sample.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.purse_sample_noalloc.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp]
     lib.purse_megb.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
                                ctypes.c_size_t, vp]
     lib.purse_megb_backward.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
                                         vp, vp, ctypes.c_size_t, vp]
-    for f in ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_megb",
-              "purse_megb_backward"):
+    for f in ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
+              "purse_megb", "purse_megb_backward"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.purse_status_string.argtypes = [ctypes.c_int32]
     lib.purse_status_string.restype = ctypes.c_char_p

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "purse_launch.hpp"
@@ -144,6 +145,49 @@ purse_status sample_into(const purse_batch *b, const purse_params *p, float *pos
   return hip_check(hipGetLastError(), "sampler launch");
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of purse_sample_noalloc: room for the instance records,
+// keypoint records and tile schedule of a batch of at most kNoAllocMaxInst
+// instances and kNoAllocMaxKp keypoints (3.4 MB), held by every device the
+// library runs on until the process ends.  In host code `scratch` names a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, once
+// per device, and only that address is ever passed to a kernel.
+constexpr int64_t kNoAllocMaxInst = 1024;
+constexpr int64_t kNoAllocMaxKp = 65536;
+constexpr size_t kScratchBytes =
+    purse::align_up(sizeof(purse::InstRec) * kNoAllocMaxInst) + purse::align_up(sizeof(purse::KpRec) * kNoAllocMaxKp) +
+    purse::align_up(sizeof(int32_t) * purse::kSchedGroups * (2 * kNoAllocMaxInst + 1));
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with the device current).
+purse_status scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(PURSE_E_NO_DEVICE, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % purse::kAlign)
+      return fail(PURSE_E_HIP, "static scratch has no aligned device address");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return PURSE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -185,6 +229,22 @@ purse_status purse_sample(const purse_batch *b, const purse_params *p, float *po
   if (!poses || !mask || !inst_status) return fail(PURSE_E_NULL, "an output is NULL");
   if ((s = check_ws(b, p, ws, ws_bytes))) return s;
   if ((s = check_device())) return s;
+  return sample_into(b, p, poses, mask, inst_status, ws, static_cast<hipStream_t>(stream));
+}
+
+purse_status purse_sample_noalloc(const purse_batch *b, const purse_params *p, float *poses, uint8_t *mask,
+                                  int32_t *inst_status, void *stream) {
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  if (!poses || !mask || !inst_status) return fail(PURSE_E_NULL, "an output is NULL");
+  if (b->n_inst > kNoAllocMaxInst || b->total_kp > kNoAllocMaxKp)
+    return fail(PURSE_E_BAD_ARG, "batch beyond the static scratch (at most 1024 instances, 65536 keypoints)");
+  if (layout_for(b, p).megb > kScratchBytes)
+    return fail(PURSE_E_BAD_ARG, "batch beyond the static scratch");
+  if ((s = check_device())) return s;
+  void *ws = nullptr;
+  if ((s = scratch_address(&ws))) return s;
   return sample_into(b, p, poses, mask, inst_status, ws, static_cast<hipStream_t>(stream));
 }
 

@@ -135,3 +135,25 @@ def test_status_strings():
     for code in (0, -1, -2, -3, -4, -5, 7):
         assert lib.purse_status_string(code)
 
+
+def test_sample_noalloc_limits_without_device():
+    """The allocation-free sampler rejects batches beyond its static scratch
+    on the host, before any device call."""
+    lib = _native.load()
+    p = _params()
+    fake = 0x100000
+    b = _batch()
+    b.n_inst, b.total_kp = 1025, 1025 * 8
+    assert lib.purse_sample_noalloc(ctypes.byref(b), ctypes.byref(p), fake, fake, fake, None) \
+        == _native.PURSE_E_BAD_ARG
+    b = _batch()
+    b.n_inst, b.max_kp, b.total_kp = 1024, 64, 65537
+    assert lib.purse_sample_noalloc(ctypes.byref(b), ctypes.byref(p), fake, fake, fake, None) \
+        == _native.PURSE_E_BAD_ARG
+    b = _batch()
+    assert lib.purse_sample_noalloc(ctypes.byref(b), ctypes.byref(p), None, fake, fake, None) \
+        == _native.PURSE_E_NULL
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.purse_sample_noalloc(ctypes.byref(b), ctypes.byref(p), fake, fake, fake, None) \
+            == _native.PURSE_E_NO_DEVICE
