@@ -112,6 +112,42 @@ def cpu_baseline(batch, iters, megb_iters, budget_s=20.0):
                                                                        megb_iters, t_s, t_m))
 
 
+def walk_bench(P, torch, reps=5):
+    """The paper's Step II (strategic random walk, both modes) on an
+    LM-O-shaped 2D-3D instance (N = 10 keypoints, 100 starts in S drawn by
+    purse_sample) with the paper's CLOSURE and CLOSURE++ walk parameters;
+    the paper's own timing of this step (RTX 3090, CuPy) is context only."""
+    from paper_2403_09990_amd import workloads as W
+    rng = np.random.default_rng(2024)
+    inst = W.make_2d3d(rng, 10, 2.0, (5.0, 20.0), 1500)
+    db = P.DeviceBatch(W.Batch([inst]))
+    gp = P.purse_default_params(n_iters=30)
+    out = P.sample(db, gp)
+    torch.cuda.synchronize()
+    feas = torch.nonzero((out["mask"] & 1) != 0)[:, 0][:100]
+    starts = out["poses"][feas].contiguous()
+    off = torch.as_tensor([0, starts.shape[0]], dtype=torch.int64, device=starts.device)
+    res = {}
+    for name, kw in (("closure", dict(n_walks=2, n_iters=5)), ("closure_pp", dict(n_walks=10, n_iters=10))):
+        wp = P.purse_walk_default_params(**kw)
+        ws = torch.empty(max(1, P.purse_walk_workspace_size(db)), dtype=torch.uint8, device=starts.device)
+        nw = starts.shape[0] * wp.n_walks
+        poses = torch.empty(2, nw, 12, dtype=torch.float32, device=starts.device)
+        mask = torch.empty(2, nw, dtype=torch.uint8, device=starts.device)
+
+        def run():
+            P.purse_walk(db, gp, wp, off, starts, poses, mask, None, ws)
+
+        run()
+        ms = time_events(run, reps, torch.cuda.current_stream())
+        checks = 2 * nw * wp.n_iters * (wp.n_perturb + wp.n_keep * wp.n_scales)
+        res[name] = {"ms": ms, "starts": int(starts.shape[0]), "walks_per_mode": nw,
+                     "pose_checks": checks, "pose_checks_per_s": checks / (ms * 1e-3),
+                     "end_in_S_fraction": float((mask == 1).float().mean())}
+    res["paper_context"] = "RTX 3090 / CuPy, LM-O average: 0.0915 s (CLOSURE), 0.6235 s (CLOSURE++)"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +159,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="time the forward alone as the step")
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-graph", action="store_true", help="time the eager step instead of its graph replay")
+    ap.add_argument("--no-walk", action="store_true", help="skip the strategic random walk figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -309,6 +346,9 @@ def main():
         # write-out: 12 float32 of pose and one mask byte per sample
         "hbm_write_gbs": total_m * 49 / (ms_traj * 1e-3) / 1e9,
     }
+    if not args.no_walk:
+        _progress("strategic random walk (LM-O-shaped)")
+        out["walk_lmo"] = walk_bench(P, torch)
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(batch, cfg["iters"], gp.megb_iters)

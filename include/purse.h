@@ -270,6 +270,67 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p,
                                  float *g_bounds, int32_t *bwd_status, void *ws, size_t ws_bytes,
                                  void *stream);
 
+/*
+ * The paper's own Step II, the strategic random walk (Section "The CLOSURE
+ * Algorithm", Step II; Alg. "d S_R parallel sampler" and, in the appendix
+ * "Boundary Sampler Algorithms", Alg. "d S_t parallel sampler"), as a second
+ * sampler mode that starts from given poses of S (S0; e.g. samples of
+ * purse_sample).
+ *
+ * From each start, n_walks walks per mode run n_iters iterations.  Rotation
+ * mode: the angular velocity w = omega0 (u + u~) (u: axis of the start's
+ * rotation relative to the average rotation of the instance's starts, u~: a
+ * random unit vector); each iteration draws n_perturb translation
+ * perturbations of the walk's pose (random direction, magnitude uniform in
+ * [0, t_pert)), keeps the n_keep of largest boundary distance
+ * min_i (beta_i - ||g_i||_Lambda_i) (eq. partial-s-dist; ties to the lower
+ * draw index), and moves to the candidate (Exp(w gamma^(m-1)) R, t_k) in S
+ * with the largest step (smallest m = 1..n_scales), then the best rank k; no
+ * move when none is in S.  Translation mode: v = v0 ((t0 - t_bar)/|.| + v~),
+ * rotation perturbations Exp(theta e) R (theta uniform in [0, r_pert)), and
+ * candidates (R_k, t + v gamma^(m-1)).  in_purse is the sampler's test
+ * (r_i <= beta_i + tau, depth > z_min), with tau and z_min from p.
+ * Random numbers: Philox4x64-10, key (seed[j], 1 + mode), counter
+ * (instance-local walk index, iteration, perturbation index, 0)
+ * (iteration 2^32 - 1 for the initial velocity); the top 24 bits of output
+ * words 0..2 give the direction (z = 1 - 2 U1, phi = 2 pi U2) and the
+ * magnitude fraction U3.  Instance-local walk index of start s (s-th start of
+ * the instance) and walk n: s * n_walks + n.
+ *
+ * Inputs (device): start_off [n_inst+1] int64 prefix sums of the instances'
+ * start counts; starts [total_starts][12] float poses (R row-major, t).
+ * Outputs (device, caller-owned):
+ *   poses     [2][total_starts * n_walks][12] float: end poses, rotation-mode
+ *             walks first, then translation-mode walks;
+ *   mask      [2][total_starts * n_walks] uint8: PURSE_MASK_FEASIBLE if the end
+ *             pose is in S;
+ *   decisions [2][total_starts * n_walks][n_iters] int32 or NULL: per
+ *             iteration k * n_scales + (m - 1) of the move taken, -1 for none.
+ * Workspace: purse_walk_workspace_size bytes (the average pose of each
+ * instance's starts), 256-byte aligned.
+ */
+typedef struct purse_walk_params {
+  int32_t n_walks;    /* N_W: walks per start and mode */
+  int32_t n_iters;    /* N_I */
+  int32_t n_perturb;  /* N_P <= 256 */
+  int32_t n_keep;     /* N_P* <= min(16, N_P) */
+  int32_t n_scales;   /* N_T <= 32 */
+  float gamma;        /* step decay in (0, 1] */
+  float omega0;       /* angular velocity magnitude (rad per unit step) */
+  float v0;           /* centre velocity magnitude (m per unit step) */
+  float t_pert;       /* translation perturbation scale (m), rotation mode */
+  float r_pert;       /* rotation perturbation scale (rad), translation mode */
+} purse_walk_params;
+
+/* Defaults: N_W 2, N_I 5, N_P 150, N_P* 10, N_T 15, gamma 0.5, omega0 0.5,
+ * v0 0.05, t_pert 0.005, r_pert 0.02. */
+purse_status purse_walk_default_params(purse_walk_params *w);
+purse_status purse_walk_workspace_size(const purse_batch *b, size_t *bytes);
+purse_status purse_walk(const purse_batch *b, const purse_params *p, const purse_walk_params *w,
+                        const int64_t *start_off, const float *starts, int64_t total_starts,
+                        float *poses, uint8_t *mask, int32_t *decisions, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* Static description of a status code. */
 const char *purse_status_string(purse_status s);
 

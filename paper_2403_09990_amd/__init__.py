@@ -20,10 +20,11 @@ from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURS
                       PURSE_INST_ANCHOR_ITERATED, PURSE_INST_BAD_SHAPE, PURSE_INST_BAD_SIZE,
                       PURSE_INST_EMPTY, PURSE_INST_FIT_FAILED, PURSE_INST_NO_ANCHOR, PURSE_INST_OK,
                       PURSE_MASK_FAILED, PURSE_MASK_FEASIBLE, PURSE_MASK_PULLED_IN, PurseBatch,
-                      PurseParams)
+                      PurseParams, PurseWalkParams)
 
 __all__ = ["PurseError", "DeviceBatch", "purse_default_params", "purse_workspace_size",
-           "purse_sample", "purse_sample_noalloc", "purse_megb", "purse_megb_backward", "sample", "megb", "workspace"]
+           "purse_sample", "purse_sample_noalloc", "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
+           "purse_walk", "sample", "megb", "walk", "workspace"]
 
 
 class PurseError(RuntimeError):
@@ -161,3 +162,46 @@ def megb(db: DeviceBatch, params: PurseParams, poses, mask, inst_status, ws=None
     trace = torch.empty(db.n_inst, params.megb_iters, 2, dtype=torch.int32, device=dev)
     purse_megb(db, params, poses, mask, centre, radii, nf, trace, inst_status, ws, stream)
     return dict(centre=centre, radii=radii, n_feasible=nf, trace=trace, inst_status=inst_status)
+
+
+# ----------------------------------------------------------------------------
+# the strategic random walk (second sampler mode)
+
+def purse_walk_default_params(**overrides) -> PurseWalkParams:
+    w = PurseWalkParams()
+    _check(_native.load().purse_walk_default_params(ctypes.byref(w)), "purse_walk_default_params")
+    for k, v in overrides.items():
+        if not hasattr(w, k):
+            raise KeyError(k)
+        setattr(w, k, v)
+    return w
+
+
+def purse_walk_workspace_size(db: DeviceBatch) -> int:
+    n = ctypes.c_size_t(0)
+    _check(_native.load().purse_walk_workspace_size(ctypes.byref(db.struct), ctypes.byref(n)),
+           "purse_walk_workspace_size")
+    return int(n.value)
+
+
+def purse_walk(db, params, wparams, start_off, starts, poses, mask, decisions, ws, stream=None):
+    _check(_native.load().purse_walk(ctypes.byref(db.struct), ctypes.byref(params), ctypes.byref(wparams),
+                                     _ptr(start_off), _ptr(starts), int(starts.shape[0]), _ptr(poses), _ptr(mask),
+                                     _ptr(decisions), _ptr(ws), ws.numel(), _stream(stream)), "purse_walk")
+
+
+def walk(db: DeviceBatch, params: PurseParams, wparams: PurseWalkParams, start_off, starts, ws=None,
+         with_decisions=False, stream=None) -> dict:
+    """Allocates the outputs and runs purse_walk: poses (2, W, 12) and mask
+    (2, W) for the rotation-mode and translation-mode walks (W = starts x
+    n_walks), and the per-iteration decisions if asked."""
+    import torch
+    dev = db.kind.device
+    if ws is None:
+        ws = torch.empty(max(1, purse_walk_workspace_size(db)), dtype=torch.uint8, device=dev)
+    nw = int(starts.shape[0]) * wparams.n_walks
+    poses = torch.empty(2, nw, 12, dtype=torch.float32, device=dev)
+    mask = torch.empty(2, nw, dtype=torch.uint8, device=dev)
+    dec = torch.empty(2, nw, max(1, wparams.n_iters), dtype=torch.int32, device=dev) if with_decisions else None
+    purse_walk(db, params, wparams, start_off, starts, poses, mask, dec, ws, stream)
+    return dict(poses=poses, mask=mask, decisions=dec, ws=ws)

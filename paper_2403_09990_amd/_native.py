@@ -42,7 +42,8 @@ PURSE_FLAG_QUAD_LANES = 128
 PURSE_FLAG_MATRIX_COTANGENT = 256
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
-            "purse_megb", "purse_megb_backward", "purse_status_string", "purse_last_error")
+            "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
+            "purse_walk", "purse_status_string", "purse_last_error")
 
 
 class PurseBatch(ctypes.Structure):
@@ -85,6 +86,21 @@ class PurseParams(ctypes.Structure):
     ]
 
 
+class PurseWalkParams(ctypes.Structure):
+    _fields_ = [
+        ("n_walks", ctypes.c_int32),
+        ("n_iters", ctypes.c_int32),
+        ("n_perturb", ctypes.c_int32),
+        ("n_keep", ctypes.c_int32),
+        ("n_scales", ctypes.c_int32),
+        ("gamma", ctypes.c_float),
+        ("omega0", ctypes.c_float),
+        ("v0", ctypes.c_float),
+        ("t_pert", ctypes.c_float),
+        ("r_pert", ctypes.c_float),
+    ]
+
+
 _lib = None
 
 
@@ -107,8 +123,13 @@ def load(path: str = LIB_PATH):
                                ctypes.c_size_t, vp]
     lib.purse_megb_backward.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
                                         vp, vp, ctypes.c_size_t, vp]
+    lib.purse_walk_default_params.argtypes = [P(PurseWalkParams)]
+    lib.purse_walk_workspace_size.argtypes = [P(PurseBatch), P(ctypes.c_size_t)]
+    lib.purse_walk.argtypes = [P(PurseBatch), P(PurseParams), P(PurseWalkParams), vp, vp, ctypes.c_int64, vp, vp,
+                               vp, vp, ctypes.c_size_t, vp]
     for f in ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
-              "purse_megb", "purse_megb_backward"):
+              "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
+              "purse_walk"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.purse_status_string.argtypes = [ctypes.c_int32]
     lib.purse_status_string.restype = ctypes.c_char_p

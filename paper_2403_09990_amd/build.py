@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpurse.so")
 ARCH = os.environ.get("PURSE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["purse_abi.hip", "purse_prologue.hip", "purse_sample.hip", "purse_megb.hip", "purse_backward.hip"]
+SOURCES = ["purse_abi.hip", "purse_prologue.hip", "purse_sample.hip", "purse_megb.hip", "purse_backward.hip",
+           "purse_walk.hip"]
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -291,6 +291,67 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
   return hip_check(hipGetLastError(), "backward launch");
 }
 
+purse_status purse_walk_default_params(purse_walk_params *w) {
+  if (!w) return fail(PURSE_E_NULL, "walk params is NULL");
+  w->n_walks = 2;
+  w->n_iters = 5;
+  w->n_perturb = 150;
+  w->n_keep = 10;
+  w->n_scales = 15;
+  w->gamma = 0.5f;
+  w->omega0 = 0.5f;
+  w->v0 = 0.05f;
+  w->t_pert = 0.005f;
+  w->r_pert = 0.02f;
+  return PURSE_OK;
+}
+
+purse_status purse_walk_workspace_size(const purse_batch *b, size_t *bytes) {
+  if (!bytes) return fail(PURSE_E_NULL, "bytes is NULL");
+  purse_status s = check_batch(b);
+  if (s) return s;
+  *bytes = purse::align_up(sizeof(float) * 12 * (size_t)b->n_inst);
+  return PURSE_OK;
+}
+
+purse_status purse_walk(const purse_batch *b, const purse_params *p, const purse_walk_params *w,
+                        const int64_t *start_off, const float *starts, int64_t total_starts, float *poses,
+                        uint8_t *mask, int32_t *decisions, void *ws, size_t ws_bytes, void *stream) {
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  if (!w) return fail(PURSE_E_NULL, "walk params is NULL");
+  if (w->n_walks < 1 || w->n_walks > 1 << 20 || w->n_iters < 0 || w->n_iters > 10000 || w->n_perturb < 1 ||
+      w->n_perturb > purse::kWalkMaxPerturb || w->n_keep < 1 || w->n_keep > purse::kWalkMaxKeep ||
+      w->n_keep > w->n_perturb || w->n_scales < 1 || w->n_scales > purse::kWalkMaxScales)
+    return fail(PURSE_E_BAD_ARG, "walk counts out of range (N_P <= 256, N_P* <= min(16, N_P), N_T <= 32)");
+  if (!(w->gamma > 0.f && w->gamma <= 1.f) || !(w->omega0 >= 0.f && w->omega0 < 3.f) || !(w->v0 >= 0.f) ||
+      !std::isfinite(w->v0) || !(w->t_pert >= 0.f) || !std::isfinite(w->t_pert) || !(w->r_pert >= 0.f) ||
+      !(w->r_pert < 3.f))
+    return fail(PURSE_E_BAD_ARG, "walk scales out of range");
+  if (total_starts < 0 || total_starts > ((int64_t)1 << 40) / w->n_walks)
+    return fail(PURSE_E_BAD_ARG, "total_starts out of range");
+  if (!start_off || !starts || !poses || !mask) return fail(PURSE_E_NULL, "an argument is NULL");
+  if (!ws) return fail(PURSE_E_NULL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % purse::kAlign) return fail(PURSE_E_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < purse::align_up(sizeof(float) * 12 * (size_t)b->n_inst)) return fail(PURSE_E_WORKSPACE, "workspace too small");
+  if ((s = check_device())) return s;
+  purse::WalkParams wp;
+  wp.n_walks = w->n_walks;
+  wp.n_iters = w->n_iters;
+  wp.n_perturb = w->n_perturb;
+  wp.n_keep = w->n_keep;
+  wp.n_scales = w->n_scales;
+  wp.gamma = w->gamma;
+  wp.omega0 = w->omega0;
+  wp.v0 = w->v0;
+  wp.t_pert = w->t_pert;
+  wp.r_pert = w->r_pert;
+  purse::launch_walk(dev_batch(b), dev_params(p), wp, start_off, total_starts, starts, static_cast<float *>(ws), poses,
+                     mask, decisions, static_cast<hipStream_t>(stream));
+  return hip_check(hipGetLastError(), "walk launch");
+}
+
 const char *purse_status_string(purse_status s) {
   switch (s) {
     case PURSE_OK: return "ok";

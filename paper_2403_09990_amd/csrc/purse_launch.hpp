@@ -36,4 +36,11 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
                            int64_t *items, float *g_centres, float *g_shapes, float *g_bounds, int32_t *bwd_status,
                            hipStream_t stream);
 
+// The strategic random walks of every start, rotation mode then translation
+// mode; centre: [n_inst][12] scratch for the average pose of each instance's
+// starts; decisions may be NULL.
+void launch_walk(const DevBatch &b, const DevParams &p, const WalkParams &wp, const int64_t *start_off,
+                 int64_t total_starts, const float *starts, float *centre, float *poses, uint8_t *mask,
+                 int32_t *decisions, hipStream_t stream);
+
 }  // namespace purse

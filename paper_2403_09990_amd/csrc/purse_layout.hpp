@@ -174,6 +174,15 @@ struct DevBatch {
   const uint64_t *seed;
 };
 
+// Strategic random walk parameters (purse_walk_params as the kernels see it).
+constexpr int kWalkMaxPerturb = 256;  // N_P
+constexpr int kWalkMaxKeep = 16;      // N_P*
+constexpr int kWalkMaxScales = 32;    // N_T
+struct WalkParams {
+  int32_t n_walks, n_iters, n_perturb, n_keep, n_scales;
+  float gamma, omega0, v0, t_pert, r_pert;
+};
+
 struct DevParams {
   int32_t n_iters, n_gn, n_bis, megb_iters, megb_avg, centre_gn, ckpt_every, flags;
   float omega0, v0, kappa, tau3, tau2, z_min;
