@@ -117,3 +117,21 @@ def so3_minimax(R: np.ndarray, starts=None, n_restarts: int = 4, seed: int = 0):
         if res.fun < best[1]:
             best = ((C0t @ so3.exp_so3(torch.as_tensor(w))).numpy(), float(res.fun))
     return best
+
+
+def exact_megb(poses: np.ndarray, mask: np.ndarray):
+    """Step III on a sample set: the exact minimum enclosing ball of the
+    feasible translations (R^3) and of their rotations as unit quaternions in
+    R^4 on the hemisphere of the first feasible sample; the rotation centre is
+    the normalised quaternion centre.  Returns (R*, t*, D, d) with D the
+    largest geodesic angle and d the largest distance from that centre."""
+    P = np.asarray(poses, dtype=np.float64)[(np.asarray(mask) & 1) != 0]
+    R = P[:, :9].reshape(-1, 3, 3)
+    t = P[:, 9:]
+    from scipy.spatial.transform import Rotation
+    q = Rotation.from_matrix(R).as_quat()[:, [3, 0, 1, 2]]   # (w, x, y, z)
+    q = q * np.where(q @ q[0] < 0, -1.0, 1.0)[:, None]
+    c, _ = welzl(q)
+    C = so3.quat_to_rot(torch.as_tensor(c / np.linalg.norm(c))).numpy()
+    ct, d = welzl(t)
+    return C, ct, max_angle(C, R), float(np.linalg.norm(t - ct, axis=1).max())

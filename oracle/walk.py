@@ -29,7 +29,8 @@ the rotation step is a left increment about the camera frame with t fixed,
 the translation step leaves R fixed; the translation-mode ranking uses the
 perturbed rotation (the printed dist(R*, t_j) there is read as
 dist(R_j, t*)); in_purse is the sampler's test r_i <= beta_i + tau (and depth
-> z_min for 2D-3D); the velocity's radial part is dropped when the start is
+> z_min for 2D-3D; for the pose-regression set both families of balls of
+oracle/reg.py, with the 3D-3D tau); the velocity's radial part is dropped when the start is
 at the centre; the PCA rescaling of the translation velocity is omitted.
 
 Random numbers: Philox4x64-10 with key (seed, 1 + mode) and counter
@@ -45,6 +46,7 @@ from typing import Optional
 import numpy as np
 import torch
 
+from . import reg
 from .philox import philox4x64_10
 from .purse import KIND_2D3D, Problem, residual
 from .so3 import exp_so3, log_so3, proj_so3
@@ -103,6 +105,8 @@ def perturbations(seed, mode, walks, iteration, n_perturb, scale):
 def boundary_distance(prob: Problem, R, t):
     """eq. partial-s-dist: min_i (beta_i - ||g_i||_Lambda_i), batched over
     leading pose dims (R: (..., 3, 3), t: (..., 3))."""
+    if isinstance(prob, reg.RegProblem):
+        return reg.boundary_distance(prob, R, t)
     lead = R.shape[:-2]
     e, r, depth = residual(prob, R.reshape(-1, 3, 3), t.reshape(-1, 3))
     d = (prob.beta - r).min(-1).values
@@ -110,6 +114,8 @@ def boundary_distance(prob: Problem, R, t):
 
 
 def in_purse(prob: Problem, R, t, wp: WalkParams):
+    if isinstance(prob, reg.RegProblem):
+        return reg.in_purse(prob, R, t, wp.tau_abs_3d)
     lead = R.shape[:-2]
     e, r, depth = residual(prob, R.reshape(-1, 3, 3), t.reshape(-1, 3))
     tau = wp.tau_abs_2d if prob.kind == KIND_2D3D else wp.tau_abs_3d
@@ -121,6 +127,8 @@ def in_purse(prob: Problem, R, t, wp: WalkParams):
 
 def feasibility_ratio(prob: Problem, R, t, wp: WalkParams):
     """Diagnostic: max_i r_i / (beta_i + tau) (inf behind z_min)."""
+    if isinstance(prob, reg.RegProblem):
+        return reg.feasibility_ratio(prob, R, t, wp.tau_abs_3d)
     lead = R.shape[:-2]
     e, r, depth = residual(prob, R.reshape(-1, 3, 3), t.reshape(-1, 3))
     tau = wp.tau_abs_2d if prob.kind == KIND_2D3D else wp.tau_abs_3d

@@ -150,3 +150,25 @@ def test_trace_ties_go_to_lowest_index():
     assert int(out["trace"][1, 1]) == 10          # from (1,0,0): samples 10 and 13 tie
     rad = radii_at(out["R"], out["t"], torch.as_tensor(R), torch.as_tensor(t))
     assert rad[0] == 0.0
+
+
+def test_exact_megb_of_rotations_about_one_axis_and_two_points():
+    """Step III's ball: rotations about one axis through angles in [a, b]
+    have the centre at angle (a + b)/2 and radius (b - a)/2; two translations
+    have their midpoint and half their distance."""
+    ax = np.array([0.3, -0.4, 0.866])
+    ax /= np.linalg.norm(ax)
+    angs = np.array([0.1, 0.35, 0.22, 0.6, 0.45])
+    R = Rotation.from_rotvec(angs[:, None] * ax).as_matrix()
+    t = np.zeros((5, 3))
+    t[0] = [0.1, 0.2, 0.3]
+    t[3] = [0.5, -0.2, 0.1]
+    t[1:3] = 0.5 * (t[0] + t[3])
+    t[4] = 0.5 * (t[0] + t[3]) + 0.01
+    poses = np.concatenate([R.reshape(5, 9), t], 1)
+    C, ct, D, d = exact.exact_megb(poses, np.ones(5, dtype=np.uint8))
+    mid = Rotation.from_rotvec(0.35 * ax).as_matrix()
+    assert np.abs(C - mid).max() < 1e-9
+    assert abs(D - 0.25) < 1e-9
+    assert np.abs(ct - 0.5 * (t[0] + t[3])).max() < 1e-9
+    assert abs(d - 0.5 * np.linalg.norm(t[0] - t[3])) < 1e-9
