@@ -45,10 +45,14 @@ CONFIGS = {
 }
 
 
-def make_batch(cfg, seed=0):
+def make_batch(cfg, seed=0, n_inst=None):
     from paper_2403_09990_amd import workloads as W
-    return {"c1": W.config_c1, "c2": W.config_c2, "c3": W.config_c3, "c4": W.config_c4,
-            "c5": W.config_c5}[cfg](seed)
+    make = {"c1": W.config_c1, "c2": W.config_c2, "c3": W.config_c3, "c4": W.config_c4, "c5": W.config_c5}[cfg]
+    if n_inst is None:
+        return make(seed)
+    if cfg not in ("c3", "c5"):
+        raise SystemExit("--n-inst applies to the multi-instance workloads (c3, c5)")
+    return make(seed, n_inst=n_inst)
 
 
 def read_traffic(kernel, workload):
@@ -160,6 +164,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-graph", action="store_true", help="time the eager step instead of its graph replay")
     ap.add_argument("--no-walk", action="store_true", help="skip the strategic random walk figures")
+    ap.add_argument("--n-inst", type=int, default=None,
+                    help="first N instances of c3/c5 only (profiling runs whose per-dispatch counters must stay "
+                         "short); the reported workload names the count")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no "
@@ -173,7 +180,7 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = CONFIGS[args.config]
-    batch = make_batch(args.config)
+    batch = make_batch(args.config, n_inst=args.n_inst)
     gp = P.purse_default_params(n_iters=cfg["iters"])
     db = P.DeviceBatch(batch)
     ws = P.workspace(db, gp)
@@ -287,7 +294,7 @@ def main():
     # when the schedule runs 2D-3D trajectories on two or four lanes each
     traj_kernel = ("k_sample2d_lanes" if gp.flags & (P.PURSE_FLAG_PAIR_LANES | P.PURSE_FLAG_QUAD_LANES)
                    else "k_sample")
-    traffic = read_traffic(traj_kernel, args.config)
+    traffic = read_traffic(traj_kernel, args.config if args.n_inst is None else "%s_n%d" % (args.config, db.n_inst))
 
     # calibration kernel for the traffic counters: a copy of known size
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -309,7 +316,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded generator shaped like the paper's 2D-3D / 3D-3D workloads)",
-        "config": {"workload": "%s: %s" % (args.config, cfg["desc"]), "n_inst": db.n_inst,
+        "config": {"workload": "%s: %s" % (args.config, cfg["desc"]) +
+                   ("" if args.n_inst is None else " (first %d instances only)" % db.n_inst), "n_inst": db.n_inst,
                    "samples": total_m, "megb_iters": gp.megb_iters,
                    "step": "sample + MEGB" + ("" if args.no_backward else " + backward (all instances, one call)"),
                    "parallelism": "single GPU"},

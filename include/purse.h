@@ -69,6 +69,12 @@ typedef int32_t purse_status;
 
 #define PURSE_KIND_3D3D 0 /* balls around target points b_i (eq. PURSE3D3D, Lambda_i = I) */
 #define PURSE_KIND_2D3D 1 /* ellipses around image points z_i (eq. PURSE2D3D) */
+#define PURSE_KIND_REG 2  /* pose regression (eq. PURSEregression): keypoint i is pose hypothesis i,
+                             with centres[i] = t_i (m), shapes[i] = R_i as a unit quaternion
+                             (w, x, y, z), model_pts[i][0] = beta_i^R (bound on ||R - R_i||_F),
+                             bounds[i] = beta_i^t (bound on ||t - t_i||, m).  Accepted by purse_init,
+                             purse_walk and purse_megb (which takes any poses); purse_sample reports
+                             it as PURSE_INST_BAD_SIZE */
 
 #define PURSE_MAX_KP 64
 
@@ -93,6 +99,11 @@ typedef int32_t purse_status;
 #define PURSE_FLAG_REPLAY_DESCENT 64  /* purse_megb_backward: replay the MEGB descent from the trace even
                                          when purse_megb left its checkpoints for this trace in the
                                          workspace (same results; for testing) */
+#define PURSE_FLAG_EXACT_MEB 512      /* purse_megb: after the descent, replace its centre by the exact
+                                         minimum enclosing ball (Step III): translations in R^3 and rotations
+                                         as hemisphere-aligned unit quaternions in R^4, float64; the radii are
+                                         then taken about that centre.  purse_megb_backward differentiates
+                                         the descent, so it rejects this flag */
 #define PURSE_FLAG_MATRIX_COTANGENT 256 /* purse_megb_backward: g_centre is [n_inst][12], the cotangent of the
                                            centre's entries as purse_megb returns them (R* row-major, then
                                            t*); its rotation part is taken along SO(3) at R* */
@@ -269,6 +280,35 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p,
                                  const float *g_centre, float *g_centres, float *g_shapes,
                                  float *g_bounds, int32_t *bwd_status, void *ws, size_t ws_bytes,
                                  void *stream);
+
+/*
+ * Step I of the paper (Section "The CLOSURE Algorithm"): candidate start poses
+ * for the strategic random walk, each kept when it lies in S.  Instance j runs
+ * M_j trials (its sample count in the batch), written to its sample range:
+ *  - 3D-3D (random sample averaging with Arun's method): three distinct
+ *    correspondences, a random point inside each of their balls, the rigid fit
+ *    of the three pairs;
+ *  - 2D-3D (random sample averaging with P3P): three distinct correspondences, a
+ *    random point inside each of their ellipses, the perspective-3-point
+ *    solutions for the three bearing rays in increasing order of the ratio of
+ *    the third and first depths; the first in S is kept;
+ *  - pose regression (PURSE_KIND_REG): a random convex combination of the
+ *    hypotheses, R = proj_SO3(sum w_i R_i), t = sum w_i t_i, weights uniform on
+ *    the simplex.
+ * in_purse is the sampler's test (tolerance tau, depth > z_min), in float64.
+ * Random numbers: Philox4x64-10; pose regression key (seed, 3), counter
+ * (trial, i, 0, 0), weight w_i = -ln(1 - U) from the top 24 bits of word 0;
+ * keypoint sets key (seed, 4), counter (trial, k, 0, 0): k = 0 picks the
+ * correspondences (i_q = floor(U_q (N - q)), skipping those taken), k = 1..3
+ * the point in the k-th constraint (ball: direction z = 1 - 2 U1,
+ * phi = 2 pi U2, radius beta U3^(1/3); ellipse: z + beta sqrt(U3) U^-1
+ * (cos 2 pi U2, sin 2 pi U2), U^T U = Lambda).
+ * Outputs (device): poses [total_samples][12] (the identity where no
+ * candidate was found), mask [total_samples] (PURSE_MASK_FEASIBLE for a pose in
+ * S).  No workspace.
+ */
+purse_status purse_init(const purse_batch *b, const purse_params *p, float *poses, uint8_t *mask,
+                        void *stream);
 
 /*
  * The paper's own Step II, the strategic random walk (Section "The CLOSURE

@@ -88,3 +88,14 @@ def convex_samples(prob: RegProblem, seed: int, n_trials: int, tau: float):
     t = w @ prob.t_i
     ok = in_purse(prob, R, t, tau)
     return torch.cat([R.reshape(-1, 9), t], 1), ok.to(torch.uint8)
+
+
+def from_instance(inst) -> RegProblem:
+    """The pose-regression set of a batch instance (keypoint i = hypothesis
+    i: centres = t_i, shapes = quaternion (w, x, y, z) of R_i, model_pts x =
+    beta_i^R, bounds = beta_i^t)."""
+    from .so3 import quat_to_rot
+    q = torch.as_tensor(np.asarray(inst.shapes, dtype=np.float64)).reshape(-1, 4)
+    return RegProblem(quat_to_rot(q), torch.as_tensor(np.asarray(inst.centres, dtype=np.float64)).reshape(-1, 3),
+                      torch.as_tensor(np.asarray(inst.model_pts, dtype=np.float64)).reshape(-1, 3)[:, 0].clone(),
+                      torch.as_tensor(np.asarray(inst.bounds, dtype=np.float64)).reshape(-1))

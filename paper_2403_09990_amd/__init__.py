@@ -11,7 +11,7 @@ import ctypes
 from typing import Optional
 
 from . import _native
-from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
+from ._native import (PURSE_FLAG_EXACT_MEB, PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
                       PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_MATRIX_COTANGENT, PURSE_FLAG_PAIR_LANES,
                       PURSE_FLAG_QUAD_LANES, PURSE_BWD_BAD_TRACE, PURSE_BWD_EMPTY, PURSE_BWD_NON_FINITE,
                       PURSE_BWD_OK, PURSE_BWD_OVERFLOW, PURSE_BWD_STALE,
@@ -24,7 +24,7 @@ from ._native import (PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_GENERIC_LOOP, PURS
 
 __all__ = ["PurseError", "DeviceBatch", "purse_default_params", "purse_workspace_size",
            "purse_sample", "purse_sample_noalloc", "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
-           "purse_walk", "sample", "megb", "walk", "workspace"]
+           "purse_walk", "purse_init", "init", "sample", "megb", "walk", "workspace"]
 
 
 class PurseError(RuntimeError):
@@ -205,3 +205,21 @@ def walk(db: DeviceBatch, params: PurseParams, wparams: PurseWalkParams, start_o
     dec = torch.empty(2, nw, max(1, wparams.n_iters), dtype=torch.int32, device=dev) if with_decisions else None
     purse_walk(db, params, wparams, start_off, starts, poses, mask, dec, ws, stream)
     return dict(poses=poses, mask=mask, decisions=dec, ws=ws)
+
+
+# ----------------------------------------------------------------------------
+# Step I candidates
+
+def purse_init(db, params, poses, mask, stream=None):
+    _check(_native.load().purse_init(ctypes.byref(db.struct), ctypes.byref(params), _ptr(poses), _ptr(mask),
+                                     _stream(stream)), "purse_init")
+
+
+def init(db: DeviceBatch, params: PurseParams, stream=None) -> dict:
+    """Allocates the outputs and runs purse_init: one trial per sample slot."""
+    import torch
+    dev = db.kind.device
+    poses = torch.empty(db.total_samples, 12, dtype=torch.float32, device=dev)
+    mask = torch.empty(db.total_samples, dtype=torch.uint8, device=dev)
+    purse_init(db, params, poses, mask, stream)
+    return dict(poses=poses, mask=mask)

@@ -31,6 +31,10 @@ PURSE_MASK_FEASIBLE = 1
 PURSE_MASK_PULLED_IN = 2
 PURSE_MASK_FAILED = 4
 
+PURSE_KIND_3D3D = 0
+PURSE_KIND_2D3D = 1
+PURSE_KIND_REG = 2
+
 PURSE_FLAG_FORCE_FP64_POLAR = 1
 PURSE_FLAG_NO_PRUNING = 2
 PURSE_FLAG_REUSE_PROLOGUE = 4
@@ -40,10 +44,11 @@ PURSE_FLAG_PAIR_LANES = 32
 PURSE_FLAG_REPLAY_DESCENT = 64
 PURSE_FLAG_QUAD_LANES = 128
 PURSE_FLAG_MATRIX_COTANGENT = 256
+PURSE_FLAG_EXACT_MEB = 512
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
             "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
-            "purse_walk", "purse_status_string", "purse_last_error")
+            "purse_walk", "purse_init", "purse_status_string", "purse_last_error")
 
 
 class PurseBatch(ctypes.Structure):
@@ -123,13 +128,14 @@ def load(path: str = LIB_PATH):
                                ctypes.c_size_t, vp]
     lib.purse_megb_backward.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp, vp, vp, vp, vp, vp,
                                         vp, vp, ctypes.c_size_t, vp]
+    lib.purse_init.argtypes = [P(PurseBatch), P(PurseParams), vp, vp, vp]
     lib.purse_walk_default_params.argtypes = [P(PurseWalkParams)]
     lib.purse_walk_workspace_size.argtypes = [P(PurseBatch), P(ctypes.c_size_t)]
     lib.purse_walk.argtypes = [P(PurseBatch), P(PurseParams), P(PurseWalkParams), vp, vp, ctypes.c_int64, vp, vp,
                                vp, vp, ctypes.c_size_t, vp]
     for f in ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
               "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
-              "purse_walk"):
+              "purse_walk", "purse_init"):
         getattr(lib, f).restype = ctypes.c_int32
     lib.purse_status_string.argtypes = [ctypes.c_int32]
     lib.purse_status_string.restype = ctypes.c_char_p

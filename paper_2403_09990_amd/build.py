@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libpurse.so")
 ARCH = os.environ.get("PURSE_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["purse_abi.hip", "purse_prologue.hip", "purse_sample.hip", "purse_megb.hip", "purse_backward.hip",
-           "purse_walk.hip"]
+           "purse_walk.hip", "purse_init.hip"]
 
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

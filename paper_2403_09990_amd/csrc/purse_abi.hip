@@ -277,6 +277,8 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
   if ((s = check_params(p))) return s;
   if (!poses || !mask || !trace || !g_radii || !g_centre || !g_centres || !g_shapes || !g_bounds)
     return fail(PURSE_E_NULL, "an argument is NULL");
+  if (p->flags & PURSE_FLAG_EXACT_MEB)
+    return fail(PURSE_E_BAD_ARG, "the backward differentiates the descent's centre, not the exact ball");
   if ((s = check_ws(b, p, ws, ws_bytes))) return s;
   if ((s = check_device())) return s;
   const purse::WsLayout L = layout_for(b, p);
@@ -289,6 +291,16 @@ purse_status purse_megb_backward(const purse_batch *b, const purse_params *p, co
                          static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_check(e, "backward stream join");
   return hip_check(hipGetLastError(), "backward launch");
+}
+
+purse_status purse_init(const purse_batch *b, const purse_params *p, float *poses, uint8_t *mask, void *stream) {
+  purse_status s = check_batch(b);
+  if (s) return s;
+  if ((s = check_params(p))) return s;
+  if (!poses || !mask) return fail(PURSE_E_NULL, "an output is NULL");
+  if ((s = check_device())) return s;
+  purse::launch_init(dev_batch(b), dev_params(p), poses, mask, static_cast<hipStream_t>(stream));
+  return hip_check(hipGetLastError(), "init launch");
 }
 
 purse_status purse_walk_default_params(purse_walk_params *w) {

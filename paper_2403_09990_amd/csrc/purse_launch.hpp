@@ -43,4 +43,7 @@ void launch_walk(const DevBatch &b, const DevParams &p, const WalkParams &wp, co
                  int64_t total_starts, const float *starts, float *centre, float *poses, uint8_t *mask,
                  int32_t *decisions, hipStream_t stream);
 
+// Step I candidates: one trial per sample slot of the batch.
+void launch_init(const DevBatch &b, const DevParams &p, float *poses, uint8_t *mask, hipStream_t stream);
+
 }  // namespace purse

@@ -1152,6 +1152,354 @@ __global__ void __launch_bounds__(kBlock) k_megb_sign(const int64_t *__restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Step III of the paper ("The CLOSURE Algorithm"): the exact minimum enclosing
+// ball of the feasible samples, translations in R^3 and rotations as unit
+// quaternions in R^4 put on one hemisphere (the quaternions of the descent's
+// centre and of every sample with a non-negative inner product), replacing
+// the descent's centre.  One workgroup per (instance, chain), float64.
+//
+// The support of the exact ball lies among the samples farthest from the
+// descent's centre, which is close to the exact one: a shell of the
+// farthest samples (a 256-bin histogram of their distance picks a threshold
+// that keeps at most kExactShell of them) is staged in LDS and its exact
+// ball found by support-set iteration: the support set B (at most dim + 1
+// points) and its ball; the shell's farthest point p from the centre, if
+// outside, gives the new ball as the smallest ball enclosing B and p whose
+// boundary holds p and some subset of B (the lanes try the 2^|B| subsets,
+// each by the circumsphere of its points in their affine hull).  The radius
+// grows at every step and the support sets are finite, so this ends; the
+// last ball encloses the shell and is the ball of a subset of it, hence the
+// shell's minimum ball.  Every sample is then checked against it; any sample
+// outside is added to the shell and the iteration resumes, so the final ball
+// encloses all samples and is the minimum ball of a subset: the exact one.
+constexpr int kExactShell = 1024;   // staged at first
+constexpr int kExactCap = 2048;     // shell capacity including samples added by the checks
+constexpr int kExactRounds = 16;    // check-and-add rounds before giving up (the descent's centre is kept)
+constexpr int kExactBins = 256;
+
+__device__ __forceinline__ void exact_point(const float4 *D, int64_t s, int chain, const double ref[4], double x[4]) {
+  const float4 a = D[s];
+  if (chain == 0) {
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+    x[3] = a.w;
+    const double dot = x[0] * ref[0] + x[1] * ref[1] + x[2] * ref[2] + x[3] * ref[3];
+    if (dot < 0.0)
+      for (int k = 0; k < 4; ++k) x[k] = -x[k];
+  } else {
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+    x[3] = 0.0;
+  }
+}
+
+__device__ __forceinline__ double exact_d2(const double x[4], const double c[4]) {
+  double d = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d += (x[k] - c[k]) * (x[k] - c[k]);
+  return d;
+}
+
+// Circumsphere of k points P[0..k) (rows of 4) in their affine hull:
+// c = P0 + sum lam_i (P_i - P0) with 2 (P_i - P0).(c - P0) = |P_i - P0|^2.
+// Returns false for affinely dependent points.
+__device__ __forceinline__ bool exact_circumsphere(const double P[5][4], int k, double c[4], double &r2) {
+  double A[4][4], G[4][4], b[4], lam[4];
+  const int m = k - 1;
+  for (int i = 0; i < m; ++i)
+    for (int q = 0; q < 4; ++q) A[i][q] = P[i + 1][q] - P[0][q];
+  for (int i = 0; i < m; ++i) {
+    b[i] = 0.0;
+    for (int q = 0; q < 4; ++q) b[i] += 0.5 * A[i][q] * A[i][q];
+    for (int jj = 0; jj < m; ++jj) {
+      double g = 0.0;
+      for (int q = 0; q < 4; ++q) g += A[i][q] * A[jj][q];
+      G[i][jj] = g;
+    }
+  }
+  // Cholesky of the Gram matrix (positive definite iff independent)
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = fmax(scale, G[i][i]);
+  for (int i = 0; i < m; ++i) {
+    for (int jj = 0; jj <= i; ++jj) {
+      double v = G[i][jj];
+      for (int q = 0; q < jj; ++q) v -= G[i][q] * G[jj][q];
+      if (i == jj) {
+        if (!(v > 1e-14 * scale)) return false;
+        G[i][i] = sqrt(v);
+      } else {
+        G[i][jj] = v / G[jj][jj];
+      }
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    double v = b[i];
+    for (int q = 0; q < i; ++q) v -= G[i][q] * lam[q];
+    lam[i] = v / G[i][i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double v = lam[i];
+    for (int q = i + 1; q < m; ++q) v -= G[q][i] * lam[q];
+    lam[i] = v / G[i][i];
+  }
+  for (int q = 0; q < 4; ++q) {
+    double v = P[0][q];
+    for (int i = 0; i < m; ++i) v += lam[i] * A[i][q];
+    c[q] = v;
+  }
+  r2 = exact_d2(P[0], c);
+  return true;
+}
+
+__global__ void __launch_bounds__(kBlock) k_megb_exact(const int64_t *__restrict__ sample_off, int64_t total,
+                                                       int64_t max_m, const float4 *__restrict__ quat,
+                                                       const float4 *__restrict__ trans, MegbRec *rec) {
+  const int j = blockIdx.x >> 1, chain = blockIdx.x & 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t off, M64;
+  sample_range(sample_off, j, total, max_m, off, M64);
+  const int M = (int)M64;
+  if (rec[j].first == INT32_MAX) return;  // empty instance (whole workgroup)
+  const float4 *D = (chain ? trans : quat) + off;
+  const int dim = chain ? 3 : 4;
+  __shared__ double pts[kExactCap][4];
+  __shared__ int hist[kExactBins];
+  __shared__ int n_s, fail_s, nb_s, add_s;
+  __shared__ double B_s[5][4], c_s[4], r2_s, thr_s;
+  __shared__ double red_v[kWaves];
+  __shared__ int red_i[kWaves];
+  // the descent's centre (and the hemisphere's reference)
+  double ref[4];
+  {
+    const float *C = rec[j].centre;
+    if (chain == 0) {
+      const float4 q = quat_from_rot(C);
+      ref[0] = q.x;
+      ref[1] = q.y;
+      ref[2] = q.z;
+      ref[3] = q.w;
+    } else {
+      ref[0] = C[9];
+      ref[1] = C[10];
+      ref[2] = C[11];
+      ref[3] = 0.0;
+    }
+  }
+  // ---- largest distance from the descent's centre, then the shell threshold
+  auto block_max = [&](double v, int i, double &bv, int &bi) {
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int i2 = __shfl_xor(i, o, 64);
+      if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = v;
+      red_i[wave] = i;
+    }
+    __syncthreads();
+    bv = red_v[0];
+    bi = red_i[0];
+    for (int w = 1; w < kWaves; ++w)
+      if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+        bv = red_v[w];
+        bi = red_i[w];
+      }
+    __syncthreads();
+  };
+  double dmax = -1.0;
+  int imax = INT32_MAX;
+  for (int s = tid; s < M; s += kBlock) {
+    if (!feasible_pt(D[s], chain)) continue;
+    double x[4];
+    exact_point(D, s, chain, ref, x);
+    const double d = exact_d2(x, ref);
+    if (d > dmax) {
+      dmax = d;
+      imax = s;
+    }
+  }
+  double r2hat;
+  int ihat;
+  block_max(dmax, imax, r2hat, ihat);
+  const double rhat = sqrt(fmax(r2hat, 0.0));
+  for (int k = tid; k < kExactBins; k += kBlock) hist[k] = 0;
+  __syncthreads();
+  // bins of the distance over [0, rhat]; the threshold keeps at most
+  // kExactShell samples (all of them when there are fewer)
+  const double binw = rhat > 0.0 ? rhat / kExactBins : 1.0;
+  for (int s = tid; s < M; s += kBlock) {
+    if (!feasible_pt(D[s], chain)) continue;
+    double x[4];
+    exact_point(D, s, chain, ref, x);
+    const int bin = min(kExactBins - 1, (int)(sqrt(exact_d2(x, ref)) / binw));
+    atomicAdd(&hist[bin], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0, b = kExactBins;
+    while (b > 0 && acc + hist[b - 1] <= kExactShell) acc += hist[--b];
+    thr_s = b == kExactBins ? rhat : b * binw;  // (a top bin over capacity: its farthest sample only)
+    n_s = 0;
+    fail_s = 0;
+  }
+  __syncthreads();
+  const double thr = thr_s;
+  for (int s = tid; s < M; s += kBlock) {
+    if (!feasible_pt(D[s], chain)) continue;
+    double x[4];
+    exact_point(D, s, chain, ref, x);
+    if (sqrt(exact_d2(x, ref)) >= thr || s == ihat) {
+      const int k = atomicAdd(&n_s, 1);
+      if (k < kExactShell)
+        for (int q = 0; q < 4; ++q) pts[k][q] = x[q];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    n_s = min(n_s, kExactShell);
+    // start: the ball of the single farthest sample
+    double x[4];
+    exact_point(D, ihat, chain, ref, x);
+    for (int q = 0; q < 4; ++q) {
+      B_s[0][q] = x[q];
+      c_s[q] = x[q];
+    }
+    nb_s = 1;
+    r2_s = 0.0;
+  }
+  __syncthreads();
+  const double eps = 1e-12;
+  for (int round = 0; round < kExactRounds; ++round) {
+    // ---- support-set iteration on the shell
+    for (int step = 0; step < 4 * kExactCap; ++step) {
+      const double c[4] = {c_s[0], c_s[1], c_s[2], c_s[3]};
+      const double r2 = r2_s;
+      double bv = -1.0;
+      int bi = INT32_MAX;
+      for (int k = tid; k < n_s; k += kBlock) {
+        const double d = exact_d2(pts[k], c);
+        if (d > bv) {
+          bv = d;
+          bi = k;
+        }
+      }
+      double fv;
+      int fi;
+      block_max(bv, bi, fv, fi);
+      if (fi == INT32_MAX || fv <= r2 * (1.0 + eps) + 1e-300) break;
+      // smallest ball with p on its boundary enclosing B and p (wave 0: one
+      // subset of B per lane)
+      if (wave == 0) {
+        const int nb = nb_s;
+        double best_r2 = INFINITY, best_c[4] = {0, 0, 0, 0};
+        int best_m = -1;
+        if (lane < (1 << nb)) {
+          double P[5][4];
+          int k = 0;
+          for (int q = 0; q < 4; ++q) P[k][q] = pts[fi][q];
+          ++k;
+          for (int i = 0; i < nb; ++i)
+            if ((lane >> i) & 1) {
+              if (k < dim + 1)
+                for (int q = 0; q < 4; ++q) P[k][q] = B_s[i][q];
+              ++k;
+            }
+          double cc[4], rr2;
+          if (k <= dim + 1 && exact_circumsphere(P, k, cc, rr2)) {
+            bool encl = true;
+            for (int i = 0; i < nb; ++i) encl = encl && exact_d2(B_s[i], cc) <= rr2 * (1.0 + 1e-10) + 1e-300;
+            if (encl) {
+              best_r2 = rr2;
+              best_m = lane;
+              for (int q = 0; q < 4; ++q) best_c[q] = cc[q];
+            }
+          }
+        }
+        // smallest radius, then the lower subset index
+        double v = -best_r2;
+        int m = best_m < 0 ? INT32_MAX : best_m;
+        for (int o = 32; o >= 1; o >>= 1) {
+          const double v2 = __shfl_xor(v, o, 64);
+          const int m2 = __shfl_xor(m, o, 64);
+          if (v2 > v || (v2 == v && m2 < m)) {
+            v = v2;
+            m = m2;
+          }
+        }
+        if (m == INT32_MAX) {
+          if (lane == 0) fail_s = 1;
+        } else if (lane == m) {
+          double nB[5][4];
+          int k = 0;
+          for (int q = 0; q < 4; ++q) nB[k][q] = pts[fi][q];
+          ++k;
+          for (int i = 0; i < nb; ++i)
+            if ((m >> i) & 1) {
+              for (int q = 0; q < 4; ++q) nB[k][q] = B_s[i][q];
+              ++k;
+            }
+          for (int i = 0; i < k; ++i)
+            for (int q = 0; q < 4; ++q) B_s[i][q] = nB[i][q];
+          nb_s = k;
+          for (int q = 0; q < 4; ++q) c_s[q] = best_c[q];
+          r2_s = best_r2;
+        }
+      }
+      __syncthreads();
+      if (fail_s) break;
+    }
+    if (fail_s) break;
+    // ---- every sample against the ball; samples outside join the shell
+    if (tid == 0) add_s = 0;
+    __syncthreads();
+    {
+      const double c[4] = {c_s[0], c_s[1], c_s[2], c_s[3]};
+      const double lim = r2_s * (1.0 + 1e-9) + 1e-300;
+      for (int s = tid; s < M; s += kBlock) {
+        if (!feasible_pt(D[s], chain)) continue;
+        double x[4];
+        exact_point(D, s, chain, ref, x);
+        if (exact_d2(x, c) > lim) {
+          const int k = atomicAdd(&add_s, 1);
+          const int slot = n_s + k;
+          if (slot < kExactCap)
+            for (int q = 0; q < 4; ++q) pts[slot][q] = x[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (add_s == 0) break;
+    if (tid == 0) {
+      if (n_s + add_s > kExactCap) fail_s = 1;  // (the shell is full: the descent's centre is kept)
+      n_s = min(kExactCap, n_s + add_s);
+    }
+    __syncthreads();
+    if (fail_s) break;
+    if (round == kExactRounds - 1 && tid == 0) fail_s = 1;
+  }
+  __syncthreads();
+  if (tid == 0 && !fail_s) {
+    if (chain == 0) {
+      double q[4] = {c_s[0], c_s[1], c_s[2], c_s[3]};
+      const double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      if (n > 0.0) {
+        const float4 qf = make_float4((float)(q[0] / n), (float)(q[1] / n), (float)(q[2] / n), (float)(q[3] / n));
+        float Rr[9];
+        rot_from_quat(qf, Rr);
+        for (int k = 0; k < 9; ++k) rec[j].centre[k] = Rr[k];
+      }
+    } else {
+      for (int k = 0; k < 3; ++k) rec[j].centre[9 + k] = (float)c_s[k];
+    }
+  }
+}
+
 __global__ void k_megb_final(int n_inst, const MegbRec *rec, float *centre, double *radii, int64_t *n_feasible,
                              int32_t *inst_status) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1211,6 +1559,9 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
                        cap, no_prune);
   hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      trace, rec, p.megb_iters, ck);
+  if (p.flags & PURSE_FLAG_EXACT_MEB)
+    hipLaunchKernelGGL(k_megb_exact, dim3(2 * n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
+                       quat, trans, rec);
   hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                      poses, mask, rec);
   hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,

@@ -25,11 +25,12 @@ constexpr int kWalkBlock = 64 * kWalkWaves;
 
 struct WalkKp {
   float m[3];   // model point a_i / Z_i
-  float c[3];   // b_i, or (z_i.x, z_i.y, 0)
-  float w[3];   // 2D-3D: whitening factor of Lambda_i (upper triangle)
-  float beta;   // beta_i
+  float c[3];   // b_i, or (z_i.x, z_i.y, 0); pose regression: t_i
+  float w[3];   // 2D-3D: whitening factor of Lambda_i (upper triangle); pose regression:
+                // (beta_i^R, beta_i^R + tau, 0)
+  float beta;   // beta_i (pose regression: beta_i^t)
   float bt;     // beta_i + tau
-  float pad;
+  float Ri[9];  // pose regression: the hypothesis' rotation R_i
 };
 
 struct WalkInst {
@@ -49,7 +50,17 @@ __device__ __forceinline__ void walk_eval(const WalkKp *kp, const WalkInst &I, c
 #pragma unroll
     for (int r = 0; r < 3; ++r) P[r] = fmaf(R[3 * r], k.m[0], fmaf(R[3 * r + 1], k.m[1], fmaf(R[3 * r + 2], k.m[2], t[r])));
     float rr;
-    if (I.kind == PURSE_KIND_2D3D) {
+    if (I.kind == PURSE_KIND_REG) {
+      // ||R - R_i||_F and ||t - t_i||: both balls of hypothesis i
+      float f = 0.f;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) f = fmaf(R[q] - k.Ri[q], R[q] - k.Ri[q], f);
+      const float rR = sqrtf(f);
+      d = fminf(d, k.w[0] - rR);
+      ok = ok && (rR <= k.w[1]);
+      const float e0 = t[0] - k.c[0], e1 = t[1] - k.c[1], e2 = t[2] - k.c[2];
+      rr = sqrtf(fmaf(e0, e0, fmaf(e1, e1, e2 * e2)));
+    } else if (I.kind == PURSE_KIND_2D3D) {
       const float iz = 1.f / P[2];
       const float e0 = fmaf(I.K[0], P[0] * iz, I.K[2]) - k.c[0];
       const float e1 = fmaf(I.K[1], P[1] * iz, I.K[3]) - k.c[1];
@@ -176,7 +187,8 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(DevBatch b, DevParams p, Wa
   I.kind = b.kind[j];
   I.n = b.n_kp[j];
   const int64_t ko = b.kp_off[j];
-  const bool valid = (I.kind == PURSE_KIND_3D3D || I.kind == PURSE_KIND_2D3D) && I.n >= 1 && I.n <= PURSE_MAX_KP &&
+  const bool valid = (I.kind == PURSE_KIND_3D3D || I.kind == PURSE_KIND_2D3D || I.kind == PURSE_KIND_REG) && I.n >= 1 &&
+                     I.n <= PURSE_MAX_KP &&
                      ko >= 0 && b.kp_off[j + 1] - ko == I.n && b.kp_off[j + 1] <= b.total_kp;
   if (!valid) {  // (whole wavefront) the start is returned as it is, not in S
     if (lane < 12) out[lane] = lane < 9 ? R[lane] : t[lane - 9];
@@ -185,7 +197,7 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(DevBatch b, DevParams p, Wa
       for (int it = lane; it < wp.n_iters; it += 64) decisions[out_i * wp.n_iters + it] = -1;
     return;
   }
-  const bool is2d = I.kind == PURSE_KIND_2D3D;
+  const bool is2d = I.kind == PURSE_KIND_2D3D, isreg = I.kind == PURSE_KIND_REG;
   for (int k = 0; k < 4; ++k) I.K[k] = is2d ? b.intrinsics[4 * j + k] : 0.f;
   const float tau = is2d ? p.tau2 : p.tau3;
   WalkKp *kp = kp_s[wave];
@@ -193,18 +205,27 @@ __global__ void __launch_bounds__(kWalkBlock) k_walk(DevBatch b, DevParams p, Wa
     const int64_t q = ko + lane;
     WalkKp k;
     for (int r = 0; r < 3; ++r) {
-      k.m[r] = b.model_pts[3 * q + r];
+      k.m[r] = isreg ? 0.f : b.model_pts[3 * q + r];
       k.c[r] = (r < 2 || !is2d) ? b.centres[3 * q + r] : 0.f;
       k.w[r] = 0.f;
     }
+    for (int r = 0; r < 9; ++r) k.Ri[r] = 0.f;
     if (is2d) {
       double w[3];
       whiten_factor<double>(b.shapes + 4 * q, w);
       for (int r = 0; r < 3; ++r) k.w[r] = (float)w[r];
     }
+    if (isreg) {
+      // hypothesis i: rotation from its unit quaternion (shapes), its
+      // rotation bound (model_pts x)
+      const float *qq = b.shapes + 4 * q;
+      const float n = rsqrtf(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+      rot_from_quat(make_float4(qq[0] * n, qq[1] * n, qq[2] * n, qq[3] * n), k.Ri);
+      k.w[0] = b.model_pts[3 * q];
+      k.w[1] = b.model_pts[3 * q] + tau;
+    }
     k.beta = b.bounds[q];
     k.bt = b.bounds[q] + tau;
-    k.pad = 0.f;
     kp[lane] = k;
   }
   __builtin_amdgcn_wave_barrier();

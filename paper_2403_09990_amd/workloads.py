@@ -156,6 +156,52 @@ def make_2d3d(rng: np.random.Generator, n_kp: int = 12, sigma_px: float = 2.0,
                     _seed64(rng), n_samples, R, t)
 
 
+KIND_REG = 2
+
+
+def _quat_of(R: np.ndarray) -> np.ndarray:
+    """Unit quaternion (w, x, y, z), w >= 0, of a rotation matrix."""
+    from scipy.spatial.transform import Rotation
+    q = Rotation.from_matrix(R).as_quat()          # (x, y, z, w)
+    q = np.array([q[3], q[0], q[1], q[2]])
+    return q if q[0] >= 0 else -q
+
+
+def make_reg(rng: np.random.Generator, n_hyp: int = 10, sigma_rot: float = 0.05,
+             sigma_t: float = 0.01, n_samples: int = 1500) -> Instance:
+    """Pose-regression instance (Example 3, eq. PURSEregression with
+    Frobenius and Euclidean balls), shaped like the top pose hypotheses of a
+    regression network: a Haar rotation and t = (U[-.05,.05], U[-.05,.05],
+    U[0.9,1.1]); hypothesis i has R_i = Exp(w_i) R, w_i ~ N(0, sigma_rot^2 I)
+    and t_i = t + N(0, sigma_t^2 I); its bounds are beta_i^R = 2 sqrt(2)
+    sin(theta_i / 2), theta_i ~ U[2, 4] sigma_rot, and beta_i^t ~ U[2, 4]
+    sigma_t, each hypothesis redrawn until the true pose lies within 0.9 of
+    both bounds.  Keypoint i of the batch arrays is hypothesis i: centres =
+    t_i, shapes = the quaternion of R_i, model_pts[:, 0] = beta^R, bounds =
+    beta^t."""
+    from scipy.spatial.transform import Rotation
+    R = haar_rotation(rng)
+    t = np.array([rng.uniform(-0.05, 0.05), rng.uniform(-0.05, 0.05), rng.uniform(0.9, 1.1)])
+    model = np.zeros((n_hyp, 3))
+    centres = np.zeros((n_hyp, 3))
+    shapes = np.zeros((n_hyp, 4))
+    beta = np.zeros(n_hyp)
+    for i in range(n_hyp):
+        th = rng.uniform(2.0, 4.0) * sigma_rot
+        bR = 2.0 * np.sqrt(2.0) * np.sin(th / 2.0)
+        bt = rng.uniform(2.0, 4.0) * sigma_t
+        while True:
+            Ri = Rotation.from_rotvec(rng.normal(0.0, sigma_rot, size=3)).as_matrix() @ R
+            ti = t + rng.normal(0.0, sigma_t, size=3)
+            if np.linalg.norm(R - Ri) <= 0.9 * bR and np.linalg.norm(t - ti) <= 0.9 * bt:
+                break
+        model[i, 0] = bR
+        centres[i] = ti
+        shapes[i] = _quat_of(Ri)
+        beta[i] = bt
+    return Instance(KIND_REG, model, centres, shapes, beta, np.zeros(4), _seed64(rng), n_samples, R, t)
+
+
 # ---------------------------------------------------------------------------
 # The five workloads.  Each takes a seed; instances are reproducible.
 

@@ -329,3 +329,40 @@ def test_fp64_polar_path_agrees():
     st = PT.compare_samples(r32["poses"].cpu().numpy(), r32["mask"].cpu().numpy(),
                             r64["poses"].cpu().numpy(), r64["mask"].cpu().numpy(), max_flip_frac=2e-3)
     _log(st)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2-16k", "batch"])
+def test_exact_meb_against_oracle(cfg):
+    """Step III (PURSE_FLAG_EXACT_MEB): the GPU's exact ball of its own
+    samples against the oracle's (Welzl on the translations and on the
+    hemisphere-aligned quaternions) of the same samples, to float32 input
+    rounding; the exact radii never exceed the descent's."""
+    import paper_2403_09990_amd as P
+    from oracle.exact import exact_megb
+    _log("case: exact meb", cfg)
+    if cfg == "c1":
+        b = W.config_c1(0)
+        gp = _params(n_iters=50)
+    elif cfg == "c2-16k":
+        b = W.config_c2(1, n_samples=16384)
+        gp = _params(n_iters=100)
+    else:
+        b = W.config_c3(6, n_inst=6, m_range=(2000, 40000), n_range=(6, 20))
+        gp = _params(n_iters=30)
+    res = PT.run_gpu(b, gp)
+    gx = _params(**{f: getattr(gp, f) for f, _ in type(gp)._fields_})
+    gx.flags = gp.flags | P.PURSE_FLAG_EXACT_MEB
+    ex = P.megb(res["db"], gx, res["poses"], res["mask"], res["inst_status"].clone(), ws=res["ws"])
+    torch.cuda.synchronize()
+    assert torch.equal(ex["trace"], res["trace"])
+    for j in range(b.n_inst):
+        off, end = int(res["db"].sample_off_host[j]), int(res["db"].sample_off_host[j + 1])
+        C, ct, D, d = exact_megb(res["poses"][off:end].cpu().numpy(), res["mask"][off:end].cpu().numpy())
+        rad = ex["radii"][j].cpu().numpy()
+        gd = res["radii"][j].cpu().numpy()
+        cen = ex["centre"][j].cpu().numpy().astype(np.float64)
+        _log(j, "exact", rad, "oracle", D, d, "descent", gd)
+        assert abs(rad[0] - D) <= 1e-5 * D and abs(rad[1] - d) <= 1e-5 * d
+        assert float(PT.rot_angle(cen[:9].reshape(1, 3, 3), C.reshape(1, 3, 3))[0]) <= PT.CENTRE_TOL
+        assert np.linalg.norm(cen[9:] - ct) <= PT.CENTRE_TOL
+        assert rad[0] <= gd[0] * (1 + 1e-6) and rad[1] <= gd[1] * (1 + 1e-6)
