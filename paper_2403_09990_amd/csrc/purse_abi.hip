@@ -108,7 +108,8 @@ purse::DevParams dev_params(const purse_params *p) {
 }
 
 purse::WsLayout layout_for(const purse_batch *b, const purse_params *p) {
-  return purse::ws_layout(b->n_inst, b->total_kp, b->total_samples, b->max_kp, p->megb_iters, p->ckpt_every);
+  return purse::ws_layout(b->n_inst, b->total_kp, b->total_samples, b->max_samples, b->max_kp, p->megb_iters,
+                          p->ckpt_every);
 }
 
 purse_status check_ws(const purse_batch *b, const purse_params *p, void *ws, size_t ws_bytes) {
@@ -262,8 +263,9 @@ purse_status purse_megb(const purse_batch *b, const purse_params *p, const float
   const purse::DevBatch db = dev_batch(b);
   const purse::DevParams dp = dev_params(p);
   purse::launch_megb(db, dp, poses, mask, at<purse::MegbRec>(ws, L.megb), at<float4>(ws, L.quat),
-                     at<float4>(ws, L.trans), at<float>(ws, L.dref), at<float4>(ws, L.ckpt), centre, radii,
-                     n_feasible, trace, inst_status, b->max_samples, b->total_samples,
+                     at<float4>(ws, L.trans), at<float>(ws, L.dref), at<float4>(ws, L.ckpt),
+                     at<purse::EarlyScratch>(ws, L.early), at<int32_t>(ws, L.gid), at<float4>(ws, L.gpt), centre,
+                     radii, n_feasible, trace, inst_status, b->max_samples, b->total_samples,
                      static_cast<hipStream_t>(stream));
   return hip_check(hipGetLastError(), "megb launch");
 }

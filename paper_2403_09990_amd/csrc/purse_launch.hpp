@@ -20,10 +20,12 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
 
 // ckpt: the rotation iterates C_0, C_ck, ... of every descent, left for the
 // backward ([n_inst][ckpt_count] quaternions) with their trace signature in rec.
+// es, gid, gpt: the first-phase scratch and the global shells (WsLayout
+// early, gid, gpt).
 void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask,
-                 MegbRec *rec, float4 *quat, float4 *trans, float *dref, float4 *ckpt, float *centre,
-                 double *radii, int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
-                 int64_t total_samples, hipStream_t stream);
+                 MegbRec *rec, float4 *quat, float4 *trans, float *dref, float4 *ckpt, EarlyScratch *es,
+                 int32_t *gid, float4 *gpt, float *centre, double *radii, int64_t *n_feasible, int32_t *trace,
+                 int32_t *inst_status, int64_t max_samples, int64_t total_samples, hipStream_t stream);
 
 // megb / ckpt: the records and checkpoints purse_megb left in the workspace,
 // used when the signature matches the given trace; otherwise the descent is

@@ -50,17 +50,36 @@ struct MegbRec {
   float centre[12];       // R* row-major, t*
   long long n_groups[2];  // diagnostics: chunk groups scanned in shell steps per chain
   float4 early_c[2];      // centre after the steps taken by the multi-workgroup first phase
-  int32_t early_arrive[2];  // workgroups of the current first-phase step that have finished
-  int32_t pad2[2];
+  // global shell of each chain (instances of the first phase): the gs_n
+  // samples at distance >= gs_theta from early_c (gs_theta = -1: every
+  // feasible sample; gs_n = -1: no shell)
+  int32_t gs_n[2];
+  float gs_theta[2];
   // rotation iterates C_0, C_ck, C_2ck, ... left for the backward, valid for
   // the trace whose signature is ck_hash (ck_T = 0: none)
   unsigned long long ck_hash;
   int32_t ck_T, ck_every;
-  // best (key, id) of the current first-phase step per chain, packed as
-  // key bits << 32 | ~id so that an unsigned max keeps the larger key and,
-  // on equal keys, the lower id (0: none yet)
-  unsigned long long early_best[2];
+  int32_t pad2[4];
 };
+static_assert(sizeof(MegbRec) == 192, "MegbRec layout");
+
+// Instances of at least kBigInstance samples take the first kEarlySteps
+// descent steps in kEarlyWG workgroups per chain, one launch per step, and
+// then gather their global shell: the farthest samples from the centre the
+// first phase reached, at most one in kShellDiv of the instance's samples,
+// which the chain's rescans stream instead of every sample.
+constexpr int64_t kBigInstance = 32768;
+constexpr int kEarlySteps = 32;
+constexpr int kEarlyWG = 64;
+constexpr int kShellBins = 256;
+constexpr int kShellDiv = 16;
+
+// Global-shell slots of an instance: [off / kShellDiv, off / kShellDiv +
+// M / kShellDiv) in each chain's array (disjoint between instances, since
+// floor(a) + floor(b) <= floor(a + b)).
+__host__ __device__ inline int64_t gshell_stride(int64_t total_samples, int64_t max_samples) {
+  return max_samples >= kBigInstance ? total_samples / kShellDiv + 1 : 0;
+}
 
 // Per-step term of the signature that ties the stored iterates to the
 // rotation argmax trace they belong to: the splitmix64 finaliser of (i, id),
@@ -98,7 +117,20 @@ constexpr size_t kAlign = 256;
 __host__ __device__ constexpr size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, items, total;
+  size_t inst, kp, sched, megb, quat, trans, dref, bwd, ckpt, tan, contrib, items, early, gid, gpt, total;
+};
+
+// First-phase scratch per (instance, chain): the packed (key, ~id) argmax of
+// every workgroup for two consecutive steps, the centre for two consecutive
+// steps, every workgroup's largest distance, the global shell's histogram
+// and its fill count.
+struct EarlyScratch {
+  unsigned long long part[2][kEarlyWG];
+  float4 cbuf[2];
+  float dmax[kEarlyWG];
+  unsigned int hist[kShellBins];
+  int32_t count;
+  int32_t pad[3];
 };
 
 // Tile schedule of the sampler, one per launch group (3D-3D; 2D-3D with the
@@ -109,8 +141,8 @@ constexpr int kSchedGroups = 3;
 __host__ __device__ inline size_t sched_ints(int64_t n_inst) { return 2 * (size_t)n_inst + 1; }
 
 // Byte offsets of the workspace regions.
-inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, int max_kp, int megb_iters,
-                          int ckpt_every) {
+inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_samples, int64_t max_samples, int max_kp,
+                          int megb_iters, int ckpt_every) {
   WsLayout L;
   size_t o = 0;
   L.inst = o;
@@ -139,6 +171,14 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   o += align_up(sizeof(float) * (size_t)n_inst * kMaxActive * dirs);
   L.items = o;  // work-item prefix sums of the tangent kernels, 2D-3D then 3D-3D
   o += align_up(sizeof(int64_t) * 2 * ((size_t)n_inst + 1));
+  const bool big = max_samples >= kBigInstance;
+  L.early = o;  // [n_inst][2] first-phase scratch
+  o += big ? align_up(sizeof(EarlyScratch) * 2 * (size_t)n_inst) : 0;
+  const size_t gs = (size_t)gshell_stride(total_samples, max_samples);
+  L.gid = o;  // [2][stride] sample ids of the global shells
+  o += align_up(sizeof(int32_t) * 2 * gs);
+  L.gpt = o;  // [2][stride] their points (quaternion or translation)
+  o += align_up(16 * 2 * gs);
   L.total = o;
   return L;
 }

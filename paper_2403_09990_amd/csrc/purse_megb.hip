@@ -43,7 +43,6 @@ constexpr int chain_cap() { return PIPE ? 3072 : 1536; }
 constexpr int kUnroll = 8;
 constexpr int kCap = 3072;
 constexpr int kMaxChunks = kCap / 64;
-constexpr int kEarlySteps = 32;
 constexpr int kRecentreChunks = 4;  // a step scanning more chunks than this ...
 constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
 constexpr int kPipeSteps = 64;       // steps per round of a pipelined segment (one per lane)
@@ -175,71 +174,131 @@ __global__ void k_megb_init(int n_inst, MegbRec *rec) {
   rec[j].n_feasible = 0ull;
   rec[j].max_rot = 0ull;
   rec[j].max_trans = 0ull;
-  rec[j].early_arrive[0] = rec[j].early_arrive[1] = 0;
-  rec[j].early_best[0] = rec[j].early_best[1] = 0ull;
+  rec[j].gs_n[0] = rec[j].gs_n[1] = -1;
+  rec[j].gs_theta[0] = rec[j].gs_theta[1] = -1.f;
   rec[j].ck_hash = 0ull;
   rec[j].ck_T = 0;
   rec[j].ck_every = 0;
 }
 
+// Bin of d among kBins bins of width 1 / rw from lo (rw the reciprocal of
+// the width, so a pass over every sample takes no division).  The rounding of
+// the product can move d by one bin near an edge, which shifts the bins'
+// edges as bounds by about 1e-7 of the distance, far inside the shell
+// checks' slack; every pass uses this same function, so counts and members
+// agree.
+__device__ __forceinline__ int bin_of(float d, float lo, float rw) {
+  int b = (int)((d - lo) * rw);
+  return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+}
+
+static_assert(kShellBins == kBins, "one binning for the global and the chain shells");
+
 // The first kEarlySteps steps move the centre across the whole sample cloud,
 // so each needs a scan of every feasible sample.  For instances of at least
-// kBigInstance samples these scans are spread over many workgroups, one
-// launch per step (k_megb_early); smaller instances take them inside their
-// chain's workgroup.  Host and device apply the same rule.
-constexpr int64_t kBigInstance = 32768;
+// kBigInstance samples these scans are spread over kEarlyWG workgroups per
+// chain, one launch per step (k_megb_early); smaller instances take them
+// inside their chain's workgroup.  Host and device apply the same rule.
 constexpr int kEarlyBlock = 256;
-constexpr int kEarlyPer = 8;                            // samples per thread
-constexpr int kEarlySpan = kEarlyBlock * kEarlyPer;     // samples per workgroup
 
 __host__ __device__ inline bool early_phase_applies(int64_t M, int T, int avg, int no_prune) {
   return M >= kBigInstance && T > kEarlySteps + avg && !no_prune;
 }
 
-// One step i of both chains of every instance the rule selects, whose
-// feasible samples outnumber the shell capacity (else the shell holds them
-// all and the chain's workgroup needs no full scans).  Workgroup b of
-// (instance j, chain c) finds the farthest of its kEarlySpan samples from the
-// current centre and folds (key, id) into the chain's packed maximum with one
-// 64-bit atomic; the last workgroup to finish (arrival counter) takes the
-// maximum and clears it, takes the geodesic step, records the trace and
-// resets the counter.  The sample loads are issued before the per-instance
-// record is read, so their latency overlaps that read.
+// Samples [sb, se) of workgroup b of a chain: kEarlyWG ranges of a multiple
+// of kEarlyBlock samples.
+__device__ __forceinline__ void early_range(int M, int b, int &sb, int &se) {
+  const int span = ((M + kEarlyWG - 1) / kEarlyWG + kEarlyBlock - 1) / kEarlyBlock * kEarlyBlock;
+  sb = min(M, b * span);
+  se = min(M, sb + span);
+}
+
+// Largest 64-bit value of the wavefront (unsigned), in every lane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// (key, id) packed so that an unsigned maximum keeps the larger key and, on
+// equal keys, the lower id; keys are >= 0 (a -0 is taken as +0, which it
+// equals).  0: no sample.
+__device__ __forceinline__ unsigned long long pack_best(float k, int id) {
+  return id == INT32_MAX ? 0ull
+                         : ((unsigned long long)(__float_as_uint(k) & 0x7fffffffu) << 32) |
+                               (unsigned long long)(~(unsigned)id);
+}
+
+// Step i of the first phase for every (instance, chain) the rule selects,
+// whose feasible samples outnumber the shell capacity (else the shell holds
+// them all and the chain's workgroup needs no full scans).  Every workgroup
+// first completes step i - 1 itself: it reduces the kEarlyWG packed argmaxes
+// the previous launch left and takes the geodesic step from the centre that
+// launch started from, so all workgroups hold the same centre with no atomic
+// or fence (kernel boundaries order the launches); workgroup 0 records the
+// trace, the checkpoint and the centre for the next launch.  Then each
+// workgroup finds the farthest of its samples and leaves its packed argmax.
+// Launch kEarlySteps + 1 only completes the last step and, as the first pass
+// of the global shell, writes every sample's distance from that centre to
+// dref and each workgroup's largest distance.  Buffers alternate between
+// consecutive launches, so a launch never writes what it reads.
 __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__restrict__ sample_off, int64_t total,
                                                             int64_t max_m, const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
-                                                            int32_t *trace, float4 *ckpt, int ck,
-                                                            int T, int avg, int cap, int no_prune, int i) {
+                                                            EarlyScratch *es, float *dref_all, int32_t *trace,
+                                                            float4 *ckpt, int ck, int T, int avg, int cap,
+                                                            int no_prune, int i) {
   const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
   sample_range(sample_off, j, total, max_m, off, M64);
   if (!early_phase_applies(M64, T, avg, no_prune)) return;
   const int M = (int)M64;  // >= kBigInstance here
-  const int nb = (M + kEarlySpan - 1) / kEarlySpan;
-  if (b >= nb) return;
-  const float4 *D = (chain ? trans : quat) + off;
-  float4 a[kEarlyPer];
-#pragma unroll
-  for (int u = 0; u < kEarlyPer; ++u) a[u] = D[min(b * kEarlySpan + u * kEarlyBlock + tid, M - 1)];
   const int first = rec[j].first;
   if (first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
-  const float4 C = i == 1 ? D[first] : rec[j].early_c[chain];
-  float bk = -1.f;
-  int bi = INT32_MAX;
-#pragma unroll
-  for (int u = 0; u < kEarlyPer; ++u) {
-    const int s = b * kEarlySpan + u * kEarlyBlock + tid;
-    const float k = sqdist(C, a[u], chain);
-    // increasing s per thread: a strictly larger key replaces the best
-    if (s < M && feasible_pt(a[u], chain) && k > bk) {
-      bk = k;
-      bi = s;
-    }
+  const float4 *D = (chain ? trans : quat) + off;
+  EarlyScratch &e = es[2 * j + chain];
+  int sb, se;
+  early_range(M, b, sb, se);
+  // ---- the centre before step i (every wave reduces the partials itself)
+  float4 C;
+  if (i == 1) {
+    C = D[first];
+  } else {
+    static_assert(kEarlyWG == 64, "one partial per lane");
+    const unsigned long long best = wave_max_u64(e.part[(i - 1) & 1][lane]);
+    const int bi = best ? (int)~(unsigned)(best & 0xffffffffull) : INT32_MAX;
+    const float4 Cp = e.cbuf[i & 1];
+    C = bi < M ? geodesic_step(Cp, D[bi], i - 1, chain) : Cp;
+    if (b == 0 && tid == 0) trace[((int64_t)j * T + i - 2) * 2 + chain] = bi;
+  }
+  if (b == 0 && tid == 0) {
+    e.cbuf[(i + 1) & 1] = C;
+    if (i <= kEarlySteps && chain == 0 && (i - 1) % ck == 0) ckpt[(int64_t)j * ckpt_count(T, ck) + (i - 1) / ck] = C;
+    if (i > kEarlySteps) rec[j].early_c[chain] = C;
   }
   __shared__ float red_k[kEarlyBlock / 64];
   __shared__ int red_i[kEarlyBlock / 64];
-  auto block_argmax = [&]() {
+  if (i <= kEarlySteps) {
+    // ---- step i over this workgroup's samples
+    float bk = -1.f;
+    int bi = INT32_MAX;
+    stream_rounds<kEarlyBlock>(D + sb, se - sb, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int s = sb + s0 + u * kEarlyBlock + tid;
+        if (s < se && feasible_pt(a[u], chain)) {
+          const float k = sqdist(C, a[u], chain);
+          if (better(k, s, bk, bi)) {
+            bk = k;
+            bi = s;
+          }
+        }
+      }
+    });
     float wk;
     int wi;
     wave_argmax(bk, bi, wk, wi);
@@ -248,31 +307,173 @@ __global__ void __launch_bounds__(kEarlyBlock) k_megb_early(const int64_t *__res
       red_i[wave] = wi;
     }
     __syncthreads();
-    bk = red_k[0];
-    bi = red_i[0];
+    if (tid == 0) {
+      bk = red_k[0];
+      bi = red_i[0];
 #pragma unroll
-    for (int w = 1; w < kEarlyBlock / 64; ++w)
-      if (better(red_k[w], red_i[w], bk, bi)) {
-        bk = red_k[w];
-        bi = red_i[w];
+      for (int w = 1; w < kEarlyBlock / 64; ++w)
+        if (better(red_k[w], red_i[w], bk, bi)) {
+          bk = red_k[w];
+          bi = red_i[w];
+        }
+      e.part[i & 1][b] = pack_best(bk, bi);
+    }
+    return;
+  }
+  // ---- global shell, first pass: distances from the centre
+  float *dref = dref_all + chain * total + off;
+  float mx = 0.f;
+  stream_rounds<kEarlyBlock>(D + sb, se - sb, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int s = sb + s0 + u * kEarlyBlock + tid;
+      if (s < se) {
+        float d = -1.f;
+        if (feasible_pt(a[u], chain)) {
+          d = __builtin_amdgcn_sqrtf(sqdist(C, a[u], chain));
+          mx = fmaxf(mx, d);
+        }
+        dref[s] = d;
       }
-  };
-  block_argmax();
-  if (tid != 0) return;
-  // keys are >= 0 (no NaN is ever selected; a -0 is taken as +0, which it
-  // equals), so their bit patterns order as the values do
-  if (bi != INT32_MAX)
-    atomicMax(&rec[j].early_best[chain], ((unsigned long long)(__float_as_uint(bk) & 0x7fffffffu) << 32) |
-                                             (unsigned long long)(~(unsigned)bi));
-  __threadfence();
-  if (atomicAdd(&rec[j].early_arrive[chain], 1) != nb - 1) return;
-  __threadfence();
-  const unsigned long long best = atomicExch(&rec[j].early_best[chain], 0ull);
-  bi = best ? (int)~(unsigned)(best & 0xffffffffull) : INT32_MAX;
-  if (chain == 0 && (i - 1) % ck == 0) ckpt[(int64_t)j * ckpt_count(T, ck) + (i - 1) / ck] = C;
-  if (bi < M) rec[j].early_c[chain] = geodesic_step(C, D[bi], i, chain);
-  trace[((int64_t)j * T + i - 1) * 2 + chain] = bi;
-  rec[j].early_arrive[chain] = 0;
+    }
+  });
+  mx = wave_max(mx);
+  if (lane == 0) red_k[wave] = mx;
+  if (b == 0) {
+    for (int k = tid; k < kShellBins; k += kEarlyBlock) e.hist[k] = 0u;
+    if (tid == 0) e.count = 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int w = 1; w < kEarlyBlock / 64; ++w) mx = fmaxf(mx, red_k[w]);
+    e.dmax[b] = fmaxf(mx, red_k[0]);
+  }
+}
+
+// Histogram bin width of a chain's global shell: the largest distance over
+// kShellBins (every workgroup computes it the same way); 0 when every
+// feasible sample sits at the centre.
+__device__ __forceinline__ float gshell_width(const EarlyScratch &e) {
+  static_assert(kEarlyWG == 64, "one entry per lane");
+  return wave_max(e.dmax[threadIdx.x & 63]) / (float)kShellBins;
+}
+
+// Global shell, second pass: histogram of the distances over [0, max].
+__global__ void __launch_bounds__(kEarlyBlock) k_megb_gshell_hist(const int64_t *__restrict__ sample_off,
+                                                                  int64_t total, int64_t max_m, MegbRec *rec,
+                                                                  EarlyScratch *es, const float *dref_all, int T,
+                                                                  int avg, int cap, int no_prune) {
+  const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
+  const int tid = threadIdx.x;
+  int64_t off, M64;
+  sample_range(sample_off, j, total, max_m, off, M64);
+  if (!early_phase_applies(M64, T, avg, no_prune)) return;
+  if (rec[j].first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
+  EarlyScratch &e = es[2 * j + chain];
+  const float w = gshell_width(e);
+  if (!(w > 0.f)) return;
+  const float rw = 1.f / w;
+  __shared__ unsigned int h[kShellBins];
+  for (int k = tid; k < kShellBins; k += kEarlyBlock) h[k] = 0u;
+  __syncthreads();
+  int sb, se;
+  early_range((int)M64, b, sb, se);
+  const float *dref = dref_all + chain * total + off;
+  stream_rounds<kEarlyBlock, 16>(dref + sb, se - sb, -1.f, [&](const float *dd, int) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (dd[u] >= 0.f) atomicAdd(&h[bin_of(dd[u], 0.f, rw)], 1u);
+  });
+  __syncthreads();
+  for (int k = tid; k < kShellBins; k += kEarlyBlock)
+    if (h[k]) atomicAdd(&e.hist[k], h[k]);
+}
+
+// Global shell, third pass: the threshold (the lowest bin edge above which at
+// most M / kShellDiv samples lie) and the members, compacted into the
+// chain's slots: each workgroup counts its members per wave, reserves its
+// range with one atomic, and writes them wave by wave in sample order.  The
+// order of the workgroups' ranges varies from run to run; every use of the
+// shell is order-independent (argmax ties go to the lowest sample id).
+__global__ void __launch_bounds__(kEarlyBlock) k_megb_gshell_collect(const int64_t *__restrict__ sample_off,
+                                                                     int64_t total, int64_t max_m,
+                                                                     const float4 *__restrict__ quat,
+                                                                     const float4 *__restrict__ trans,
+                                                                     MegbRec *rec, EarlyScratch *es,
+                                                                     const float *dref_all, int32_t *gid_all,
+                                                                     float4 *gpt_all, int64_t gstride, int T,
+                                                                     int avg, int cap, int no_prune) {
+  const int j = blockIdx.z, chain = blockIdx.y, b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t off, M64;
+  sample_range(sample_off, j, total, max_m, off, M64);
+  if (!early_phase_applies(M64, T, avg, no_prune)) return;
+  if (rec[j].first == INT32_MAX || (int64_t)rec[j].n_feasible <= cap) return;
+  EarlyScratch &e = es[2 * j + chain];
+  const float w = gshell_width(e);
+  if (!(w > 0.f)) return;  // no shell (gs_n stays -1)
+  const float rw = 1.f / w;
+  const int M = (int)M64;
+  const int G = M / kShellDiv;
+  __shared__ int sh_bstar, sh_n;
+  __shared__ int wcount[kEarlyBlock / 64], wbase[kEarlyBlock / 64];
+  if (tid == 0) {
+    int cum = 0, bb = kShellBins - 1;
+    for (; bb >= 0; --bb) {
+      if (cum + (int)e.hist[bb] > G) break;
+      cum += (int)e.hist[bb];
+    }
+    // bb < 0: every feasible sample fits; bb = kShellBins - 1: the top bin
+    // alone is too large (no shell)
+    sh_bstar = bb + 1;
+    sh_n = cum;
+    if (b == 0) {
+      rec[j].gs_n[chain] = bb == kShellBins - 1 ? -1 : cum;
+      rec[j].gs_theta[chain] = bb < 0 ? -1.f : (float)(bb + 1) * w;
+    }
+  }
+  __syncthreads();
+  const int bstar = sh_bstar;
+  if (bstar >= kShellBins) return;
+  int sb, se;
+  early_range(M, b, sb, se);
+  // each wave takes a contiguous quarter of the range
+  const int q = ((se - sb + kEarlyBlock / 64 - 1) / (kEarlyBlock / 64) + 63) / 64 * 64;
+  const int wb = min(se, sb + wave * q), we = min(se, wb + q);
+  const float *dref = dref_all + chain * total + off;
+  auto member = [&](float d) { return d >= 0.f && bin_of(d, 0.f, rw) >= bstar; };
+  int cnt = 0;
+  for (int s = wb + lane; s < we; s += 64) cnt += member(dref[s]) ? 1 : 0;
+  for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (lane == 0) wcount[wave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int t = 0;
+    for (int k = 0; k < kEarlyBlock / 64; ++k) {
+      wbase[k] = t;
+      t += wcount[k];
+    }
+    const int base = t ? atomicAdd(&e.count, t) : 0;
+    for (int k = 0; k < kEarlyBlock / 64; ++k) wbase[k] += base;
+  }
+  __syncthreads();
+  const float4 *D = (chain ? trans : quat) + off;
+  int32_t *gid = gid_all + chain * gstride + off / kShellDiv;
+  float4 *gpt = gpt_all + chain * gstride + off / kShellDiv;
+  int pos = wbase[wave];
+  for (int s0 = wb; s0 < we; s0 += 64) {
+    const int s = s0 + lane;
+    const bool m = s < we && member(dref[s]);
+    const unsigned long long mk = __ballot(m);
+    const int p = pos + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+    if (m && p < G) {
+      gid[p] = s;
+      gpt[p] = D[s];
+    }
+    pos += __popcll(mk);
+  }
+  (void)sh_n;
 }
 
 // Per sample: quaternion (w >= 0; w = -2 marks an infeasible sample) and
@@ -339,23 +540,13 @@ struct ChainShared {
   int (*red_i)[kChainWaves];
 };
 
-// Bin of distance d in a histogram of kBins bins of width w from lo.
-// Bin of d among kBins bins of width 1 / rw from lo (rw the reciprocal of
-// the width, so a pass over every sample takes no division).  The rounding of
-// the product can move d by one bin near an edge, which shifts the bins'
-// edges as bounds by about 1e-7 of the distance, far inside the shell
-// checks' slack; every pass uses this same function, so counts and members
-// agree.
-__device__ __forceinline__ int bin_of(float d, float lo, float rw) {
-  int b = (int)((d - lo) * rw);
-  return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
-}
-
 template <int CHAIN, bool PIPE>
 __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *__restrict__ sample_off,
                                           int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
                                           float *dref_all, int64_t total_samples, int32_t *trace,
-                                          float4 *ckpt_all, int ck, int T, int avg, int cap, int no_prune) {
+                                          float4 *ckpt_all, int ck, int T, int avg, int cap, int no_prune,
+                                          const int32_t *__restrict__ gid_all, const float4 *__restrict__ gpt_all,
+                                          int64_t gstride) {
   __shared__ float4 st_C;
   __shared__ int st_i;
   __shared__ float st_theta, st_lo, st_w, st_rref;
@@ -392,10 +583,20 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
     return;
   }
   const int n_feas = (int)rec[j].n_feasible;
+  // the first steps were taken by k_megb_early when the rule selects it,
+  // which also gathered the global shell: the gs_n samples at distance
+  // >= gs_theta from C_g (gs_theta = -1: every feasible sample).  Samples
+  // outside it lie within gs_theta + d(C, C_g) of any centre C, so rescans
+  // stream the shell alone while that bound stays below the farthest member.
+  const bool ep = early_phase_applies(M64, T, avg, no_prune) && n_feas > cap;
+  const int gs_n = ep ? rec[j].gs_n[chain] : -1;
+  const float gs_theta = ep ? rec[j].gs_theta[chain] : -1.f;
+  const float4 Cg = rec[j].early_c[chain];
+  const int32_t *gid = gid_all + chain * gstride + off / kShellDiv;
+  const float4 *gpt = gpt_all + chain * gstride + off / kShellDiv;
+  bool use_gs = gs_n > 0;
   if (tid == 0) {
-    // the first steps were taken by k_megb_early when the rule selects it
-    const bool ep = early_phase_applies(M64, T, avg, no_prune) && n_feas > cap;
-    st_C = ep ? rec[j].early_c[chain] : D[first];
+    st_C = ep ? Cg : D[first];
     st_i = ep ? kEarlySteps + 1 : 1;
   }
   __syncthreads();
@@ -416,12 +617,16 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
     if (!global) {
       // -------------------------------------------------------------- rescan
       ++n_rescan;
+      // entries: the global shell's or every sample
+      const float4 *src = use_gs ? gpt : D;
+      const int n_src = use_gs ? gs_n : M;
+      const int n_src_feas = use_gs ? gs_n : n_feas;
       float mx = 0.f;
-      stream_rounds<BLK>(D, M, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
+      stream_rounds<BLK>(src, n_src, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           int s = s0 + u * BLK + tid;
-          if (s < M) {
+          if (s < n_src) {
             float d = -1.f;
             if (feasible_pt(a[u], chain)) {
               d = __builtin_amdgcn_sqrtf(sqdist(Cref, a[u], chain));  // within the slack
@@ -437,6 +642,17 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       float rref = 0.f;
 #pragma unroll
       for (int k = 0; k < NW; ++k) rref = fmaxf(rref, S.red_k[0][k]);
+      // bound of every sample outside the global shell
+      float theta_out = -1.f;
+      if (use_gs && gs_theta >= 0.f) {
+        theta_out = gs_theta + __builtin_amdgcn_sqrtf(sqdist(Cref, Cg, chain));
+        if (!(theta_out < rref)) {
+          // the shell can no longer certify a step: rescan every sample
+          use_gs = false;
+          __syncthreads();  // (S.red_k is read above and written by the next rescan)
+          continue;
+        }
+      }
       // Shell membership: d >= theta and (coarse) bin >= bstar of the
       // histogram (lo, w); theta = -1 when every feasible sample fits.
       if (tid == 0) {
@@ -448,7 +664,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         st_rref = rref;
       }
       __syncthreads();
-      if (n_feas > cap) {
+      if (n_src_feas > cap) {
         for (int level = 0; level < 2; ++level) {
           const float lo = st_lo, wdt = st_w;
           if (!(wdt > 0.f)) {
@@ -459,7 +675,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
           __syncthreads();
           const float rw = 1.f / wdt;
-          stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
+          stream_rounds<BLK, UF>(dref, n_src, -1.f, [&](const float *dd, int) {
 #pragma unroll
             for (int u = 0; u < UF; ++u)
               if (dd[u] >= lo && dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], lo, rw)], 1u);
@@ -489,6 +705,9 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           if (st_theta != -2.f || st_mode == 1) break;
         }
       }
+      // samples outside the global shell are bounded by theta_out
+      if (use_gs && tid == 0 && st_mode == 0) st_theta = fmaxf(st_theta, theta_out);
+      __syncthreads();
       // ---------------- collect, ordered by fine bins over [max(theta,0), rref]
       if (st_mode == 0) {
         const float lo = st_lo, wdt = st_w, theta = st_theta;
@@ -503,7 +722,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         auto fbin = [&](float d) { return fine ? bin_of(d, flo, rfw) : kBins - 1; };
         for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
         __syncthreads();
-        stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int) {
+        stream_rounds<BLK, UF>(dref, n_src, -1.f, [&](const float *dd, int) {
 #pragma unroll
           for (int u = 0; u < UF; ++u)
             if (member(dd[u])) atomicAdd(&S.hist[fbin(dd[u])], 1u);
@@ -523,7 +742,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         if (st_mode == 0) {
           // the ids first; the points are gathered afterwards in one pass
           // over the shell, all loads in flight at once
-          stream_rounds<BLK, UF>(dref, M, -1.f, [&](const float *dd, int s0) {
+          stream_rounds<BLK, UF>(dref, n_src, -1.f, [&](const float *dd, int s0) {
 #pragma unroll
             for (int u = 0; u < UF; ++u) {
               int s = s0 + u * BLK + tid;
@@ -534,7 +753,16 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             }
           });
           __syncthreads();
-          for (int e = tid; e < (int)sh_n; e += BLK) S.pt[e] = D[S.id[e]];
+          // (global shell: the entry index becomes the sample id)
+          if (use_gs) {
+            for (int e = tid; e < (int)sh_n; e += BLK) {
+              const int x = S.id[e];
+              S.pt[e] = gpt[x];
+              S.id[e] = gid[x];
+            }
+          } else {
+            for (int e = tid; e < (int)sh_n; e += BLK) S.pt[e] = D[S.id[e]];
+          }
           __syncthreads();
           // upper bound of d_ref over each chunk of 64 entries: the upper edge
           // of the fine bin holding its first entry (the top bin's is rref)
@@ -1015,7 +1243,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         // the next write to either follows the barrier that ends the next
         // sequential segment)
       }
-      stalled = st_i == i0;
+      // a stage that made no step: with the global shell, rescan every
+      // sample next; else a stage of full scans
+      stalled = st_i == i0 && !use_gs;
+      if (st_i == i0) use_gs = false;
     }
   }
   // ------------------------------------------------------------------ centre
@@ -1049,7 +1280,8 @@ __global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chai
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
                                                             int32_t *trace, float4 *ckpt, int ck, int T, int avg,
-                                                            int cap, int no_prune) {
+                                                            int cap, int no_prune, const int32_t *gid,
+                                                            const float4 *gpt, int64_t gstride) {
   extern __shared__ float4 sh_pt[];
   __shared__ unsigned int hist[kBins];
   __shared__ unsigned int cursor[kBins];
@@ -1059,10 +1291,10 @@ __global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chai
   const ChainShared S{sh_pt, reinterpret_cast<int *>(sh_pt + cap), hist, cursor, chunk_ub, red_k, red_i};
   if (blockIdx.x & 1)
     chain_run<1, PIPE>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
-                       no_prune);
+                       no_prune, gid, gpt, gstride);
   else
     chain_run<0, PIPE>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
-                       no_prune);
+                       no_prune, gid, gpt, gstride);
 }
 
 // float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.
@@ -1522,9 +1754,9 @@ __global__ void k_megb_final(int n_inst, const MegbRec *rec, float *centre, doub
 }
 
 void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, const uint8_t *mask, MegbRec *rec,
-                 float4 *quat, float4 *trans, float *dref, float4 *ckpt, float *centre, double *radii,
-                 int64_t *n_feasible, int32_t *trace, int32_t *inst_status, int64_t max_samples,
-                 int64_t total_samples, hipStream_t stream) {
+                 float4 *quat, float4 *trans, float *dref, float4 *ckpt, EarlyScratch *es, int32_t *gid, float4 *gpt,
+                 float *centre, double *radii, int64_t *n_feasible, int32_t *trace, int32_t *inst_status,
+                 int64_t max_samples, int64_t total_samples, hipStream_t stream) {
   const int ck = ckpt_spacing(p.ckpt_every);
   const int n = b.n_inst;
   hipLaunchKernelGGL(k_megb_init, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec);
@@ -1543,20 +1775,26 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   const int cap = pipe ? chain_cap<true>() : chain_cap<false>();
   const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
   const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
+  const int64_t gstride = gshell_stride(total_samples, max_samples);
   if (early_phase_applies(max_samples, p.megb_iters, p.megb_avg, no_prune)) {
-    const dim3 eg((unsigned)((max_samples + kEarlySpan - 1) / kEarlySpan), 2u, (unsigned)n);
-    for (int i = 1; i <= kEarlySteps; ++i)
+    const dim3 eg((unsigned)kEarlyWG, 2u, (unsigned)n);
+    for (int i = 1; i <= kEarlySteps + 1; ++i)
       hipLaunchKernelGGL(k_megb_early, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples, max_samples,
-                         quat, trans, rec, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
+                         quat, trans, rec, es, dref, trace, ckpt, ck, p.megb_iters, p.megb_avg, cap, no_prune, i);
+    hipLaunchKernelGGL(k_megb_gshell_hist, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples,
+                       max_samples, rec, es, dref, p.megb_iters, p.megb_avg, cap, no_prune);
+    hipLaunchKernelGGL(k_megb_gshell_collect, eg, dim3(kEarlyBlock), 0, stream, b.sample_off, total_samples,
+                       max_samples, quat, trans, rec, es, dref, gid, gpt, gstride, p.megb_iters, p.megb_avg, cap,
+                       no_prune);
   }
   if (pipe)
     hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(chain_block<true>()), lds, stream, b.sample_off,
                        max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
-                       cap, no_prune);
+                       cap, no_prune, gid, gpt, gstride);
   else
     hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(chain_block<false>()), lds, stream, b.sample_off,
                        max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
-                       cap, no_prune);
+                       cap, no_prune, gid, gpt, gstride);
   hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      trace, rec, p.megb_iters, ck);
   if (p.flags & PURSE_FLAG_EXACT_MEB)

@@ -237,12 +237,13 @@ def test_megb_against_oracle_on_gpu_samples(cfg):
     assert int(res["n_feasible"][0]) == ora["n"]
 
 
-@pytest.mark.parametrize("m", [12000, 40000])
+@pytest.mark.parametrize("m", [12000, 40000, 131072])
 def test_megb_pruning_is_exact(m):
     """The LDS shell with triangle-inequality checks (and, from 32,768
-    samples, the first steps spread over many workgroups) gives bitwise the
-    same argmax trace and centre as scanning every sample at every step in
-    one workgroup."""
+    samples, the first steps spread over many workgroups and rescans that
+    stream the global shell of the farthest sixteenth) gives bitwise the same
+    argmax trace and centre as scanning every sample at every step in one
+    workgroup."""
     _log("case: pruning", m)
     b = W.config_c2(1, n_samples=m)
     gp = _params(n_iters=40, megb_iters=1024)
