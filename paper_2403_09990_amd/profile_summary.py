@@ -169,8 +169,16 @@ def counters(dirname, kernel):
 
 
 def _mean_for(disp, pred):
+    """Mean over the dispatches of the matching kernels that carry the
+    workload: those within half of the largest (a launch group with no
+    instances, whose workgroups exit at once, would otherwise pull the mean
+    down)."""
     v = [x for n, x in disp if pred(n)]
-    return (sum(v) / len(v), len(v)) if v else (None, 0)
+    if not v:
+        return None, 0
+    top = max(v)
+    v = [x for x in v if x >= 0.5 * top]
+    return sum(v) / len(v), len(v)
 
 
 def traffic(fetch_dir, write_dir, kernel, copy_bytes, out, cmd_fetch=None, cmd_write=None):

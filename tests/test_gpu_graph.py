@@ -64,11 +64,24 @@ def _equal(a, b):
         assert torch.equal(x, y)
 
 
-def test_graph_replay_matches_eager():
+_CASES = {
+    # 12 mixed instances, every MEGB in its chain's workgroup
+    "mixed-12": (lambda: W.config_c3(2, n_inst=12, m_range=(256, 2048), n_range=(6, 24)), 20, 256),
+    # the 512-instance batch (both kinds, N in 6..48, M in 1,024..16,384)
+    "c3-512": (lambda: W.config_c3(0), 20, 512),
+    # instances of 2^17 samples: the multi-workgroup first phase (35 launches
+    # whose buffers alternate between steps) and rescans of the global shell
+    "big-4": (lambda: W.config_c5(1, n_inst=4, n_samples=1 << 17), 20, 1024),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_CASES))
+def test_graph_replay_matches_eager(case):
     import paper_2403_09990_amd as P
-    _log("case: graph replay, 12 mixed instances")
-    b = W.config_c3(2, n_inst=12, m_range=(256, 2048), n_range=(6, 24))
-    gp = P.purse_default_params(n_iters=20, megb_iters=256)
+    _log("case: graph replay,", case)
+    make, iters, T = _CASES[case]
+    b = make()
+    gp = P.purse_default_params(n_iters=iters, megb_iters=T)
     db = P.DeviceBatch(b)
     run = _Run(P, db, gp)
     run()
