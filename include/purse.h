@@ -107,6 +107,11 @@ typedef int32_t purse_status;
 #define PURSE_FLAG_MATRIX_COTANGENT 256 /* purse_megb_backward: g_centre is [n_inst][12], the cotangent of the
                                            centre's entries as purse_megb returns them (R* row-major, then
                                            t*); its rotation part is taken along SO(3) at R* */
+#define PURSE_FLAG_FORWARD_TANGENTS 1024 /* purse_megb_backward: differentiate the 2D-3D trajectories in
+                                           forward mode, one re-run per input direction (6N per active
+                                           sample), instead of one reverse sweep per active sample (the
+                                           default while n_iters * n_gn <= 320); the same derivative to
+                                           float32 rounding */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints

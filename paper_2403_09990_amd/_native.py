@@ -45,6 +45,7 @@ PURSE_FLAG_REPLAY_DESCENT = 64
 PURSE_FLAG_QUAD_LANES = 128
 PURSE_FLAG_MATRIX_COTANGENT = 256
 PURSE_FLAG_EXACT_MEB = 512
+PURSE_FLAG_FORWARD_TANGENTS = 1024
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
             "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",

@@ -1287,6 +1287,686 @@ __global__ void __launch_bounds__(64) k_bwd_traj2d_group(DevBatch b, DevParams p
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse-mode tangent pass of 2D-3D trajectories.  The forward-mode kernels
+// above re-run an active sample's trajectory once per input direction (6N
+// re-runs); the trajectory's derivative is a linear map from the frame and
+// keypoint data to the end pose, so one reverse sweep per active sample gives
+// the cotangent of all of them, and every direction's contribution is then a
+// dot product with that direction's tangent of the frame and of its keypoint.
+// The sweep differentiates the same computation as the forward-mode kernels:
+// the same clamp band, the same frozen decisions (clamp sets, the feasibility
+// and depth tests, the bisection's outcome), float32 throughout.
+//
+// Layout: kRevGroup lanes per active sample (lane q takes keypoints q, q + 16,
+// ...), four samples per wavefront.  A first pass recomputes the trajectory
+// and keeps every Gauss-Newton pass's input pose in LDS (the tape); the
+// reverse pass then walks the passes backwards, recomputing each pass's
+// normal equations from its input pose.  Per pass (x' = Exp(dw) x about the
+// pivot, d = A^-1 g):
+//   d_bar from the update's adjoint; g_bar = A^-1 d_bar (the same factor);
+//   per keypoint and Jacobian row j_r with residual rt_r:
+//     rt_bar_r = g_bar . j_r,  j_bar_r = g_bar (rt_r - d . j_r) - d (g_bar . j_r),
+//   then back through the rows (pt x d_r, d_r), the whitened projection
+//   Jacobian, the residual (the clamp scale s = kappa beta / r when clamped,
+//   the second pass's targets from the iteration's first pose) and the
+//   projection, into the pose, the pivot and the keypoint's data.
+constexpr int kRevGroup = 16;
+constexpr int kRevPerLane = (PURSE_MAX_KP + kRevGroup - 1) / kRevGroup;
+constexpr int kRevSamples = 64 / kRevGroup;  // active samples per wavefront
+constexpr int kRevMaxPasses = 320;            // Gauss-Newton passes the LDS tape holds (61 KB)
+
+struct RevPose {
+  float R[9], t[3];
+};
+
+// Group-summed normal equations of one pass at x (targets from xk for the
+// later passes), as gn_pass2d_group computes them; false on a depth below
+// z_min.
+template <bool FIRST>
+__device__ __forceinline__ bool rev_normal_eqs(const KpRec *__restrict__ kp, int n, int q, const float K[4],
+                                               const float oc[3], float z_min, float band, const RevPose &xk,
+                                               const RevPose &x, float A[21], float g[6]) {
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = 0.f;
+  bool ok = true;
+  for (int i = q; i < n; i += kRevGroup) {
+    const KpRec k = kp[i];
+    float P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    ok = ok && (P[2] > z_min);
+    float rt0, rt1;
+    if (FIRST) {
+      const float e0 = u - k.c[0], e1 = v - k.c[1];
+      const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      const float r2 = et0 * et0 + et1 * et1;
+      const float s = (r2 <= k.kb2 * band) ? 1.f : k.kb * drsqrt(r2);
+      rt0 = (s - 1.f) * et0;
+      rt1 = (s - 1.f) * et1;
+    } else {
+      float Pk[3], izk, uk, vk;
+      project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
+      const float e0 = uk - k.c[0], e1 = vk - k.c[1];
+      const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+      const float r2 = et0 * et0 + et1 * et1;
+      const float s = (r2 <= k.kb2 * band) ? 1.f : k.kb * drsqrt(r2);
+      const float r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
+      rt0 = k.w[0] * r0 + k.w[1] * r1;
+      rt1 = k.w[2] * r1;
+    }
+    const float pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+    gn_accumulate<float>(P, pt, iz, K[0], K[1], k.w, rt0, rt1, A, g);
+  }
+#pragma unroll
+  for (int k = 0; k < 21; ++k) A[k] = group_sum<kRevGroup>(A[k]);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = group_sum<kRevGroup>(g[k]);
+  return group_and<kRevGroup>(ok);
+}
+
+// <E_bar, dExp(w)/dw_k> for k = 0, 1, 2 (the literal exp_so3 differentiated
+// by dual numbers, as the forward-mode kernels do).
+__device__ __forceinline__ void rev_exp_adjoint(const float w[3], const float Eb[9], float wb[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Dual<float> wd[3] = {Dual<float>(w[0], k == 0 ? 1.f : 0.f), Dual<float>(w[1], k == 1 ? 1.f : 0.f),
+                         Dual<float>(w[2], k == 2 ? 1.f : 0.f)};
+    Dual<float> E[9];
+    exp_so3(wd, E);
+    float acc = 0.f;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) acc += Eb[m] * E[m].d;
+    wb[k] = acc;
+  }
+}
+
+// Adjoint of the pose update x' = (E R, E (t - o) + o + dv), E = Exp(dw):
+// from x_bar' to the cotangents of the input pose (uniform part), of o and
+// of the step d = (dw, dv).
+__device__ __forceinline__ void rev_update_adjoint(const float d[6], const float o[3], const RevPose &x,
+                                                   const RevPose &xb_out, RevPose &xb_in, float ob[3],
+                                                   float db[6]) {
+  float E[9];
+  exp_so3(d, E);
+  float Eb[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // R_bar_in = E^T R_bar', t_bar_in = E^T t_bar'
+      xb_in.R[3 * r + c] = E[r] * xb_out.R[c] + E[3 + r] * xb_out.R[3 + c] + E[6 + r] * xb_out.R[6 + c];
+      // E_bar = R_bar' R^T + t_bar' (t - o)^T
+      Eb[3 * r + c] = xb_out.R[3 * r] * x.R[3 * c] + xb_out.R[3 * r + 1] * x.R[3 * c + 1] +
+                      xb_out.R[3 * r + 2] * x.R[3 * c + 2] + xb_out.t[r] * (x.t[c] - o[c]);
+    }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    xb_in.t[r] = E[r] * xb_out.t[0] + E[3 + r] * xb_out.t[1] + E[6 + r] * xb_out.t[2];
+    ob[r] += xb_out.t[r] - xb_in.t[r];
+    db[3 + r] = xb_out.t[r];
+  }
+  rev_exp_adjoint(d, Eb, db);
+}
+
+// Per-keypoint adjoint of one pass: adds this lane's part of the input
+// pose's cotangent (xb), of the iteration's first pose (xkb, later passes),
+// of the pivot (ob) and of its keypoints' data (kb: c0, c1, w0, w1, w2,
+// kappa beta).
+template <bool FIRST>
+__device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int n, int q, const float K[4],
+                                              const float oc[3], float band, const RevPose &xk,
+                                              const RevPose &x, const float d[6], const float gb[6],
+                                              RevPose &xb, RevPose &xkb, float ob[3],
+                                              float kb[kRevPerLane][6]) {
+#pragma unroll
+  for (int rr = 0; rr < kRevPerLane; ++rr) {
+    const int i = q + kRevGroup * rr;
+    if (i >= n) break;
+    const KpRec k = kp[i];
+    const float w0 = k.w[0], w1 = k.w[1], w2 = k.w[2];
+    float P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    // residual (and what its adjoint needs)
+    float rt0, rt1, e0, e1, et0, et1, r2 = 0.f, s = 1.f;
+    bool cl = false;
+    float Pk[3] = {0.f, 0.f, 0.f}, izk = 0.f;
+    if (FIRST) {
+      e0 = u - k.c[0];
+      e1 = v - k.c[1];
+      et0 = w0 * e0 + w1 * e1;
+      et1 = w2 * e1;
+      r2 = et0 * et0 + et1 * et1;
+      cl = !(r2 <= k.kb2 * band);
+      s = cl ? k.kb * drsqrt(r2) : 1.f;
+      rt0 = (s - 1.f) * et0;
+      rt1 = (s - 1.f) * et1;
+    } else {
+      float uk, vk;
+      project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
+      e0 = uk - k.c[0];
+      e1 = vk - k.c[1];
+      et0 = w0 * e0 + w1 * e1;
+      et1 = w2 * e1;
+      r2 = et0 * et0 + et1 * et1;
+      cl = !(r2 <= k.kb2 * band);
+      s = cl ? k.kb * drsqrt(r2) : 1.f;
+      const float r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
+      rt0 = w0 * r0 + w1 * r1;
+      rt1 = w2 * r1;
+      // (r0, r1 are needed below: keep them in e-form)
+      et0 = r0;  // reuse: r0
+      et1 = r1;  // reuse: r1
+    }
+    const float pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+    const float a = K[0] * iz, cc = K[1] * iz, nx = P[0] * iz, ny = P[1] * iz;
+    const float d0[3] = {w0 * a, w1 * cc, -(w0 * a * nx + w1 * cc * ny)};
+    const float d1[3] = {0.f, w2 * cc, -w2 * cc * ny};
+    float j0[6], j1[6];
+    cross3(pt, d0, j0);
+    j0[3] = d0[0];
+    j0[4] = d0[1];
+    j0[5] = d0[2];
+    j1[0] = pt[1] * d1[2] - pt[2] * d1[1];
+    j1[1] = -pt[0] * d1[2];
+    j1[2] = pt[0] * d1[1];
+    j1[3] = 0.f;
+    j1[4] = d1[1];
+    j1[5] = d1[2];
+    float al0 = 0.f, al1 = 0.f, be0 = 0.f, be1 = 0.f;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      al0 += d[m] * j0[m];
+      al1 += d[m] * j1[m];
+      be0 += gb[m] * j0[m];
+      be1 += gb[m] * j1[m];
+    }
+    float jb0[6], jb1[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      jb0[m] = gb[m] * (rt0 - al0) - d[m] * be0;
+      jb1[m] = gb[m] * (rt1 - al1) - d[m] * be1;
+    }
+    // rows (pt x d_r, d_r): d_bar_r = z + y x pt, pt_bar += d_r x y
+    float D0[3], D1[3], ptb[3], tmp[3];
+    cross3(jb0, pt, tmp);
+    D0[0] = jb0[3] + tmp[0];
+    D0[1] = jb0[4] + tmp[1];
+    D0[2] = jb0[5] + tmp[2];
+    cross3(d0, jb0, ptb);
+    cross3(jb1, pt, tmp);
+    D1[1] = jb1[4] + tmp[1];
+    D1[2] = jb1[5] + tmp[2];
+    cross3(d1, jb1, tmp);
+    ptb[0] += tmp[0];
+    ptb[1] += tmp[1];
+    ptb[2] += tmp[2];
+    // back through d0, d1
+    float wb0 = D0[0] * a - D0[2] * a * nx;
+    float wb1 = D0[1] * cc - D0[2] * cc * ny;
+    float wb2 = D1[1] * cc - D1[2] * cc * ny;
+    const float ab = D0[0] * w0 - D0[2] * w0 * nx;
+    const float ccb = D0[1] * w1 - D0[2] * w1 * ny + D1[1] * w2 - D1[2] * w2 * ny;
+    const float nxb = -D0[2] * w0 * a;
+    const float nyb = -D0[2] * w1 * cc - D1[2] * w2 * cc;
+    float izb = ab * K[0] + ccb * K[1] + nxb * P[0] + nyb * P[1];
+    float Pb[3] = {nxb * iz, nyb * iz, 0.f};
+    // residual
+    float ub = 0.f, vb = 0.f, cb0 = 0.f, cb1 = 0.f, kbb = 0.f;
+    if (FIRST) {
+      float etb0 = (s - 1.f) * be0, etb1 = (s - 1.f) * be1;
+      if (cl) {
+        const float sb = be0 * et0 + be1 * et1;
+        kbb += sb * drsqrt(r2);
+        const float r2b = -0.5f * sb * s / r2;
+        etb0 += 2.f * r2b * et0;
+        etb1 += 2.f * r2b * et1;
+      }
+      wb0 += etb0 * e0;
+      wb1 += etb0 * e1;
+      wb2 += etb1 * e1;
+      const float eb0 = etb0 * w0, eb1 = etb0 * w1 + etb1 * w2;
+      ub += eb0;
+      vb += eb1;
+      cb0 -= eb0;
+      cb1 -= eb1;
+    } else {
+      const float r0 = et0, r1 = et1;
+      wb0 += be0 * r0;
+      wb1 += be0 * r1;
+      wb2 += be1 * r1;
+      const float rb0 = be0 * w0, rb1 = be0 * w1 + be1 * w2;
+      cb0 += rb0;
+      cb1 += rb1;
+      ub -= rb0;
+      vb -= rb1;
+      float ekb0 = s * rb0, ekb1 = s * rb1;
+      if (cl) {
+        const float skb = rb0 * e0 + rb1 * e1;
+        kbb += skb * drsqrt(r2);
+        const float r2b = -0.5f * skb * s / r2;
+        const float etk0 = w0 * e0 + w1 * e1, etk1 = w2 * e1;
+        const float etkb0 = 2.f * r2b * etk0, etkb1 = 2.f * r2b * etk1;
+        wb0 += etkb0 * e0;
+        wb1 += etkb0 * e1;
+        wb2 += etkb1 * e1;
+        ekb0 += etkb0 * w0;
+        ekb1 += etkb0 * w1 + etkb1 * w2;
+      }
+      cb0 -= ekb0;
+      cb1 -= ekb1;
+      // projection at the iteration's first pose
+      const float izkb = ekb0 * K[0] * Pk[0] + ekb1 * K[1] * Pk[1];
+      const float Pkb[3] = {ekb0 * K[0] * izk, ekb1 * K[1] * izk, -izkb * izk * izk};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        xkb.R[3 * r] += Pkb[r] * k.m[0];
+        xkb.R[3 * r + 1] += Pkb[r] * k.m[1];
+        xkb.R[3 * r + 2] += Pkb[r] * k.m[2];
+        xkb.t[r] += Pkb[r];
+      }
+    }
+    // projection at x, pt = P - o, iz = 1 / P.z, P = R m + t
+    Pb[0] += ub * K[0] * iz;
+    Pb[1] += vb * K[1] * iz;
+    izb += ub * K[0] * P[0] + vb * K[1] * P[1];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Pb[r] += ptb[r];
+      ob[r] -= ptb[r];
+    }
+    Pb[2] += -izb * iz * iz;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      xb.R[3 * r] += Pb[r] * k.m[0];
+      xb.R[3 * r + 1] += Pb[r] * k.m[1];
+      xb.R[3 * r + 2] += Pb[r] * k.m[2];
+      xb.t[r] += Pb[r];
+    }
+    kb[rr][0] += cb0;
+    kb[rr][1] += cb1;
+    kb[rr][2] += wb0;
+    kb[rr][3] += wb1;
+    kb[rr][4] += wb2;
+    kb[rr][5] += kbb;
+  }
+}
+
+// One pass of the reverse sweep: the normal equations at x recomputed, the
+// update's and the solve's adjoints, the keypoints' adjoints; xb holds the
+// cotangent of the pass's output on entry and of its input on return.
+template <bool FIRST>
+__device__ __forceinline__ void rev_pass(const KpRec *__restrict__ kp, int n, int q, const float K[4],
+                                         const float oc[3], float z_min, float band, const RevPose &xk,
+                                         const RevPose &x, RevPose &xb, RevPose &xkb, float ob_u[3],
+                                         float ob_k[3], float kb[kRevPerLane][6]) {
+  float A[21], g[6], L[21], dinv[6], d[6];
+  rev_normal_eqs<FIRST>(kp, n, q, K, oc, z_min, band, xk, x, A, g);
+  chol6_factor<float>(A, L, dinv);
+  chol6_subst<float>(L, dinv, g, d);
+  RevPose xin;
+  float db[6];
+  rev_update_adjoint(d, oc, x, xb, xin, ob_u, db);
+  float gb[6];
+  chol6_subst<float>(L, dinv, db, gb);
+  RevPose part;
+#pragma unroll
+  for (int m = 0; m < 9; ++m) part.R[m] = 0.f;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) part.t[m] = 0.f;
+  rev_keypoints<FIRST>(kp, n, q, K, oc, band, xk, x, d, gb, part, xkb, ob_k, kb);
+  if (FIRST) {
+    // the pass's input is the iteration's first pose: the later passes' parts join here
+#pragma unroll
+    for (int m = 0; m < 9; ++m) part.R[m] += xkb.R[m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) part.t[m] += xkb.t[m];
+  }
+#pragma unroll
+  for (int m = 0; m < 9; ++m) xb.R[m] = xin.R[m] + group_sum<kRevGroup>(part.R[m]);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) xb.t[m] = xin.t[m] + group_sum<kRevGroup>(part.t[m]);
+}
+
+// Adjoint of R_r = R (3 I - R^T R) / 2.
+__device__ __forceinline__ void rev_reorthonormalise(const float R[9], float Rb[9]) {
+  float S[9], F[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) F[m] = Rb[m];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[3 * r + c] = -(R[r] * R[c] + R[3 + r] * R[3 + c] + R[6 + r] * R[6 + c]);
+  S[0] += 3.f;
+  S[4] += 3.f;
+  S[8] += 3.f;
+  // R_bar = (F S - R F^T R - R R^T F) / 2
+  float FS[9], RFt[9], RFtR[9], RRt[9], RRtF[9];
+  matmul3(F, S, FS);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      RFt[3 * r + c] = R[3 * r] * F[3 * c] + R[3 * r + 1] * F[3 * c + 1] + R[3 * r + 2] * F[3 * c + 2];
+      RRt[3 * r + c] = R[3 * r] * R[3 * c] + R[3 * r + 1] * R[3 * c + 1] + R[3 * r + 2] * R[3 * c + 2];
+    }
+  matmul3(RFt, R, RFtR);
+  matmul3(RRt, F, RRtF);
+#pragma unroll
+  for (int m = 0; m < 9; ++m) Rb[m] = 0.5f * (FS[m] - RFtR[m] - RRtF[m]);
+}
+
+// Adjoint of w = log_so3(Q) (the literal formula, differentiated by dual
+// numbers one entry of Q at a time): Q_bar from w_bar.
+__device__ __forceinline__ void rev_log_adjoint(const float Q[9], const float wb[3], float Qb[9]) {
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    Dual<float> Qd[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Qd[k] = Dual<float>(Q[k], k == m ? 1.f : 0.f);
+    Dual<float> w[3];
+    log_so3(Qd, w);
+    Qb[m] = wb[0] * w[0].d + wb[1] * w[1].d + wb[2] * w[2].d;
+  }
+}
+
+__device__ __forceinline__ void rev_items_at(const int64_t *__restrict__ off, int n, int64_t it, int &j, int &a) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  j = lo;
+  a = (int)(it - off[j]);
+}
+
+// Work items of the reverse kernel: one per active sample of every 2D-3D
+// instance the backward differentiates (prefix sums, n + 1 entries).
+__global__ void __launch_bounds__(1024) k_bwd_items_rev(DevBatch b, const InstRec *__restrict__ inst,
+                                                        const BwdRec *recs, int64_t *__restrict__ item_off) {
+  __shared__ int64_t part[1024];
+  const int n = b.n_inst, tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int j0 = tid * per, j1 = min(n, j0 + per);
+  auto items_of = [&](int j) -> int64_t {
+    const BwdRec &r = recs[j];
+    const InstRec I = inst[j];
+    if (r.status != kBwdOk || I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK ||
+        !inst_record_ok(I, inst_view(b, j)))
+      return 0;
+    return (int64_t)min(max(r.n_act, 0), kMaxActive);
+  };
+  int64_t acc = 0;
+  for (int j = j0; j < j1; ++j) acc += items_of(j);
+  part[tid] = acc;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = tid ? part[tid - 1] : 0;
+  for (int j = j0; j < j1; ++j) {
+    item_off[j] = run;
+    run += items_of(j);
+  }
+  if (tid == 1023) item_off[n] = part[1023];
+}
+
+// The sampler's feasibility test (float, group-combined).
+__device__ __forceinline__ bool rev_feasible(const KpRec *__restrict__ kp, int n, int q, const float K[4],
+                                             const RevPose &x, float z_min) {
+  bool ok = true;
+  for (int i = q; i < n; i += kRevGroup) {
+    const KpRec k = kp[i];
+    float P[3], iz, u, v;
+    project2d(x.R, x.t, k, K, P, iz, u, v);
+    const float e0 = u - k.c[0], e1 = v - k.c[1];
+    const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
+    const float rr = sqrtf(et0 * et0 + et1 * et1);
+    ok = ok && (P[2] > z_min) && (rr <= k.bt);
+  }
+  return group_and<kRevGroup>(ok);
+}
+
+// One wavefront per kRevSamples active samples; dynamic LDS: the tape,
+// kRevSamples x n_iters x n_gn poses of 12 floats.
+__global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
+                                                  const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                  const int64_t *__restrict__ item_off,
+                                                  const float *__restrict__ tan_all, float *contrib, int max_dirs) {
+  extern __shared__ float tape_all[];
+  const int64_t total = item_off[b.n_inst];
+  const int lane = threadIdx.x, grp = lane / kRevGroup, q = lane % kRevGroup;
+  const int passes = p.n_iters * p.n_gn;
+  float *tape = tape_all + (int64_t)grp * passes * 12;
+  const float band = ClampBand<Dual<float>>::v;
+  for (int64_t wv = blockIdx.x; wv * kRevSamples < total; wv += gridDim.x) {
+    const int64_t it = wv * kRevSamples + grp;
+    const bool live = it < total;
+    int j = 0, a = 0;
+    if (live) rev_items_at(item_off, b.n_inst, it, j, a);
+    const InstRec I = inst[j];
+    const BwdRec *rec = recs + j;
+    const KpRec *kp = kprec + I.kp_off;
+    const int n = live ? I.n_kp : 0;
+    const float oc[3] = {I.oc[0], I.oc[1], I.oc[2]};
+    const int s = live ? rec->active[a] : 0;
+    // ---------------------------------------------------------- forward
+    RevPose x;
+    {
+      const PoseT<float> x0 = initial_pose<float>(frame_ref(I), I.seed, (uint64_t)s, p);
+#pragma unroll
+      for (int m = 0; m < 9; ++m) x.R[m] = x0.R[m];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) x.t[m] = x0.t[m];
+    }
+    bool ok = live;
+    for (int itr = 0; itr < p.n_iters && ok; ++itr) {
+      const RevPose xk = x;
+      for (int gs = 0; gs < p.n_gn && ok; ++gs) {
+        const int ps = itr * p.n_gn + gs;
+        if (q < 12) tape[12 * ps + q] = q < 9 ? x.R[q] : x.t[q - 9];
+        float A[21], g[6], L[21], dinv[6], d[6];
+        ok = gs == 0 ? rev_normal_eqs<true>(kp, n, q, I.K, oc, p.z_min, band, xk, x, A, g)
+                     : rev_normal_eqs<false>(kp, n, q, I.K, oc, p.z_min, band, xk, x, A, g);
+        ok = ok && chol6_factor<float>(A, L, dinv);
+        if (ok) {
+          chol6_subst<float>(L, dinv, g, d);
+          apply_update<float>(d, oc, x.R, x.t);
+        }
+      }
+    }
+    const RevPose xe = x;  // before the final reorthonormalisation
+    reorthonormalise(x.R);
+    uint8_t mask = 0;
+    float lo = 1.f, w[3] = {0.f, 0.f, 0.f};
+    if (ok) {
+      if (rev_feasible(kp, n, q, I.K, x, p.z_min)) {
+        mask = PURSE_MASK_FEASIBLE;
+      } else if (I.has_anchor) {
+        float RaT[9], Q[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) RaT[3 * r + c] = I.Ra[3 * c + r];
+        matmul3(RaT, x.R, Q);
+        log_so3(Q, w);
+        lo = 0.f;
+        float hi = 1.f;
+        for (int bb = 0; bb < p.n_bis; ++bb) {
+          const float mid = 0.5f * (lo + hi);
+          const float wm[3] = {mid * w[0], mid * w[1], mid * w[2]};
+          float E[9];
+          RevPose mp;
+          exp_so3(wm, E);
+          matmul3(I.Ra, E, mp.R);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) mp.t[r] = I.ta[r] + mid * (x.t[r] - I.ta[r]);
+          if (rev_feasible(kp, n, q, I.K, mp, p.z_min))
+            lo = mid;
+          else
+            hi = mid;
+        }
+        mask = PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
+      }
+    }
+    __syncthreads();  // the tape is complete
+    // ---------------------------------------------------------- reverse
+    float Rcb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tcb[3] = {0.f, 0.f, 0.f};
+    float Rab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tab[3] = {0.f, 0.f, 0.f};
+    float ob_u[3] = {0.f, 0.f, 0.f}, ob_k[3] = {0.f, 0.f, 0.f};
+    float kb[kRevPerLane][6];
+#pragma unroll
+    for (int rr = 0; rr < kRevPerLane; ++rr)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) kb[rr][m] = 0.f;
+    if (mask & PURSE_MASK_FEASIBLE) {
+      float cR[9], ct[3];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) cR[m] = (float)rec->cot[a][m];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) ct[m] = (float)rec->cot[a][9 + m];
+      RevPose xb;
+      if (!(mask & PURSE_MASK_PULLED_IN)) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) xb.R[m] = cR[m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xb.t[m] = ct[m];
+      } else if (lo == 0.f) {
+        // the anchor itself
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          Rab[m] += cR[m];
+          xb.R[m] = 0.f;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          tab[m] += ct[m];
+          xb.t[m] = 0.f;
+        }
+      } else {
+        // out = (Ra Exp(lo w), ta + lo (t - ta)), w = Log(Ra^T R)
+        const float phi[3] = {lo * w[0], lo * w[1], lo * w[2]};
+        float E[9], Eb[9], phib[3], Qb[9], RaT[9], Q[9];
+        exp_so3(phi, E);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Rab[3 * r + c] += cR[3 * r] * E[3 * c] + cR[3 * r + 1] * E[3 * c + 1] + cR[3 * r + 2] * E[3 * c + 2];
+            Eb[3 * r + c] = I.Ra[r] * cR[c] + I.Ra[3 + r] * cR[3 + c] + I.Ra[6 + r] * cR[6 + c];
+            RaT[3 * r + c] = I.Ra[3 * c + r];
+          }
+        rev_exp_adjoint(phi, Eb, phib);
+        const float wb[3] = {lo * phib[0], lo * phib[1], lo * phib[2]};
+        matmul3(RaT, x.R, Q);
+        rev_log_adjoint(Q, wb, Qb);
+        // Q = Ra^T R: R_bar = Ra Q_bar, Ra_bar += R Q_bar^T
+        matmul3(I.Ra, Qb, xb.R);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Rab[3 * r + c] += x.R[3 * r] * Qb[3 * c] + x.R[3 * r + 1] * Qb[3 * c + 1] + x.R[3 * r + 2] * Qb[3 * c + 2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          xb.t[m] = lo * ct[m];
+          tab[m] += (1.f - lo) * ct[m];
+        }
+      }
+      rev_reorthonormalise(xe.R, xb.R);
+      for (int itr = p.n_iters - 1; itr >= 0; --itr) {
+        RevPose xk, xkb;
+        const float *tk = tape + 12 * (itr * p.n_gn);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          xk.R[m] = tk[m];
+          xkb.R[m] = 0.f;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          xk.t[m] = tk[9 + m];
+          xkb.t[m] = 0.f;
+        }
+        for (int gs = p.n_gn - 1; gs >= 1; --gs) {
+          const float *tx = tape + 12 * (itr * p.n_gn + gs);
+          RevPose xin;
+#pragma unroll
+          for (int m = 0; m < 9; ++m) xin.R[m] = tx[m];
+#pragma unroll
+          for (int m = 0; m < 3; ++m) xin.t[m] = tx[9 + m];
+          rev_pass<false>(kp, n, q, I.K, oc, p.z_min, band, xk, xin, xb, xkb, ob_u, ob_k, kb);
+        }
+        rev_pass<true>(kp, n, q, I.K, oc, p.z_min, band, xk, xk, xb, xkb, ob_u, ob_k, kb);
+      }
+      // the start: even s rotate the centre by E about the pivot, odd s shift it
+      if ((s & 1) == 0) {
+        float dd[3];
+        trajectory_direction(I.seed, (uint64_t)s, dd);
+        const float w0[3] = {p.omega0 * dd[0], p.omega0 * dd[1], p.omega0 * dd[2]};
+        float E[9];
+        exp_so3(w0, E);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Rcb[3 * r + c] += E[r] * xb.R[c] + E[3 + r] * xb.R[3 + c] + E[6 + r] * xb.R[6 + c];
+          const float et = E[r] * xb.t[0] + E[3 + r] * xb.t[1] + E[6 + r] * xb.t[2];
+          tcb[r] += et;
+          ob_u[r] += xb.t[r] - et;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Rcb[m] += xb.R[m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) tcb[m] += xb.t[m];
+      }
+    }
+    float fb[27];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      fb[m] = Rcb[m];
+      fb[15 + m] = Rab[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      fb[9 + m] = tcb[m];
+      fb[12 + m] = ob_u[m] + group_sum<kRevGroup>(ob_k[m]);
+      fb[24 + m] = tab[m];
+    }
+    // ---------------------------------------------------- contributions
+    if (live) {
+      const bool feas = (mask & PURSE_MASK_FEASIBLE) != 0;
+#pragma unroll
+      for (int rr = 0; rr < kRevPerLane; ++rr) {
+        const int i = q + kRevGroup * rr;
+        if (i >= n) break;
+        for (int c = 0; c < 6; ++c) {
+          const int d = 6 * i + c;
+          float acc = 0.f;
+          if (feas) {
+            KpT<Dual<float>> tk;
+            kp_tangent(I, kp[i], b.shapes + 4 * (I.kp_off + i), b.bounds[I.kp_off + i], p.kappa, c, tk);
+            acc = kb[rr][0] * tk.c[0].d + kb[rr][1] * tk.c[1].d + kb[rr][2] * tk.w[0].d + kb[rr][3] * tk.w[1].d +
+                  kb[rr][4] * tk.w[2].d + kb[rr][5] * tk.kb.d;
+            const float *tn = tan_all + ((int64_t)j * max_dirs + d) * 27;
+#pragma unroll
+            for (int m = 0; m < 27; ++m) acc += fb[m] * tn[m];
+          }
+          contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = acc;
+        }
+      }
+    }
+    __syncthreads();  // (the next samples' forward rewrites the tape)
+  }
+}
+
 // Sum over active samples (fixed order) and scatter into the gradients.
 __global__ void __launch_bounds__(kMaxDirs) k_bwd_reduce(DevBatch b, const InstRec *__restrict__ inst,
                                                         const BwdRec *recs, const float *__restrict__ contrib,
@@ -1406,12 +2086,23 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
   }
   // the tangent kernels walk lists of the (instance, active sample,
   // direction block) items the active sets need
-  hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_2D3D, kTrajGroup,
-                     items);
+  // 2D-3D: one reverse sweep per active sample while the tape fits in LDS,
+  // else (or when asked) one forward-mode re-run per input direction
+  const int passes = p.n_iters * p.n_gn;
+  const bool reverse = passes <= kRevMaxPasses && !(p.flags & PURSE_FLAG_FORWARD_TANGENTS);
+  if (reverse) {
+    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, stream, b, inst, recs, items);
+    const size_t lds = sizeof(float) * 12 * (size_t)kRevSamples * (size_t)(passes > 0 ? passes : 1);
+    hipLaunchKernelGGL(k_bwd_rev2d, dim3(kItemGrid), dim3(64), lds, stream, b, p, inst, kp, recs, items, tan,
+                       contrib, max_dirs);
+  } else {
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_2D3D, kTrajGroup,
+                       items);
+    hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
+                       items, tan, contrib, max_dirs);
+  }
   hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
                      items + (n + 1));
-  hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
-                     items, tan, contrib, max_dirs);
   hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
                      items + (n + 1), tan, contrib, max_dirs);
   hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
