@@ -42,8 +42,8 @@ static_assert(sizeof(InstRec) == 192, "InstRec layout");
 struct MegbRec {
   int32_t first;          // first feasible instance-local index (INT32_MAX if none)
   int32_t n_rescan[2];    // diagnostics: rescans per chain
-  int32_t n_global[2];    // diagnostics: full-scan stages per chain
-  int32_t pad;
+  int32_t n_global[2];    // diagnostics: full-scan stages per chain (low 16 bits), global shells rebuilt (high 16)
+  int32_t n_piped;        // diagnostics: rotation steps taken in pipelined segments
   unsigned long long n_feasible;
   unsigned long long max_rot;    // float64 bit pattern of max ||R* - R_s||_F^2
   unsigned long long max_trans;  // float64 bit pattern of max ||t* - t_s||^2
@@ -59,7 +59,9 @@ struct MegbRec {
   // the trace whose signature is ck_hash (ck_T = 0: none)
   unsigned long long ck_hash;
   int32_t ck_T, ck_every;
-  int32_t pad2[4];
+  int32_t chain_us[2];    // diagnostics: each chain's workgroup time (device real-time clock, us)
+  int32_t n_pipe_fail;    // diagnostics: rotation pipelined segments ended by a failed prediction
+  int32_t n_pipe_seg;     // diagnostics: rotation pipelined segments
 };
 static_assert(sizeof(MegbRec) == 192, "MegbRec layout");
 

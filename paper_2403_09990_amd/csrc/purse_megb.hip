@@ -39,9 +39,9 @@ constexpr int kChainWaves = kChainBlock / 64;
 template <bool PIPE>
 constexpr int chain_block() { return PIPE ? kChainBlock : 256; }
 template <bool PIPE>
-constexpr int chain_cap() { return PIPE ? 3072 : 1536; }
+constexpr int chain_cap() { return PIPE ? 7168 : 1536; }
 constexpr int kUnroll = 8;
-constexpr int kCap = 3072;
+constexpr int kCap = 7168;
 constexpr int kMaxChunks = kCap / 64;
 constexpr int kRecentreChunks = 4;  // a step scanning more chunks than this ...
 constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
@@ -529,6 +529,18 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
   }
 }
 
+// A chain's global shell (the state only rescans read) and its diagnostics.
+struct ChainGs {
+  int n, built_at, n_built;
+  float theta;
+  float4 C;
+};
+struct ChainDiag {
+  int n_rescan, n_global, n_seg, n_piped, n_fail;
+  long long n_groups;
+  uint64_t t_start;
+};
+
 // Shared state of one chain's workgroup.
 struct ChainShared {
   float4 *pt;             // shell points, [cap]
@@ -545,7 +557,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                                           int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
                                           float *dref_all, int64_t total_samples, int32_t *trace,
                                           float4 *ckpt_all, int ck, int T, int avg, int cap, int no_prune,
-                                          const int32_t *__restrict__ gid_all, const float4 *__restrict__ gpt_all,
+                                          int32_t *__restrict__ gid_all, float4 *__restrict__ gpt_all,
                                           int64_t gstride) {
   __shared__ float4 st_C;
   __shared__ int st_i;
@@ -589,23 +601,33 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   // outside it lie within gs_theta + d(C, C_g) of any centre C, so rescans
   // stream the shell alone while that bound stays below the farthest member.
   const bool ep = early_phase_applies(M64, T, avg, no_prune) && n_feas > cap;
-  const int gs_n = ep ? rec[j].gs_n[chain] : -1;
-  const float gs_theta = ep ? rec[j].gs_theta[chain] : -1.f;
-  const float4 Cg = rec[j].early_c[chain];
-  const int32_t *gid = gid_all + chain * gstride + off / kShellDiv;
-  const float4 *gpt = gpt_all + chain * gstride + off / kShellDiv;
-  bool use_gs = gs_n > 0;
+  int32_t *gid = gid_all + chain * gstride + off / kShellDiv;
+  float4 *gpt = gpt_all + chain * gstride + off / kShellDiv;
+  // A global shell that no longer certifies any step (the centre has moved
+  // too far from C_g) is rebuilt around the centre of the next full rescan,
+  // from the distances that rescan computes, at most once per kMinShellSteps
+  // steps.  Its state, which only rescans read, and the diagnostics live in
+  // LDS (thread 0 writes them between barriers), so that the stepping loops
+  // keep their registers.
+  const int gs_cap = M / kShellDiv;
+  __shared__ ChainGs sg;
+  __shared__ ChainDiag sdg;
   if (tid == 0) {
-    st_C = ep ? Cg : D[first];
+    st_C = ep ? rec[j].early_c[chain] : D[first];
     st_i = ep ? kEarlySteps + 1 : 1;
+    sg.n = ep ? rec[j].gs_n[chain] : -1;
+    sg.theta = ep ? rec[j].gs_theta[chain] : -1.f;
+    sg.C = rec[j].early_c[chain];
+    sg.built_at = ep ? -kMinShellSteps : INT32_MAX;
+    sg.n_built = 0;
+    sdg = ChainDiag{0, 0, 0, 0, 0, 0ll, __builtin_amdgcn_s_memrealtime()};
   }
   __syncthreads();
+  bool use_gs = sg.n > 0;
   float acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.f;
   bool stalled = false;
-  int n_rescan = 0, n_global = 0;
-  long long n_groups = 0;
   int stage_groups = 0;
 
   while (true) {
@@ -616,11 +638,12 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
     const bool global = (no_prune || stalled || early) && n_feas > cap;
     if (!global) {
       // -------------------------------------------------------------- rescan
-      ++n_rescan;
+      if (tid == 0) ++sdg.n_rescan;
       // entries: the global shell's or every sample
-      const float4 *src = use_gs ? gpt : D;
-      const int n_src = use_gs ? gs_n : M;
-      const int n_src_feas = use_gs ? gs_n : n_feas;
+      const bool from_gs = use_gs;  // (a rebuild below does not change this rescan's source)
+      const float4 *src = from_gs ? gpt : D;
+      const int n_src = from_gs ? sg.n : M;
+      const int n_src_feas = from_gs ? sg.n : n_feas;
       float mx = 0.f;
       stream_rounds<BLK>(src, n_src, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
@@ -642,10 +665,67 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       float rref = 0.f;
 #pragma unroll
       for (int k = 0; k < NW; ++k) rref = fmaxf(rref, S.red_k[0][k]);
+      // (the sequential variant, which runs batches of more chains than
+      // compute units, keeps its registers for four chains per compute unit
+      // and leaves a stale global shell to full rescans)
+      if (PIPE && ep && !use_gs && i0 - sg.built_at >= kMinShellSteps) {
+        // ---------------------------------- rebuild the global shell at C_ref
+        const float gw = rref / (float)kShellBins;
+        if (gw > 0.f) {
+          const float grw = 1.f / gw;
+          for (int k = tid; k < kBins; k += BLK) S.hist[k] = 0u;
+          __syncthreads();
+          // (a short unroll: the rebuild is rare, and its registers would
+          // otherwise be taken from the stepping loops)
+          stream_rounds<BLK, kUnroll>(dref, M, -1.f, [&](const float *dd, int) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+              if (dd[u] >= 0.f) atomicAdd(&S.hist[bin_of(dd[u], 0.f, grw)], 1u);
+          });
+          __syncthreads();
+          if (tid == 0) {
+            int cum = 0, bb = kShellBins - 1;
+            for (; bb >= 0; --bb) {
+              if (cum + (int)S.hist[bb] > gs_cap) break;
+              cum += (int)S.hist[bb];
+            }
+            st_bstar = bb == kShellBins - 1 ? -1 : bb + 1;  // -1: the top bin alone is too large
+            sh_n = 0u;
+            if (st_bstar < 0) sg.n = -1;
+          }
+          __syncthreads();
+          const int gb = st_bstar;
+          if (gb >= 0) {
+            stream_rounds<BLK, kUnroll>(dref, M, -1.f, [&](const float *dd, int s0) {
+#pragma unroll
+              for (int u = 0; u < kUnroll; ++u) {
+                const int s = s0 + u * BLK + tid;
+                if (dd[u] >= 0.f && bin_of(dd[u], 0.f, grw) >= gb) {
+                  const unsigned int pos = atomicAdd(&sh_n, 1u);
+                  if (pos < (unsigned)gs_cap) {
+                    gid[pos] = s;
+                    gpt[pos] = D[s];
+                  }
+                }
+              }
+            });
+            __syncthreads();
+            if (tid == 0) {
+              sg.n = min((int)sh_n, gs_cap);
+              sg.theta = gb == 0 ? -1.f : (float)gb * gw;
+              sg.C = Cref;
+              ++sg.n_built;
+            }
+          }
+        }
+        if (tid == 0) sg.built_at = i0;
+        __syncthreads();
+        use_gs = sg.n > 0;
+      }
       // bound of every sample outside the global shell
       float theta_out = -1.f;
-      if (use_gs && gs_theta >= 0.f) {
-        theta_out = gs_theta + __builtin_amdgcn_sqrtf(sqdist(Cref, Cg, chain));
+      if (from_gs && sg.theta >= 0.f) {
+        theta_out = sg.theta + __builtin_amdgcn_sqrtf(sqdist(Cref, sg.C, chain));
         if (!(theta_out < rref)) {
           // the shell can no longer certify a step: rescan every sample
           use_gs = false;
@@ -654,12 +734,17 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         }
       }
       // Shell membership: d >= theta and (coarse) bin >= bstar of the
-      // histogram (lo, w); theta = -1 when every feasible sample fits.
+      // histogram (lo, w); theta = -1 when every feasible sample fits.  The
+      // global shell's entries lie at least gs_theta - d(C_ref, C_g) from
+      // C_ref, so its histogram starts there (spread over all the bins, not
+      // piled into the top few); an entry rounded below lo is within
+      // theta_out, which the stage's bound includes.
       if (tid == 0) {
+        const float lo0 = from_gs && theta_out >= 0.f ? fmaxf(0.f, 2.f * sg.theta - theta_out - 1e-5f * rref) : 0.f;
         st_mode = 0;
         st_theta = -1.f;
-        st_lo = 0.f;
-        st_w = rref / (float)kBins;
+        st_lo = lo0;
+        st_w = (rref - lo0) / (float)kBins;
         st_bstar = 0;
         st_rref = rref;
       }
@@ -706,7 +791,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
         }
       }
       // samples outside the global shell are bounded by theta_out
-      if (use_gs && tid == 0 && st_mode == 0) st_theta = fmaxf(st_theta, theta_out);
+      if (from_gs && tid == 0 && st_mode == 0) st_theta = fmaxf(st_theta, theta_out);
       __syncthreads();
       // ---------------- collect, ordered by fine bins over [max(theta,0), rref]
       if (st_mode == 0) {
@@ -754,7 +839,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           });
           __syncthreads();
           // (global shell: the entry index becomes the sample id)
-          if (use_gs) {
+          if (from_gs) {
             for (int e = tid; e < (int)sh_n; e += BLK) {
               const int x = S.id[e];
               S.pt[e] = gpt[x];
@@ -787,7 +872,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       float4 C = Cref;
       int i = i0;
       int par = 0;
-      ++n_global;
+      if (tid == 0) ++sdg.n_global;
       const int i_end = no_prune ? T : (early ? min(T, kEarlySteps) : min(T, i0 + kGlobalSteps - 1));
       while (i <= i_end) {
         float bk = -1.f;
@@ -1045,7 +1130,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           run_range(std::true_type(), std::false_type(), last_plain);
           run_range(std::true_type(), std::true_type(), T);
           if (lane < i - ib) tr[2 * (ib - 1 + lane)] = trv;
-          n_groups += stage_groups;
+          if (lane == 0) sdg.n_groups += stage_groups;
           stage_groups = 0;
           if (lane == 0) {
             st_C = C;
@@ -1230,6 +1315,11 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
             }
           }
         }
+        if (tid == 0) {
+          ++sdg.n_seg;
+          sdg.n_piped += (fail_step == INT32_MAX ? pend + 1 : fail_step) - pi0;
+          sdg.n_fail += fail_step == INT32_MAX ? 0 : 1;
+        }
         if (fail_step == INT32_MAX) {
           C = pl_Cend;
           i = pend + 1;
@@ -1251,9 +1341,16 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   }
   // ------------------------------------------------------------------ centre
   if (tid == 0) {
-    rec[j].n_rescan[chain] = n_rescan;
-    rec[j].n_global[chain] = n_global;
-    rec[j].n_groups[chain] = n_groups;
+    rec[j].n_rescan[chain] = sdg.n_rescan;
+    rec[j].n_global[chain] = sdg.n_global | (sg.n_built << 16);
+    rec[j].n_groups[chain] = sdg.n_groups;
+    // (the real-time clock runs at 100 MHz)
+    rec[j].chain_us[chain] = (int32_t)((__builtin_amdgcn_s_memrealtime() - sdg.t_start) / 100ull);
+    if (chain == 0) {
+      rec[j].n_piped = sdg.n_piped;
+      rec[j].n_pipe_fail = sdg.n_fail;
+      rec[j].n_pipe_seg = sdg.n_seg;
+    }
     if (chain == 0) {
       double Md[9], Rd[9];
 #pragma unroll
@@ -1280,8 +1377,8 @@ __global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chai
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
                                                             int32_t *trace, float4 *ckpt, int ck, int T, int avg,
-                                                            int cap, int no_prune, const int32_t *gid,
-                                                            const float4 *gpt, int64_t gstride) {
+                                                            int cap, int no_prune, int32_t *gid,
+                                                            float4 *gpt, int64_t gstride) {
   extern __shared__ float4 sh_pt[];
   __shared__ unsigned int hist[kBins];
   __shared__ unsigned int cursor[kBins];
