@@ -275,7 +275,8 @@ def main():
     ms_sample = time_events(do_sample, args.roofline_reps, stream)
     ms_megb = time_events(do_megb, args.roofline_reps, stream)
     ms_bwd = None if args.no_backward else time_events(do_backward, args.roofline_reps, stream)
-    gp_reuse = P.purse_default_params(n_iters=cfg["iters"], tile=gp.tile, flags=gp.flags | P.PURSE_FLAG_REUSE_PROLOGUE)
+    gp_reuse = P.purse_default_params(n_iters=cfg["iters"], tile=gp.tile, flags=gp.flags | P.PURSE_FLAG_REUSE_PROLOGUE,
+                                      waves_per_simd=gp.waves_per_simd)
     ms_traj = time_events(lambda: do_sample(gp_reuse), args.roofline_reps, stream)
     torch.cuda.synchronize()
     m = mask.cpu().numpy()

@@ -107,6 +107,10 @@ typedef int32_t purse_status;
 #define PURSE_FLAG_MATRIX_COTANGENT 256 /* purse_megb_backward: g_centre is [n_inst][12], the cotangent of the
                                            centre's entries as purse_megb returns them (R* row-major, then
                                            t*); its rotation part is taken along SO(3) at R* */
+#define PURSE_FLAG_WORK_QUEUE 2048 /* purse_sample: persistent trajectory kernels, about eight
+                                     wavefronts per SIMD, each workgroup taking its next tile of the
+                                     heaviest-first schedule from an atomic counter until none is left
+                                     (the same samples; speed only) */
 #define PURSE_FLAG_FORWARD_TANGENTS 1024 /* purse_megb_backward: differentiate the 2D-3D trajectories in
                                            forward mode, one re-run per input direction (6N per active
                                            sample), instead of one reverse sweep per active sample (the
@@ -154,6 +158,9 @@ typedef struct purse_params {
                           1e-13 (1 + |t|_inf) (translation, m) */
   int32_t tile;        /* samples per workgroup: 64, 128 or 256; 0 = library choice (256) */
   int32_t flags;       /* PURSE_FLAG_* */
+  int32_t waves_per_simd; /* purse_sample: cap on the trajectory kernels' resident wavefronts per SIMD
+                             (1..8, by padding each workgroup's LDS within the per-workgroup limit; the
+                             allocation granularity can leave a workgroup fewer); 0 = no cap.  Speed only */
 } purse_params;
 
 /* Fill *p with the defaults: n_iters 50, n_gn 2, n_bis 16, megb_iters 4096,

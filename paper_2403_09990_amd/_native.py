@@ -46,6 +46,7 @@ PURSE_FLAG_QUAD_LANES = 128
 PURSE_FLAG_MATRIX_COTANGENT = 256
 PURSE_FLAG_EXACT_MEB = 512
 PURSE_FLAG_FORWARD_TANGENTS = 1024
+PURSE_FLAG_WORK_QUEUE = 2048
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
             "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",
@@ -89,6 +90,7 @@ class PurseParams(ctypes.Structure):
         ("centre_gn", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("waves_per_simd", ctypes.c_int32),
     ]
 
 

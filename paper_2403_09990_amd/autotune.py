@@ -6,7 +6,10 @@ first, or instance order with PURSE_FLAG_INSTANCE_ORDER) and, for 2D-3D
 instances of at most 16 keypoints, the keypoint loop (unrolled; the general
 one with PURSE_FLAG_GENERIC_LOOP; two or four lanes per trajectory with
 PURSE_FLAG_PAIR_LANES or PURSE_FLAG_QUAD_LANES) change its speed; the last
-three change float32 rounding only.
+three change float32 rounding only.  A second stage tries, on the fastest of
+those, the persistent work-queue kernels (PURSE_FLAG_WORK_QUEUE) and caps of
+4 and 2 resident wavefronts per SIMD (params.waves_per_simd), which change
+speed only.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -18,13 +21,16 @@ import os
 from typing import Optional
 
 from . import (PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES,
-               purse_default_params, purse_sample)
+               PURSE_FLAG_WORK_QUEUE, purse_default_params, purse_sample)
 
 TILES = (64, 128, 256)
 ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
 LOOPS = (0, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES)
 SMALL_N = 16
-_TUNED = PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES | PURSE_FLAG_QUAD_LANES
+_TUNED = (PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES | PURSE_FLAG_QUAD_LANES |
+          PURSE_FLAG_WORK_QUEUE)
+# second stage, on the fastest tile / order / loop: (flags, waves per SIMD)
+STAGE2 = ((PURSE_FLAG_WORK_QUEUE, 0), (0, 4), (0, 2))
 
 
 def default_cache_path() -> str:
@@ -67,20 +73,26 @@ def _store(path, table):
         pass
 
 
-def _with(params, tile, flags):
+def _with(params, tile, flags, waves=0):
     p = purse_default_params()
     for name, _ in type(params)._fields_:
         setattr(p, name, getattr(params, name))
     p.tile = tile
     p.flags = (params.flags & ~_TUNED) | flags
+    p.waves_per_simd = waves
     return p
 
 
-def _name(tile, flags):
+def _name(tile, flags, waves=0):
     loop = ("generic" if flags & PURSE_FLAG_GENERIC_LOOP else
             "quad-lanes" if flags & PURSE_FLAG_QUAD_LANES else
             "pair-lanes" if flags & PURSE_FLAG_PAIR_LANES else "unrolled")
-    return "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first", loop)
+    name = "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first", loop)
+    if flags & PURSE_FLAG_WORK_QUEUE:
+        name += "/queue"
+    if waves:
+        name += "/%dwaves" % waves
+    return name
 
 
 def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
@@ -95,29 +107,36 @@ def tune(db, params, ws, poses, mask, inst_status, stream=None, reps: int = 3,
     table = _load(path)
     rec = table.get(key)
     if not force and isinstance(rec, dict) and "tile" in rec and "flags" in rec:
-        return _with(params, rec["tile"], rec["flags"]), dict(rec, cached=True)
+        return _with(params, rec["tile"], rec["flags"], rec.get("waves", 0)), dict(rec, cached=True)
     if stream is None:
         stream = torch.cuda.current_stream()
     loops = LOOPS if db.max_kp <= SMALL_N and bool((db.kind == 1).any()) else (0,)
     times, cand = {}, {}
+
+    def run(tile, flags, waves):
+        p = _with(params, tile, flags, waves)
+        purse_sample(db, p, poses, mask, inst_status, ws, stream)  # warm-up
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            purse_sample(db, p, poses, mask, inst_status, ws, stream)
+        e.record(stream)
+        e.synchronize()
+        name = _name(tile, flags, waves)
+        times[name] = s.elapsed_time(e) / reps
+        cand[name] = (tile, flags, waves)
+
     for tile in TILES:
         for order in ORDERS:
             for loop in loops:
-                p = _with(params, tile, order | loop)
-                purse_sample(db, p, poses, mask, inst_status, ws, stream)  # warm-up
-                s = torch.cuda.Event(enable_timing=True)
-                e = torch.cuda.Event(enable_timing=True)
-                s.record(stream)
-                for _ in range(reps):
-                    purse_sample(db, p, poses, mask, inst_status, ws, stream)
-                e.record(stream)
-                e.synchronize()
-                name = _name(tile, order | loop)
-                times[name] = s.elapsed_time(e) / reps
-                cand[name] = (tile, order | loop)
+                run(tile, order | loop, 0)
+    tile, flags, _ = cand[min(times, key=times.get)]
+    for extra, waves in STAGE2:
+        run(tile, flags | extra, waves)
     best = min(times, key=times.get)
-    tile, flags = cand[best]
-    rec = {"tile": tile, "flags": flags, "choice": best, "ms": times[best], "candidates_ms": times}
+    tile, flags, waves = cand[best]
+    rec = {"tile": tile, "flags": flags, "waves": waves, "choice": best, "ms": times[best], "candidates_ms": times}
     table[key] = rec
     _store(path, table)
-    return _with(params, tile, flags), dict(rec, cached=False)
+    return _with(params, tile, flags, waves), dict(rec, cached=False)

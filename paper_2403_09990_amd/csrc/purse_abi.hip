@@ -65,6 +65,7 @@ purse_status check_params(const purse_params *p) {
   if (p->centre_gn < 1 || p->centre_gn > 100) return fail(PURSE_E_BAD_ARG, "centre_gn out of range");
   if (!(p->tile == 0 || p->tile == 64 || p->tile == 128 || p->tile == 256))
     return fail(PURSE_E_BAD_ARG, "tile must be 0, 64, 128 or 256");
+  if (p->waves_per_simd < 0 || p->waves_per_simd > 8) return fail(PURSE_E_BAD_ARG, "waves_per_simd must be 0..8");
   return PURSE_OK;
 }
 
@@ -142,7 +143,8 @@ purse_status sample_into(const purse_batch *b, const purse_params *p, float *pos
   const int tile = p->tile ? p->tile : 256;
   if (purse::sample_grid(b->total_samples, b->n_inst, tile / 2) > INT32_MAX)
     return fail(PURSE_E_BAD_ARG, "too many sample tiles for one launch");
-  purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, st);
+  purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, b->total_samples,
+                       p->waves_per_simd, st);
   return hip_check(hipGetLastError(), "sampler launch");
 }
 
@@ -157,7 +159,7 @@ constexpr int64_t kNoAllocMaxInst = 1024;
 constexpr int64_t kNoAllocMaxKp = 65536;
 constexpr size_t kScratchBytes =
     purse::align_up(sizeof(purse::InstRec) * kNoAllocMaxInst) + purse::align_up(sizeof(purse::KpRec) * kNoAllocMaxKp) +
-    purse::align_up(sizeof(int32_t) * purse::kSchedGroups * (2 * kNoAllocMaxInst + 1));
+    purse::align_up(sizeof(int32_t) * purse::kSchedGroups * (2 * kNoAllocMaxInst + 2));
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -210,6 +212,7 @@ purse_status purse_default_params(purse_params *p) {
   p->centre_gn = 50;
   p->tile = 0;
   p->flags = 0;
+  p->waves_per_simd = 0;
   return PURSE_OK;
 }
 

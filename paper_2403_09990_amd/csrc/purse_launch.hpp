@@ -13,10 +13,13 @@ void launch_prologue(const DevBatch &b, const DevParams &p, InstRec *inst, KpRec
 // Workgroups of one sampler launch (an upper bound on sum_j ceil(M_j / tile)).
 int64_t sample_grid(int64_t total_samples, int n_inst, int tile);
 
-// Builds the tile schedule (sched: sched_ints(n_inst) int32 per kind) and runs
-// both kinds' trajectories; tile: samples per workgroup (64, 128 or 256).
+// Builds the tile schedule (sched: sched_ints(n_inst) int32 per kind, then
+// one work-queue counter per kind) and runs both kinds' trajectories; tile:
+// samples per workgroup (64, 128 or 256); waves_per_simd: residency cap (0:
+// none).
 void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
-                   float *poses, uint8_t *mask, int tile, hipStream_t stream);
+                   float *poses, uint8_t *mask, int tile, int64_t grid_samples, int waves_per_simd,
+                   hipStream_t stream);
 
 // ckpt: the rotation iterates C_0, C_ck, ... of every descent, left for the
 // backward ([n_inst][ckpt_count] quaternions) with their trace signature in rec.

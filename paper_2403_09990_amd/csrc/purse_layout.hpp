@@ -152,7 +152,7 @@ inline WsLayout ws_layout(int64_t n_inst, int64_t total_kp, int64_t total_sample
   L.kp = o;
   o += align_up(sizeof(KpRec) * (size_t)total_kp);
   L.sched = o;
-  o += align_up(sizeof(int32_t) * kSchedGroups * sched_ints(n_inst));
+  o += align_up(sizeof(int32_t) * kSchedGroups * (sched_ints(n_inst) + 1));  // schedules, then queue counters
   L.megb = o;
   o += align_up(sizeof(MegbRec) * (size_t)n_inst);
   L.quat = o;

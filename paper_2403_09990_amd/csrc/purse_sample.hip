@@ -9,6 +9,8 @@
 // consecutive tiles.  The hardware dispatches workgroups in index order, so the
 // heaviest tiles start first and the tail of the launch is made of light ones
 // (longest-processing-time-first list scheduling).
+#include <algorithm>
+
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
 
@@ -97,17 +99,13 @@ __global__ void __launch_bounds__(kSchedBlock) k_schedule(const InstRec *__restr
     if (tid == kSchedBlock - 1) tstart[n] = part[kSchedBlock - 1];
     __syncthreads();
   }
+  // the work-queue counters of the three groups
+  if (tid < kSchedGroups) sched[(size_t)kSchedGroups * sched_ints(n) + tid] = 0;
 }
 
-template <int KIND, int NMAX>
-__global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
-                                                const int32_t *__restrict__ sched, int n_inst, DevParams p,
-                                                float *__restrict__ poses, uint8_t *__restrict__ mask) {
-  const int32_t *order = sched + (size_t)group_of<KIND, NMAX>() * sched_ints(n_inst);
-  const int32_t *tstart = order + n_inst;
-  const int b = blockIdx.x;
-  if (b >= tstart[n_inst]) return;
-  // the entry k of the order with tstart[k] <= b < tstart[k + 1]
+// The tile of schedule entry b: the entry k of the order with
+// tstart[k] <= b < tstart[k + 1].
+__device__ __forceinline__ int tile_entry(const int32_t *__restrict__ tstart, int n_inst, int b) {
   int lo = 0, hi = n_inst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -116,6 +114,15 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
     else
       hi = mid - 1;
   }
+  return lo;
+}
+
+template <int KIND, int NMAX>
+__device__ __forceinline__ void sample_tile(int b, const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
+                                            const int32_t *__restrict__ order, const int32_t *__restrict__ tstart,
+                                            int n_inst, const DevParams &p, float *__restrict__ poses,
+                                            uint8_t *__restrict__ mask) {
+  const int lo = tile_entry(tstart, n_inst, b);
   const int j = order[lo];
   const InstRec &I = inst[j];
   const int64_t s = (int64_t)(b - tstart[lo]) * blockDim.x + threadIdx.x;
@@ -140,28 +147,48 @@ __global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst
   mask[g] = m;
 }
 
+// Work-queue mode: each workgroup takes the next tile of the group's
+// schedule from the counter k_schedule cleared, until none is left (every
+// workgroup reaches the end of the schedule and leaves).
+template <typename F>
+__device__ __forceinline__ void tile_queue(int32_t *counter, int total, F &&run) {
+  __shared__ int sh_b;
+  for (;;) {
+    if (threadIdx.x == 0) sh_b = atomicAdd(counter, 1);
+    __syncthreads();
+    const int b = sh_b;
+    __syncthreads();  // (sh_b is read before the next tile's atomic overwrites it)
+    if (b >= total) break;
+    run(b);
+  }
+}
+
+template <int KIND, int NMAX, bool QUEUE>
+__global__ void __launch_bounds__(256) k_sample(const InstRec *__restrict__ inst, const KpRec *__restrict__ kprec,
+                                                int32_t *__restrict__ sched, int n_inst, DevParams p,
+                                                float *__restrict__ poses, uint8_t *__restrict__ mask) {
+  constexpr int grp = group_of<KIND, NMAX>();
+  const int32_t *order = sched + (size_t)grp * sched_ints(n_inst);
+  const int32_t *tstart = order + n_inst;
+  const int total = tstart[n_inst];
+  if (QUEUE) {
+    tile_queue(sched + (size_t)kSchedGroups * sched_ints(n_inst) + grp, total,
+               [&](int b) { sample_tile<KIND, NMAX>(b, inst, kprec, order, tstart, n_inst, p, poses, mask); });
+  } else if ((int)blockIdx.x < total) {
+    sample_tile<KIND, NMAX>(blockIdx.x, inst, kprec, order, tstart, n_inst, p, poses, mask);
+  }
+}
+
 // Lane-group modes of the unrolled 2D-3D group (PURSE_FLAG_PAIR_LANES: G = 2,
 // PURSE_FLAG_QUAD_LANES: G = 4): a workgroup of blockDim lanes runs blockDim / G
 // trajectories, G lanes each; the instance's keypoint records are staged in
 // LDS first.
 template <int NMAX, int G>
-__global__ void __launch_bounds__(256, G == 4 ? 4 : 1) k_sample2d_lanes(const InstRec *__restrict__ inst,
-                                                        const KpRec *__restrict__ kprec,
-                                                        const int32_t *__restrict__ sched, int n_inst, DevParams p,
-                                                        float *__restrict__ poses, uint8_t *__restrict__ mask) {
-  __shared__ KpRec kp_s[NMAX];
-  const int32_t *order = sched + (size_t)2 * sched_ints(n_inst);
-  const int32_t *tstart = order + n_inst;
-  const int b = blockIdx.x;
-  if (b >= tstart[n_inst]) return;
-  int lo = 0, hi = n_inst - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tstart[mid] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
+__device__ __forceinline__ void sample_tile_lanes(int b, KpRec *kp_s, const InstRec *__restrict__ inst,
+                                                  const KpRec *__restrict__ kprec, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ tstart, int n_inst, const DevParams &p,
+                                                  float *__restrict__ poses, uint8_t *__restrict__ mask) {
+  const int lo = tile_entry(tstart, n_inst, b);
   const int j = order[lo];
   const InstRec &I = inst[j];
   if (launch_group(I, p.flags) != 2) return;  // (whole workgroup)
@@ -193,31 +220,93 @@ __global__ void __launch_bounds__(256, G == 4 ? 4 : 1) k_sample2d_lanes(const In
   }
 }
 
+template <int NMAX, int G, bool QUEUE>
+__global__ void __launch_bounds__(256, G == 4 ? 4 : 1) k_sample2d_lanes(const InstRec *__restrict__ inst,
+                                                        const KpRec *__restrict__ kprec,
+                                                        int32_t *__restrict__ sched, int n_inst, DevParams p,
+                                                        float *__restrict__ poses, uint8_t *__restrict__ mask) {
+  __shared__ KpRec kp_s[NMAX];
+  const int32_t *order = sched + (size_t)2 * sched_ints(n_inst);
+  const int32_t *tstart = order + n_inst;
+  const int total = tstart[n_inst];
+  if (QUEUE) {
+    // (the queue's barriers also keep a tile's keypoint records until every
+    // lane is done with them)
+    tile_queue(sched + (size_t)kSchedGroups * sched_ints(n_inst) + 2, total, [&](int b) {
+      sample_tile_lanes<NMAX, G>(b, kp_s, inst, kprec, order, tstart, n_inst, p, poses, mask);
+    });
+  } else if ((int)blockIdx.x < total) {
+    sample_tile_lanes<NMAX, G>(blockIdx.x, kp_s, inst, kprec, order, tstart, n_inst, p, poses, mask);
+  }
+}
+
 int64_t sample_grid(int64_t total_samples, int n_inst, int tile) {
   // sum_j ceil(M_j / tile) <= total / tile + n_inst
   return total_samples / tile + n_inst;
 }
 
 void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
-                   float *poses, uint8_t *mask, int tile, hipStream_t stream) {
+                   float *poses, uint8_t *mask, int tile, int64_t grid_samples, int waves_per_simd,
+                   hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
-  const dim3 grid((unsigned)sample_grid(b.total_samples, b.n_inst, tile));
+  // waves per SIMD: at most 8 resident (the hardware's limit), or the cap,
+  // which each workgroup's LDS padding enforces: just over the share of the
+  // compute unit's LDS that would admit one more workgroup, within the
+  // per-workgroup limit less room for the kernels' own LDS (under 1 KB).  The
+  // allocation granularity can leave one workgroup fewer than the cap.
+  const int wg_waves = tile / 64;
+  const int cap = waves_per_simd > 0 ? waves_per_simd : 8;
+  const int wg_per_cu = std::max(1, (4 * cap + wg_waves - 1) / wg_waves);
+  int dev = 0, n_cu = 256, lds_cu = 163840, lds_block = 65536;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    n_cu = 256;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      lds_cu <= 0)
+    lds_cu = 163840;
+  if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      lds_block <= 0)
+    lds_block = 65536;
+  const size_t lds = waves_per_simd > 0 ? (size_t)std::max(0, std::min(lds_cu / (wg_per_cu + 1) + 512, lds_block - 2048))
+                                        : 0;
+  const bool queue = (p.flags & PURSE_FLAG_WORK_QUEUE) != 0;
+  auto grid_of = [&](int t) {
+    const int64_t g = sample_grid(grid_samples, b.n_inst, t);
+    return dim3((unsigned)(queue ? std::min<int64_t>(g, (int64_t)n_cu * wg_per_cu) : g));
+  };
+  const dim3 grid = grid_of(tile);
   if (p.flags & PURSE_FLAG_QUAD_LANES) {
-    const dim3 grid4((unsigned)sample_grid(b.total_samples, b.n_inst, tile / 4));
-    hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 4>), grid4, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                       poses, mask);
+    if (queue)
+      hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 4, true>), grid_of(tile / 4), dim3(tile), lds, stream, inst, kp,
+                         sched, b.n_inst, p, poses, mask);
+    else
+      hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 4, false>), grid_of(tile / 4), dim3(tile), lds, stream, inst, kp,
+                         sched, b.n_inst, p, poses, mask);
   } else if (p.flags & PURSE_FLAG_PAIR_LANES) {
-    const dim3 grid2((unsigned)sample_grid(b.total_samples, b.n_inst, tile / 2));
-    hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 2>), grid2, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                       poses, mask);
+    if (queue)
+      hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 2, true>), grid_of(tile / 2), dim3(tile), lds, stream, inst, kp,
+                         sched, b.n_inst, p, poses, mask);
+    else
+      hipLaunchKernelGGL((k_sample2d_lanes<kSmallN, 2, false>), grid_of(tile / 2), dim3(tile), lds, stream, inst, kp,
+                         sched, b.n_inst, p, poses, mask);
+  } else if (queue) {
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN, true>), grid, dim3(tile), lds, stream, inst, kp, sched,
+                       b.n_inst, p, poses, mask);
   } else {
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst,
-                       p, poses, mask);
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, kSmallN, false>), grid, dim3(tile), lds, stream, inst, kp, sched,
+                       b.n_inst, p, poses, mask);
   }
-  hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                     poses, mask);
-  hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0>), grid, dim3(tile), 0, stream, inst, kp, sched, b.n_inst, p,
-                     poses, mask);
+  if (queue) {
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, true>), grid, dim3(tile), lds, stream, inst, kp, sched, b.n_inst,
+                       p, poses, mask);
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, true>), grid, dim3(tile), lds, stream, inst, kp, sched, b.n_inst,
+                       p, poses, mask);
+  } else {
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, false>), grid, dim3(tile), lds, stream, inst, kp, sched,
+                       b.n_inst, p, poses, mask);
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, false>), grid, dim3(tile), lds, stream, inst, kp, sched,
+                       b.n_inst, p, poses, mask);
+  }
 }
 
 }  // namespace purse

@@ -62,6 +62,14 @@ def test_every_schedule_writes_every_sample_identically():
                 assert (poses[off[-2]:off[-1]] == 0).all() and (mask[off[-2]:off[-1]] == 0).all()
             else:
                 assert torch.equal(poses, ref[0]) and torch.equal(mask, ref[1]) and torch.equal(status, ref[2])
+    # persistent work-queue kernels and residency caps: the same samples
+    for tile in (64, 256):
+        for flags, waves in ((P.PURSE_FLAG_WORK_QUEUE, 0), (0, 2), (P.PURSE_FLAG_WORK_QUEUE, 4),
+                             (P.PURSE_FLAG_WORK_QUEUE | P.PURSE_FLAG_INSTANCE_ORDER, 1)):
+            _log("case: schedule tile", tile, "flags", flags, "waves", waves)
+            gp = P.purse_default_params(n_iters=15, tile=tile, flags=flags, waves_per_simd=waves)
+            poses, mask, status = _run(P, db, gp)
+            assert torch.equal(poses, ref[0]) and torch.equal(mask, ref[1]) and torch.equal(status, ref[2])
 
 
 def test_unrolled_and_generic_keypoint_loops_agree():
@@ -89,6 +97,10 @@ def test_unrolled_and_generic_keypoint_loops_agree():
             diff = (a[0] - pr[0]).abs().max().item()
             _log(name, "lanes, tile", tile, "max pose difference", diff)
             assert diff <= 1e-5
+            # the same lane groups from the work queue: bitwise the same
+            pq = _run(P, db, P.purse_default_params(n_iters=40, tile=tile, flags=flag | P.PURSE_FLAG_WORK_QUEUE,
+                                                    waves_per_simd=2 if tile == 64 else 0))
+            assert torch.equal(pq[0], pr[0]) and torch.equal(pq[1], pr[1]) and torch.equal(pq[2], pr[2])
 
 
 def test_autotune_picks_and_caches(tmp_path):
@@ -103,15 +115,16 @@ def test_autotune_picks_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     best, rep = autotune.tune(db, gp, ws, out["poses"], out["mask"], out["inst_status"], cache=cache, reps=1)
     assert not rep["cached"] and best.tile in autotune.TILES
-    assert len(rep["candidates_ms"]) >= len(autotune.TILES) * len(autotune.ORDERS)
+    assert len(rep["candidates_ms"]) >= len(autotune.TILES) * len(autotune.ORDERS) + len(autotune.STAGE2)
     best2, rep2 = autotune.tune(db, gp, ws, out["poses"], out["mask"], out["inst_status"], cache=cache)
     assert rep2["cached"] and best2.tile == best.tile and best2.flags == best.flags
+    assert best2.waves_per_simd == best.waves_per_simd
     # the tuned schedule gives the default schedule's results
     ref = P.sample(db, gp)
     got = P.sample(db, best)
     torch.cuda.synchronize()
     assert torch.equal(ref["mask"], got["mask"])
-    if best.flags & (P.PURSE_FLAG_GENERIC_LOOP | P.PURSE_FLAG_PAIR_LANES):
+    if best.flags & (P.PURSE_FLAG_GENERIC_LOOP | P.PURSE_FLAG_PAIR_LANES | P.PURSE_FLAG_QUAD_LANES):
         assert (ref["poses"] - got["poses"]).abs().max().item() <= 1e-5
     else:
         assert torch.equal(ref["poses"], got["poses"])
