@@ -59,6 +59,16 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+def build_tool(src: str, exe: str) -> str:
+    """A standalone HIP program (measurement tools), with the library's flags."""
+    cmd = [_hipcc()] + FLAGS + [src, "-o", exe + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 if __name__ == "__main__":
     build()
     sys.exit(0)

@@ -1,0 +1,115 @@
+// Calibration of gfx950's FP32 issue rates and of the SQ instruction
+// counters: kernels that run a known number of one FP32 instruction (16
+// independent chains per lane, so dependences do not limit the issue), timed
+// with HIP events.  Run under rocprofv3 --pmc, the counts per dispatch can be
+// compared with the exact ones printed here.
+//   valu_calib [blocks] [iters]
+// prints, per kernel: the instruction, the time, the wave-level instruction
+// count, wave instructions per SIMD per cycle at 2.4 GHz on 1,024 SIMDs, and
+// lane operations per second.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+
+namespace {
+
+constexpr int kChains = 16;
+
+// v_fma_f32 (VOP3) with a scalar operand: x = x * a + b
+__global__ void __launch_bounds__(256) k_fma_vop3(float *out, int iters, float a, float b) {
+  float x[kChains];
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) x[j] = (float)(threadIdx.x + j);
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) x[j] = fmaf(x[j], a, b);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) s += x[j];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// v_fmac_f32_e32 (VOP2): x += y * z with vector operands
+__global__ void __launch_bounds__(256) k_fmac_vop2(float *out, int iters, float a, float) {
+  float x[kChains], y[kChains];
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) {
+    x[j] = (float)(threadIdx.x + j);
+    y[j] = a * (float)(j + 1);
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) x[j] = fmaf(y[j], y[(j + 1) % kChains], x[j]);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) s += x[j];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// v_mul_f32_e32
+__global__ void __launch_bounds__(256) k_mul_vop2(float *out, int iters, float a, float) {
+  float x[kChains], y[kChains];
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) {
+    x[j] = (float)(threadIdx.x + j);
+    y[j] = 1.f - a * (float)(j + 1);
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) x[j] = x[j] * y[j];
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) s += x[j];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// v_add_f32_e32
+__global__ void __launch_bounds__(256) k_add_vop2(float *out, int iters, float a, float) {
+  float x[kChains], y[kChains];
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) {
+    x[j] = (float)(threadIdx.x + j);
+    y[j] = a * (float)(j + 1);
+  }
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) x[j] = x[j] + y[j];
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < kChains; ++j) s += x[j];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+  const int blocks = argc > 1 ? atoi(argv[1]) : 8192;
+  const int iters = argc > 2 ? atoi(argv[2]) : 25000;
+  if (blocks < 1 || iters < 1) return 2;
+  float *out = nullptr;
+  if (hipMalloc(&out, (size_t)blocks * 256 * sizeof(float)) != hipSuccess) return 1;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1;
+  typedef void (*K)(float *, int, float, float);
+  const K ks[4] = {k_fma_vop3, k_fmac_vop2, k_mul_vop2, k_add_vop2};
+  const char *names[4] = {"v_fma_f32(vop3,sgpr)", "v_fmac_f32_e32", "v_mul_f32_e32", "v_add_f32_e32"};
+  for (int k = 0; k < 4; ++k) {
+    hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(256), 0, 0, out, 4, 0.999f, 1e-3f);
+    if (hipDeviceSynchronize() != hipSuccess) return 3;
+    if (hipEventRecord(e0, 0) != hipSuccess) return 3;
+    hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(256), 0, 0, out, iters, 0.999f, 1e-3f);
+    if (hipEventRecord(e1, 0) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 3;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 3;
+    const double wi = (double)blocks * 4 * iters * kChains;
+    printf("%-22s ms %9.3f  wave-instr %.4e  per-SIMD-cycle %.3f  lane-op/s %.3e\n", names[k], ms, wi,
+           wi / (1024.0 * 2.4e9 * ms * 1e-3), wi * 64.0 / (ms * 1e-3));
+  }
+  (void)hipFree(out);
+  return 0;
+}
