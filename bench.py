@@ -68,6 +68,20 @@ def read_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def read_valu(kernel, workload):
+    """FP32 operations per launch of the kernel from the committed F32 VALU
+    counter summary (rocprofv3 --pmc), or None if the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", "valu_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    from paper_2403_09990_amd.profile_summary import source_hash
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash(kernel):
+        return None
+    return rec.get("f32_flops_per_dispatch")
+
+
 def _progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -295,7 +309,9 @@ def main():
     # when the schedule runs 2D-3D trajectories on two or four lanes each
     traj_kernel = ("k_sample2d_lanes" if gp.flags & (P.PURSE_FLAG_PAIR_LANES | P.PURSE_FLAG_QUAD_LANES)
                    else "k_sample")
-    traffic = read_traffic(traj_kernel, args.config if args.n_inst is None else "%s_n%d" % (args.config, db.n_inst))
+    wl_key = args.config if args.n_inst is None else "%s_n%d" % (args.config, db.n_inst)
+    traffic = read_traffic(traj_kernel, wl_key)
+    flops_counted = read_valu(traj_kernel, wl_key)
 
     # calibration kernel for the traffic counters: a copy of known size
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -351,7 +367,10 @@ def main():
                      "flops_per_launch": flops,
                      "frac_nonpacked_ceiling": achieved / (FP32_VECTOR_PEAK_TFLOPS / 2),
                      "flops_per_launch_kernel_formulation": flops_kernel,
-                     "frac_kernel_formulation": flops_kernel / (ms_traj * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS},
+                     "frac_kernel_formulation": flops_kernel / (ms_traj * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                     "flops_per_launch_f32_counters": flops_counted,
+                     "frac_f32_counters": None if flops_counted is None else
+                     flops_counted / (ms_traj * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS},
         # write-out: 12 float32 of pose and one mask byte per sample
         "hbm_write_gbs": total_m * 49 / (ms_traj * 1e-3) / 1e9,
     }

@@ -8,7 +8,12 @@
         Per (kernel, workgroup size, grid size) statistics (rocpd database).
 
     python -m paper_2403_09990_amd.profile_summary counters DIR --kernel NAME
-        Mean per dispatch of every counter of a --pmc run for one kernel.
+        Mean per dispatch of every counter of a --pmc run for one kernel, over
+        the dispatches that carry the workload.
+
+    python -m paper_2403_09990_amd.profile_summary valu DIR --kernel NAME [--out FILE.json] [--cmd C]
+        FP32 operations per dispatch from the F32 VALU instruction counters
+        (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F32), stamped like traffic.
 
     python -m paper_2403_09990_amd.profile_summary traffic FETCH_DIR WRITE_DIR
             --kernel k_sample --copy-bytes B --out FILE.json [--cmd-fetch C] [--cmd-write C]
@@ -41,8 +46,9 @@ def source_hash(kernel=None) -> str:
     """Hash of the sources the kernel is built from, so that a traffic figure
     is not reported once they have changed."""
     h = hashlib.sha256()
-    if kernel in KERNEL_SOURCES:
-        files = [os.path.normpath(os.path.join(PKG, f)) for f in KERNEL_SOURCES[kernel]]
+    base = kernel.split("<")[0].strip() if kernel else None
+    if base in KERNEL_SOURCES:
+        files = [os.path.normpath(os.path.join(PKG, f)) for f in KERNEL_SOURCES[base]]
     else:
         d = os.path.join(PKG, "csrc")
         files = [os.path.join(d, f) for f in sorted(os.listdir(d))]
@@ -155,17 +161,63 @@ def _per_dispatch(dirname, counter):
     return list(vals.values())
 
 
-def counters(dirname, kernel):
-    """Mean per dispatch of every counter collected for dispatches of kernel."""
+def _counter_dispatches(dirname, kernel):
+    """{dispatch: {counter: value}} of every dispatch of the matching kernels
+    (values of a counter's instances summed)."""
     q = "select dispatch_id, kernel_name, counter_name, value from counters_collection"
     acc = {}
     for r in _db_rows(dirname, q):
         if kernel not in r["kernel_name"]:
             continue
-        d = acc.setdefault(r["counter_name"], {})
-        key = (r["_path"], r["dispatch_id"])
-        d[key] = d.get(key, 0.0) + float(r["value"])
-    return {c: sum(v.values()) / len(v) for c, v in acc.items()}
+        d = acc.setdefault((r["_path"], r["dispatch_id"]), {})
+        d[r["counter_name"]] = d.get(r["counter_name"], 0.0) + float(r["value"])
+    return acc
+
+
+def counters(dirname, kernel):
+    """Mean per dispatch of every counter collected for the dispatches of
+    kernel that carry the workload: those whose VALU instruction count (or,
+    without it, the sum of all counters) is within half of the largest.  A
+    warm-up launch of a few iterations or a launch group with no instances
+    (whose workgroups exit at once) would otherwise pull the mean down."""
+    acc = _counter_dispatches(dirname, kernel)
+    if not acc:
+        return {}
+
+    def weight(d):
+        return d["SQ_INSTS_VALU"] if "SQ_INSTS_VALU" in d else sum(d.values())
+
+    top = max(weight(d) for d in acc.values())
+    keep = [d for d in acc.values() if weight(d) >= 0.5 * top]
+    names = sorted(set().union(*keep))
+    res = {c: sum(d.get(c, 0.0) for d in keep) / len(keep) for c in names}
+    res["dispatches"] = len(keep)
+    res["dispatches_dropped"] = len(acc) - len(keep)
+    return res
+
+
+# FP32 VALU counters and the operations each instruction counts for
+_F32_OPS = {"SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_MUL_F32": 1, "SQ_INSTS_VALU_ADD_F32": 1,
+            "SQ_INSTS_VALU_TRANS_F32": 1}
+
+
+def valu(dirname, kernel, out=None, cmd=None):
+    """FP32 operations per dispatch of a kernel from the F32 VALU instruction
+    counters: 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions (packed
+    FP32 instructions are not generated by this build), stamped with the hash
+    of the kernel's sources."""
+    c = counters(dirname, kernel)
+    missing = [k for k in _F32_OPS if k not in c]
+    if missing:
+        raise RuntimeError("counters %s not collected for %s in %s" % (missing, kernel, dirname))
+    res = {"kernel": kernel, "source_hash": source_hash(kernel), "cmd": cmd, "counters": c,
+           "f32_flops_per_dispatch": 64.0 * sum(w * c[k] for k, w in _F32_OPS.items())}
+    if "SQ_ACTIVE_INST_VALU" in c and c.get("SQ_WAVE_CYCLES"):
+        res["valu_active_per_wave_cycle"] = c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"]
+    if out:
+        with open(out, "w") as f:
+            json.dump(res, f, indent=1)
+    return res
 
 
 def _mean_for(disp, pred):
@@ -216,6 +268,11 @@ def main(argv=None):
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("dir")
+    v.add_argument("--kernel", required=True)
+    v.add_argument("--out")
+    v.add_argument("--cmd")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_dir")
     b.add_argument("write_dir")
@@ -230,6 +287,9 @@ def main(argv=None):
         return
     if args.mode == "counters":
         print(json.dumps(counters(args.dir, args.kernel), indent=1))
+        return
+    if args.mode == "valu":
+        print(json.dumps(valu(args.dir, args.kernel, args.out, args.cmd), indent=1))
         return
     if args.mode == "stats":
         text = stats(args.dir, args.title, args.cmd)

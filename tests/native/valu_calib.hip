@@ -7,6 +7,11 @@
 // prints, per kernel: the instruction, the time, the wave-level instruction
 // count, wave instructions per SIMD per cycle at 2.4 GHz on 1,024 SIMDs, and
 // lane operations per second.
+//   valu_calib sweep [iters]
+// times v_fmac_f32_e32 with 1, 2, 4, 8 and 16 independent chains per lane at
+// 1, 2, 4 and 8 resident wavefronts per SIMD (256, 512, 1024 and 2048
+// four-wave workgroups on 256 compute units): the issue rate a kernel can
+// reach with that much instruction-level parallelism and occupancy.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -85,9 +90,69 @@ __global__ void __launch_bounds__(256) k_add_vop2(float *out, int iters, float a
   out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+// v_fmac_f32_e32 in C independent chains per lane
+template <int C>
+__global__ void __launch_bounds__(256) k_fmac_chains(float *out, int iters, float a, float) {
+  float x[C], y[C], z[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    x[j] = (float)(threadIdx.x + j);
+    y[j] = a * (float)(j + 1);
+    z[j] = a * (float)(j + 2);
+  }
+  // 16 instructions per loop body whatever C, so that the loop's scalar
+  // instructions and branch weigh the same in every variant
+  constexpr int kU = 16 / C;
+  for (int i = 0; i < iters; i += kU) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int j = 0; j < C; ++j) x[j] = fmaf(y[j], z[j], x[j]);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < C; ++j) s += x[j];
+  out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+int sweep(int iters) {
+  typedef void (*K)(float *, int, float, float);
+  const K ks[5] = {k_fmac_chains<1>, k_fmac_chains<2>, k_fmac_chains<4>, k_fmac_chains<8>, k_fmac_chains<16>};
+  const int chains[5] = {1, 2, 4, 8, 16};
+  float *out = nullptr;
+  if (hipMalloc(&out, (size_t)2048 * 256 * sizeof(float)) != hipSuccess) return 1;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1;
+  printf("v_fmac_f32_e32 wave instructions per SIMD per cycle (2.4 GHz, 1,024 SIMDs)\n");
+  printf("%-8s", "chains");
+  for (int w = 1; w <= 8; w *= 2) printf("  %d wave%s/SIMD", w, w > 1 ? "s" : " ");
+  printf("\n");
+  for (int k = 0; k < 5; ++k) {
+    printf("%-8d", chains[k]);
+    for (int w = 1; w <= 8; w *= 2) {
+      const int blocks = 256 * w;
+      // fewer iterations for more chains: about the same time per launch
+      const int it = iters * 16 / chains[k];  // a multiple of 16 / chains
+      hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(256), 0, 0, out, 4, 0.999f, 1e-3f);
+      if (hipDeviceSynchronize() != hipSuccess) return 3;
+      if (hipEventRecord(e0, 0) != hipSuccess) return 3;
+      hipLaunchKernelGGL(ks[k], dim3(blocks), dim3(256), 0, 0, out, it, 0.999f, 1e-3f);
+      if (hipEventRecord(e1, 0) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 3;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 3;
+      const double wi = (double)blocks * 4 * it * chains[k];
+      printf("  %12.3f", wi / (1024.0 * 2.4e9 * ms * 1e-3));
+    }
+    printf("\n");
+  }
+  (void)hipFree(out);
+  return 0;
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
+  if (argc > 1 && argv[1][0] == 's') return sweep(argc > 2 ? atoi(argv[2]) : 20000);
   const int blocks = argc > 1 ? atoi(argv[1]) : 8192;
   const int iters = argc > 2 ? atoi(argv[2]) : 25000;
   if (blocks < 1 || iters < 1) return 2;
