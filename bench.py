@@ -82,6 +82,57 @@ def read_valu(kernel, workload):
     return rec.get("f32_flops_per_dispatch")
 
 
+def per_instance_bench(P, torch, batch, db, gp, stream, no_backward, poses, mask, status, centre, radii, nfeas,
+                       trace, g_radii, g_centre, g_c, g_L, g_b, bwd_status, ref, ms_fwd_batched,
+                       ms_step_batched):
+    """The batch run as one library call per instance (the plain single-instance
+    path, as a caller without batching would): sampler, MEGB and backward of
+    each instance in turn on the stream, eager, writing into the batched
+    outputs' slices of that instance.  Timed like the batched step, and its
+    results compared with the batched call's."""
+    from paper_2403_09990_amd.workloads import Batch
+    so, ko = db.sample_off_host, db.kp_off_host
+    calls = []
+    for j, ins in enumerate(batch.instances):
+        d1 = P.DeviceBatch(Batch([ins]))
+        w1 = P.workspace(d1, gp)
+        a, b, ka, kb = int(so[j]), int(so[j + 1]), int(ko[j]), int(ko[j + 1])
+        calls.append((d1, w1, poses[a:b], mask[a:b], status[j:j + 1], centre[j:j + 1], radii[j:j + 1],
+                      nfeas[j:j + 1], trace[j:j + 1], g_radii[j:j + 1], g_centre[j:j + 1], g_c[ka:kb],
+                      g_L[ka:kb], g_b[ka:kb], bwd_status[j:j + 1]))
+
+    def fwd():
+        for d1, w1, po, ma, st, ce, ra, nf, tr, *_ in calls:
+            P.purse_sample(d1, gp, po, ma, st, w1)
+            P.purse_megb(d1, gp, po, ma, ce, ra, nf, tr, st, w1)
+
+    def step():
+        for d1, w1, po, ma, st, ce, ra, nf, tr, gr, gce, gc, gl, gb, bs in calls:
+            P.purse_sample(d1, gp, po, ma, st, w1)
+            P.purse_megb(d1, gp, po, ma, ce, ra, nf, tr, st, w1)
+            if not no_backward:
+                P.purse_megb_backward(d1, gp, po, ma, tr, gr, gce, gc, gl, gb, w1, bwd_status=bs)
+
+    step()
+    torch.cuda.synchronize()
+    ms_fwd = time_events(fwd, 1, stream)
+    ms_step = time_events(step, 1, stream)
+    torch.cuda.synchronize()
+
+    def same(a, b):
+        return bool(torch.equal(torch.nan_to_num(a, 7.0), torch.nan_to_num(b, 7.0))) if a.is_floating_point() \
+            else bool(torch.equal(a, b))
+    res = {"calls": len(calls), "fwd_ms": ms_fwd, "fwd_samples_per_s": db.total_samples / (ms_fwd * 1e-3),
+           "batched_fwd_speedup": ms_fwd / ms_fwd_batched,
+           "samples_equal_batched": same(poses, ref["poses"]) and same(mask, ref["mask"]),
+           "radii_equal_batched": same(radii, ref["radii"])}
+    if not no_backward:
+        res.update({"fwd_bwd_ms": ms_step, "fwd_bwd_samples_per_s": db.total_samples / (ms_step * 1e-3),
+                    "batched_fwd_bwd_speedup_vs_eager_step": ms_step / ms_step_batched,
+                    "gradients_equal_batched": same(g_c, ref["g_c"]) and same(g_L, ref["g_L"])})
+    return res
+
+
 def _progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -178,6 +229,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default schedule instead of the autotuned one")
     ap.add_argument("--no-graph", action="store_true", help="time the eager step instead of its graph replay")
     ap.add_argument("--no-walk", action="store_true", help="skip the strategic random walk figures")
+    ap.add_argument("--no-per-instance", action="store_true",
+                    help="skip timing the batch as one call per instance")
     ap.add_argument("--n-inst", type=int, default=None,
                     help="first N instances of c3/c5 only (profiling runs whose per-dispatch counters must stay "
                          "short); the reported workload names the count")
@@ -374,6 +427,12 @@ def main():
         # write-out: 12 float32 of pose and one mask byte per sample
         "hbm_write_gbs": total_m * 49 / (ms_traj * 1e-3) / 1e9,
     }
+    if db.n_inst > 1 and not args.no_per_instance:
+        _progress("the same batch as one call per instance")
+        ref = dict(poses=poses.clone(), mask=mask.clone(), radii=radii.clone(), g_c=g_c.clone(), g_L=g_L.clone())
+        out["per_instance_calls"] = per_instance_bench(
+            P, torch, batch, db, gp, stream, args.no_backward, poses, mask, status, centre, radii, nfeas, trace,
+            g_radii, g_centre, g_c, g_L, g_b, bwd_status, ref, ms_fwd, None if args.no_backward else ms_step_eager)
     if not args.no_walk:
         _progress("strategic random walk (LM-O-shaped)")
         out["walk_lmo"] = walk_bench(P, torch)
