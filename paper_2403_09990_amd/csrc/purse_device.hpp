@@ -38,7 +38,12 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 // ones are also host functions, so the host tests run the float64 paths)
 __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
 __host__ __device__ inline double dsqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float drsqrt(float x) { return rsqrtf(x); }
+// the hardware reciprocal square root: for normal inputs it is what rsqrtf
+// returns, without rsqrtf's rescaling of denormal inputs.  Every use here
+// bounds its input away from the denormal range, discards the result there,
+// or (a denormal Cholesky pivot, a rank-one polar input) fails the step
+// either way.
+__device__ __forceinline__ float drsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __host__ __device__ inline double drsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ void dsincos(float x, float *s, float *c) { sincosf(x, s, c); }
 __device__ __forceinline__ void dsincos(double x, double *s, double *c) { sincos(x, s, c); }
