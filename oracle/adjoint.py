@@ -23,7 +23,7 @@ import numpy as np
 import torch
 
 from .params import OracleParams
-from .purse import (KIND_2D3D, MASK_FEASIBLE, Problem, feasible, initial_poses, prologue,
+from .purse import (KIND_2D3D, MASK_FEASIBLE, Problem, feasibility_ratio, feasible, initial_poses, prologue,
                     pull_in, run_trajectories)
 from .so3 import angle, exp_so3, log_so3, proj_so3, proj_so3_newton, vee_skew
 
@@ -109,6 +109,34 @@ def backward(inst, p: OracleParams, trace, s0, sD, sd, g_radii, g_centre, lo=Non
     else:
         gL = torch.zeros_like(gL)
     return gc.detach().numpy(), gL.reshape(-1, 4).detach().numpy(), gb.detach().numpy()
+
+
+def decision_margins(inst, p: OracleParams, sample_ids, bis_steps: int = 8):
+    """Per sample, the smallest relative margin of the decisions the frozen-
+    decision map holds fixed: the projection clamps of every iteration (at
+    the derivative convention's threshold), the final in_purse test
+    (|max_i r_i / (beta_i + tau) - 1|) and, for samples pulled in, the
+    bisection's first bis_steps tests (a later step's outcome moves the
+    pulled-in pose by at most 2^-bis_steps of the segment).  A margin near
+    float32 rounding marks a decision that a float32 recomputation may take
+    the other way, and with it a different (equally valid) frozen-decision
+    derivative (diagnostic)."""
+    prob = Problem(inst.kind, inst.model_pts, torch.as_tensor(np.asarray(inst.centres), dtype=DT),
+                   torch.as_tensor(np.asarray(inst.shapes), dtype=DT),
+                   torch.as_tensor(np.asarray(inst.bounds), dtype=DT), inst.intrinsics)
+    pro = prologue(prob, p)
+    ids = np.asarray(sample_ids, dtype=np.uint64)
+    R0, t0 = initial_poses(pro, p, inst.seed, ids)
+    m_cl = []
+    with torch.no_grad():
+        R, t, failed = run_trajectories(prob, R0, t0, pro["o_c"], p, deriv_convention=True, margins=m_cl)
+        out = torch.minimum(m_cl[0], (feasibility_ratio(prob, R, t, p) - 1.0).abs())
+        need = torch.nonzero(~feasible(prob, R, t, p) & ~failed)[:, 0]
+        if len(need) and pro.get("R_a") is not None:
+            mb = []
+            pull_in(prob, pro["R_a"], pro["t_a"], R[need], t[need], p, margins=mb, margin_steps=bis_steps)
+            out[need] = torch.minimum(out[need], mb[0])
+    return out.numpy()
 
 
 def radius_argmax(poses, mask, Rstar, tstar):

@@ -364,16 +364,26 @@ def initial_poses(pro: dict, p: OracleParams, seed: int, ids: np.ndarray):
     return R0, t0
 
 
-def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams, deriv_convention: bool = False):
+def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams, deriv_convention: bool = False,
+                     margins=None):
     """n_iters alternating iterations from (R, t): project every keypoint onto
     its constraint (shrunk by kappa), then refit the pose (Arun for 3D-3D,
     n_gn Gauss-Newton steps about o_c for 2D-3D).  A 2D-3D trajectory whose
-    Gauss-Newton step fails is frozen and flagged."""
+    Gauss-Newton step fails is frozen and flagged.
+    margins (a list): receives, per trajectory, the smallest relative margin
+    |r_i / threshold_i - 1| of the projection decisions over all iterations
+    and keypoints (the threshold of project_targets under the same
+    convention; diagnostic)."""
     M = R.shape[0]
     failed = torch.zeros(M, dtype=torch.bool)
     o = o_c.expand(M, 3)
+    closest = torch.full((M,), math.inf, dtype=DT)
     for _ in range(p.n_iters):
         e, r, _ = residual(prob, R, t)
+        if margins is not None:
+            thr = p.kappa * prob.beta * ((1.0 - DERIV_EPS) if deriv_convention else 1.0)
+            with torch.no_grad():
+                closest = torch.minimum(closest, (r / thr - 1.0).abs().min(-1).values)
         q = project_targets(prob, e, r, p.kappa, deriv_convention)
         if prob.kind == KIND_3D3D:
             R, t = kabsch(prob.model, q)
@@ -383,16 +393,19 @@ def run_trajectories(prob: Problem, R, t, o_c, p: OracleParams, deriv_convention
                 failed = failed | ~ok
                 R = torch.where(failed[:, None, None], R, Rn)
                 t = torch.where(failed[:, None], t, tn)
+    if margins is not None:
+        margins.append(closest)
     return R, t, failed
 
 
-def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None, margins=None):
+def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None, margins=None, margin_steps=None):
     """Bisection on the geodesic segment x(l) = (R_a Exp(l Log(R_a^T R)),
     t_a + l (t - t_a)) from the feasible anchor (l = 0) to the infeasible end
     (l = 1); returns x(lo) after n_bis steps, which is in S, and lo.  With
     lo_fixed the bisection's outcome is taken as given (frozen decisions).
     margins (a list): receives, per trajectory, the smallest |ratio - 1| of
-    the bisection's feasibility tests (diagnostic)."""
+    the bisection's feasibility tests, or of its first margin_steps tests
+    when given (diagnostic)."""
     w = log_so3(Ra.transpose(-1, -2) @ R)
     M = R.shape[0]
     if lo_fixed is None:
@@ -400,12 +413,12 @@ def pull_in(prob: Problem, Ra, ta, R, t, p: OracleParams, lo_fixed=None, margins
         hi = torch.ones(M, dtype=DT)
         closest = torch.full((M,), math.inf, dtype=DT)
         with torch.no_grad():
-            for _ in range(p.n_bis):
+            for step in range(p.n_bis):
                 mid = 0.5 * (lo + hi)
                 Rm = Ra @ exp_so3(mid[:, None] * w)
                 tm = ta + mid[:, None] * (t - ta)
                 f = feasible(prob, Rm, tm, p)
-                if margins is not None:
+                if margins is not None and (margin_steps is None or step < margin_steps):
                     closest = torch.minimum(closest, (feasibility_ratio(prob, Rm, tm, p) - 1.0).abs())
                 lo = torch.where(f, mid, lo)
                 hi = torch.where(f, hi, mid)

@@ -1109,6 +1109,24 @@ __device__ __forceinline__ float group_sum(float x) {
   return x;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "lane groups within a row of 16");
+  x += dpp_f64<0xB1>(x);
+  if (G >= 4) x += dpp_f64<0x4E>(x);
+  if (G >= 8) x += dpp_f64<0x141>(x);
+  if (G >= 16) x += dpp_f64<0x140>(x);
+  return x;
+}
+
 template <int G>
 __device__ __forceinline__ Dual<float> group_sum(Dual<float> x) {
   return Dual<float>(group_sum<G>(x.v), group_sum<G>(x.d));
@@ -1310,54 +1328,78 @@ __global__ void __launch_bounds__(64) k_bwd_traj2d_group(DevBatch b, DevParams p
 //   then back through the rows (pt x d_r, d_r), the whitened projection
 //   Jacobian, the residual (the clamp scale s = kappa beta / r when clamped,
 //   the second pass's targets from the iteration's first pose) and the
-//   projection, into the pose, the pivot and the keypoint's data.
+//   projection, into the pose and the keypoint's data; the pivot's
+//   cotangent comes whole from each update (rev_pivot_adjoint).
 constexpr int kRevGroup = 16;
 constexpr int kRevPerLane = (PURSE_MAX_KP + kRevGroup - 1) / kRevGroup;
 constexpr int kRevSamples = 64 / kRevGroup;  // active samples per wavefront
-constexpr int kRevMaxPasses = 320;            // Gauss-Newton passes the LDS tape holds (61 KB)
+constexpr size_t kRevLds = 65536;              // LDS of a reverse-sweep workgroup at most
 
-struct RevPose {
-  float R[9], t[3];
+// LDS of a reverse-sweep workgroup: per sample, a float32 pose per pass (the
+// tape) and a byte of clamp bits per lane and iteration.
+__host__ __device__ constexpr size_t rev_lds(int passes, int iters) {
+  return sizeof(float) * 12 * kRevSamples * (size_t)(passes > 0 ? passes : 1) +
+         (size_t)kRevSamples * kRevGroup * (size_t)(iters > 0 ? iters : 1);
+}
+
+template <typename T>
+struct RevPoseT {
+  T R[9], t[3];
 };
+using RevPose = RevPoseT<float>;
+
+template <typename T>
+__device__ __forceinline__ void rev_round(const RevPoseT<T> &x, RevPose &y) {
+#pragma unroll
+  for (int m = 0; m < 9; ++m) y.R[m] = (float)x.R[m];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) y.t[m] = (float)x.t[m];
+}
 
 // Group-summed normal equations of one pass at x (targets from xk for the
 // later passes), as gn_pass2d_group computes them; false on a depth below
-// z_min.
-template <bool FIRST>
+// z_min.  Projection decisions: bit rr of cl is lane q's keypoint
+// q + kRevGroup rr; taken from cl when use_cl, else decided here and
+// recorded in cl.
+template <bool FIRST, typename T>
 __device__ __forceinline__ bool rev_normal_eqs(const KpRec *__restrict__ kp, int n, int q, const float K[4],
-                                               const float oc[3], float z_min, float band, const RevPose &xk,
-                                               const RevPose &x, float A[21], float g[6]) {
+                                               const T oc[3], float z_min, float band, const RevPoseT<T> &xk,
+                                               const RevPoseT<T> &x, T A[21], T g[6], uint32_t &cl, bool use_cl) {
 #pragma unroll
-  for (int k = 0; k < 21; ++k) A[k] = 0.f;
+  for (int k = 0; k < 21; ++k) A[k] = T(0);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = 0.f;
+  for (int k = 0; k < 6; ++k) g[k] = T(0);
   bool ok = true;
-  for (int i = q; i < n; i += kRevGroup) {
+  if (!use_cl) cl = 0u;
+  for (int i = q, rr = 0; i < n; i += kRevGroup, ++rr) {
     const KpRec k = kp[i];
-    float P[3], iz, u, v;
+    const T w[3] = {T(k.w[0]), T(k.w[1]), T(k.w[2])};
+    T P[3], iz, u, v;
     project2d(x.R, x.t, k, K, P, iz, u, v);
-    ok = ok && (P[2] > z_min);
-    float rt0, rt1;
+    ok = ok && (P[2] > T(z_min));
+    T rt0, rt1;
     if (FIRST) {
-      const float e0 = u - k.c[0], e1 = v - k.c[1];
-      const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
-      const float r2 = et0 * et0 + et1 * et1;
-      const float s = (r2 <= k.kb2 * band) ? 1.f : k.kb * drsqrt(r2);
-      rt0 = (s - 1.f) * et0;
-      rt1 = (s - 1.f) * et1;
+      const T e0 = u - T(k.c[0]), e1 = v - T(k.c[1]);
+      const T et0 = w[0] * e0 + w[1] * e1, et1 = w[2] * e1;
+      const T r2 = et0 * et0 + et1 * et1;
+      if (!use_cl && !(r2 <= T(k.kb2) * T(band))) cl |= 1u << rr;
+      const T s = ((cl >> rr) & 1u) ? T(k.kb) * drsqrt(r2) : T(1);
+      rt0 = (s - T(1)) * et0;
+      rt1 = (s - T(1)) * et1;
     } else {
-      float Pk[3], izk, uk, vk;
+      T Pk[3], izk, uk, vk;
       project2d(xk.R, xk.t, k, K, Pk, izk, uk, vk);
-      const float e0 = uk - k.c[0], e1 = vk - k.c[1];
-      const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
-      const float r2 = et0 * et0 + et1 * et1;
-      const float s = (r2 <= k.kb2 * band) ? 1.f : k.kb * drsqrt(r2);
-      const float r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
-      rt0 = k.w[0] * r0 + k.w[1] * r1;
-      rt1 = k.w[2] * r1;
+      const T e0 = uk - T(k.c[0]), e1 = vk - T(k.c[1]);
+      const T et0 = w[0] * e0 + w[1] * e1, et1 = w[2] * e1;
+      const T r2 = et0 * et0 + et1 * et1;
+      if (!use_cl && !(r2 <= T(k.kb2) * T(band))) cl |= 1u << rr;
+      const T s = ((cl >> rr) & 1u) ? T(k.kb) * drsqrt(r2) : T(1);
+      const T r0 = T(k.c[0]) + s * e0 - u, r1 = T(k.c[1]) + s * e1 - v;
+      rt0 = w[0] * r0 + w[1] * r1;
+      rt1 = w[2] * r1;
     }
-    const float pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
-    gn_accumulate<float>(P, pt, iz, K[0], K[1], k.w, rt0, rt1, A, g);
+    const T pt[3] = {P[0] - oc[0], P[1] - oc[1], P[2] - oc[2]};
+    gn_accumulate<T>(P, pt, iz, T(K[0]), T(K[1]), w, rt0, rt1, A, g);
   }
 #pragma unroll
   for (int k = 0; k < 21; ++k) A[k] = group_sum<kRevGroup>(A[k]);
@@ -1382,6 +1424,34 @@ __device__ __forceinline__ void rev_exp_adjoint(const float w[3], const float Eb
   }
 }
 
+// Cotangent of the pivot o from one Gauss-Newton update, given the cotangent
+// t_bar of the updated translation.  In the coordinates (dw, dv + o x dw) the
+// linearised fit does not depend on o (a point moves by dw x P + dv - dw x o),
+// so at a fixed input pose and fixed targets the update moves the
+// translation by (I - E + [dw]x) o, E = Exp(dw); the pivot's cotangent is
+// that matrix transposed applied to t_bar: -(1 - A) dw x t_bar
+// - B dw x (dw x t_bar), A = sin th / th, B = (1 - cos th) / th^2 (series
+// below th^2 = 0.1).  Formed directly, it is second order in the step:
+// summing the first-order terms of the update's and of the keypoint rows'
+// dependences on o, which cancel, loses it to float32 rounding.
+__device__ __forceinline__ void rev_pivot_adjoint(const float dw[3], const float tb[3], float ob[3]) {
+  const float th2 = dw[0] * dw[0] + dw[1] * dw[1] + dw[2] * dw[2];
+  float oma, bb;
+  if (th2 < 0.1f) {
+    oma = th2 * (1.f / 6.f - th2 * (1.f / 120.f - th2 * (1.f / 5040.f - th2 * (1.f / 362880.f))));
+    bb = 0.5f - th2 * (1.f / 24.f - th2 * (1.f / 720.f - th2 * (1.f / 40320.f)));
+  } else {
+    const float th = sqrtf(th2);
+    oma = 1.f - sinf(th) / th;
+    bb = (1.f - cosf(th)) / th2;
+  }
+  float wt[3], wwt[3];
+  cross3(dw, tb, wt);
+  cross3(dw, wt, wwt);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) ob[r] -= oma * wt[r] + bb * wwt[r];
+}
+
 // Adjoint of the pose update x' = (E R, E (t - o) + o + dv), E = Exp(dw):
 // from x_bar' to the cotangents of the input pose (uniform part), of o and
 // of the step d = (dw, dv).
@@ -1404,22 +1474,21 @@ __device__ __forceinline__ void rev_update_adjoint(const float d[6], const float
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     xb_in.t[r] = E[r] * xb_out.t[0] + E[3 + r] * xb_out.t[1] + E[6 + r] * xb_out.t[2];
-    ob[r] += xb_out.t[r] - xb_in.t[r];
     db[3 + r] = xb_out.t[r];
   }
+  rev_pivot_adjoint(d, xb_out.t, ob);
   rev_exp_adjoint(d, Eb, db);
 }
 
 // Per-keypoint adjoint of one pass: adds this lane's part of the input
-// pose's cotangent (xb), of the iteration's first pose (xkb, later passes),
-// of the pivot (ob) and of its keypoints' data (kb: c0, c1, w0, w1, w2,
-// kappa beta).
+// pose's cotangent (xb), of the iteration's first pose (xkb, later passes)
+// and of its keypoints' data (kb: c0, c1, w0, w1, w2, kappa beta).  (The
+// pivot's cotangent is taken whole from the update, rev_pivot_adjoint.)
 template <bool FIRST>
 __device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int n, int q, const float K[4],
-                                              const float oc[3], float band, const RevPose &xk,
+                                              const float oc[3], uint32_t clbits, const RevPose &xk,
                                               const RevPose &x, const float d[6], const float gb[6],
-                                              RevPose &xb, RevPose &xkb, float ob[3],
-                                              float kb[kRevPerLane][6]) {
+                                              RevPose &xb, RevPose &xkb, float kb[kRevPerLane][6]) {
 #pragma unroll
   for (int rr = 0; rr < kRevPerLane; ++rr) {
     const int i = q + kRevGroup * rr;
@@ -1438,7 +1507,7 @@ __device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int 
       et0 = w0 * e0 + w1 * e1;
       et1 = w2 * e1;
       r2 = et0 * et0 + et1 * et1;
-      cl = !(r2 <= k.kb2 * band);
+      cl = (clbits >> rr) & 1u;
       s = cl ? k.kb * drsqrt(r2) : 1.f;
       rt0 = (s - 1.f) * et0;
       rt1 = (s - 1.f) * et1;
@@ -1450,7 +1519,7 @@ __device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int 
       et0 = w0 * e0 + w1 * e1;
       et1 = w2 * e1;
       r2 = et0 * et0 + et1 * et1;
-      cl = !(r2 <= k.kb2 * band);
+      cl = (clbits >> rr) & 1u;
       s = cl ? k.kb * drsqrt(r2) : 1.f;
       const float r0 = k.c[0] + s * e0 - u, r1 = k.c[1] + s * e1 - v;
       rt0 = w0 * r0 + w1 * r1;
@@ -1572,10 +1641,7 @@ __device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int 
     Pb[1] += vb * K[1] * iz;
     izb += ub * K[0] * P[0] + vb * K[1] * P[1];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      Pb[r] += ptb[r];
-      ob[r] -= ptb[r];
-    }
+    for (int r = 0; r < 3; ++r) Pb[r] += ptb[r];
     Pb[2] += -izb * iz * iz;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -1598,11 +1664,11 @@ __device__ __forceinline__ void rev_keypoints(const KpRec *__restrict__ kp, int 
 // cotangent of the pass's output on entry and of its input on return.
 template <bool FIRST>
 __device__ __forceinline__ void rev_pass(const KpRec *__restrict__ kp, int n, int q, const float K[4],
-                                         const float oc[3], float z_min, float band, const RevPose &xk,
+                                         const float oc[3], float z_min, uint32_t clbits, const RevPose &xk,
                                          const RevPose &x, RevPose &xb, RevPose &xkb, float ob_u[3],
-                                         float ob_k[3], float kb[kRevPerLane][6]) {
+                                         float kb[kRevPerLane][6]) {
   float A[21], g[6], L[21], dinv[6], d[6];
-  rev_normal_eqs<FIRST>(kp, n, q, K, oc, z_min, band, xk, x, A, g);
+  rev_normal_eqs<FIRST, float>(kp, n, q, K, oc, z_min, 1.f, xk, x, A, g, clbits, true);
   chol6_factor<float>(A, L, dinv);
   chol6_subst<float>(L, dinv, g, d);
   RevPose xin;
@@ -1615,7 +1681,7 @@ __device__ __forceinline__ void rev_pass(const KpRec *__restrict__ kp, int n, in
   for (int m = 0; m < 9; ++m) part.R[m] = 0.f;
 #pragma unroll
   for (int m = 0; m < 3; ++m) part.t[m] = 0.f;
-  rev_keypoints<FIRST>(kp, n, q, K, oc, band, xk, x, d, gb, part, xkb, ob_k, kb);
+  rev_keypoints<FIRST>(kp, n, q, K, oc, clbits, xk, x, d, gb, part, xkb, kb);
   if (FIRST) {
     // the pass's input is the iteration's first pose: the later passes' parts join here
 #pragma unroll
@@ -1684,10 +1750,11 @@ __device__ __forceinline__ void rev_items_at(const int64_t *__restrict__ off, in
   a = (int)(it - off[j]);
 }
 
-// Work items of the reverse kernel: one per active sample of every 2D-3D
-// instance the backward differentiates (prefix sums, n + 1 entries).
+// Work items of the reverse kernels: one per active sample of every instance
+// of the kind that the backward differentiates (prefix sums, n + 1 entries).
 __global__ void __launch_bounds__(1024) k_bwd_items_rev(DevBatch b, const InstRec *__restrict__ inst,
-                                                        const BwdRec *recs, int64_t *__restrict__ item_off) {
+                                                        const BwdRec *recs, int kind,
+                                                        int64_t *__restrict__ item_off) {
   __shared__ int64_t part[1024];
   const int n = b.n_inst, tid = threadIdx.x;
   const int per = (n + 1023) / 1024;
@@ -1695,7 +1762,7 @@ __global__ void __launch_bounds__(1024) k_bwd_items_rev(DevBatch b, const InstRe
   auto items_of = [&](int j) -> int64_t {
     const BwdRec &r = recs[j];
     const InstRec I = inst[j];
-    if (r.status != kBwdOk || I.kind != PURSE_KIND_2D3D || (I.status & 0xFF) != PURSE_INST_OK ||
+    if (r.status != kBwdOk || I.kind != kind || (I.status & 0xFF) != PURSE_INST_OK ||
         !inst_record_ok(I, inst_view(b, j)))
       return 0;
     return (int64_t)min(max(r.n_act, 0), kMaxActive);
@@ -1718,18 +1785,19 @@ __global__ void __launch_bounds__(1024) k_bwd_items_rev(DevBatch b, const InstRe
   if (tid == 1023) item_off[n] = part[1023];
 }
 
-// The sampler's feasibility test (float, group-combined).
+// The sampler's feasibility test (group-combined).
+template <typename T>
 __device__ __forceinline__ bool rev_feasible(const KpRec *__restrict__ kp, int n, int q, const float K[4],
-                                             const RevPose &x, float z_min) {
+                                             const RevPoseT<T> &x, float z_min) {
   bool ok = true;
   for (int i = q; i < n; i += kRevGroup) {
     const KpRec k = kp[i];
-    float P[3], iz, u, v;
+    T P[3], iz, u, v;
     project2d(x.R, x.t, k, K, P, iz, u, v);
-    const float e0 = u - k.c[0], e1 = v - k.c[1];
-    const float et0 = k.w[0] * e0 + k.w[1] * e1, et1 = k.w[2] * e1;
-    const float rr = sqrtf(et0 * et0 + et1 * et1);
-    ok = ok && (P[2] > z_min) && (rr <= k.bt);
+    const T e0 = u - T(k.c[0]), e1 = v - T(k.c[1]);
+    const T et0 = T(k.w[0]) * e0 + T(k.w[1]) * e1, et1 = T(k.w[2]) * e1;
+    const T rr = dsqrt(et0 * et0 + et1 * et1);
+    ok = ok && (P[2] > T(z_min)) && (rr <= T(k.bt));
   }
   return group_and<kRevGroup>(ok);
 }
@@ -1745,6 +1813,8 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
   const int lane = threadIdx.x, grp = lane / kRevGroup, q = lane % kRevGroup;
   const int passes = p.n_iters * p.n_gn;
   float *tape = tape_all + (int64_t)grp * passes * 12;
+  uint8_t *clb = reinterpret_cast<uint8_t *>(tape_all + (int64_t)kRevSamples * (passes > 0 ? passes : 1) * 12) +
+                 (int64_t)grp * (p.n_iters > 0 ? p.n_iters : 1) * kRevGroup;
   const float band = ClampBand<Dual<float>>::v;
   for (int64_t wv = blockIdx.x; wv * kRevSamples < total; wv += gridDim.x) {
     const int64_t it = wv * kRevSamples + grp;
@@ -1758,57 +1828,70 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
     const float oc[3] = {I.oc[0], I.oc[1], I.oc[2]};
     const int s = live ? rec->active[a] : 0;
     // ---------------------------------------------------------- forward
-    RevPose x;
+    // The trajectory is recomputed in float64: its decisions (projection
+    // clamps, depth, feasibility, bisection) are those of the exact
+    // computation, which a float32 recomputation (rounding of a few 1e-6 in
+    // r) can take either way for a keypoint converged onto its kink.  The
+    // tape keeps the float32 rounding of each pass's input, the clamp bits
+    // each iteration's decisions; the sweep below is float32.
+    RevPoseT<double> x;
     {
-      const PoseT<float> x0 = initial_pose<float>(frame_ref(I), I.seed, (uint64_t)s, p);
+      const PoseT<double> x0 = initial_pose<double>(frame_ref(I), I.seed, (uint64_t)s, p);
 #pragma unroll
       for (int m = 0; m < 9; ++m) x.R[m] = x0.R[m];
 #pragma unroll
       for (int m = 0; m < 3; ++m) x.t[m] = x0.t[m];
     }
+    const double ocd[3] = {I.oc[0], I.oc[1], I.oc[2]};
     bool ok = live;
     for (int itr = 0; itr < p.n_iters && ok; ++itr) {
-      const RevPose xk = x;
+      const RevPoseT<double> xk = x;
+      uint32_t cl = 0u;
       for (int gs = 0; gs < p.n_gn && ok; ++gs) {
         const int ps = itr * p.n_gn + gs;
-        if (q < 12) tape[12 * ps + q] = q < 9 ? x.R[q] : x.t[q - 9];
-        float A[21], g[6], L[21], dinv[6], d[6];
-        ok = gs == 0 ? rev_normal_eqs<true>(kp, n, q, I.K, oc, p.z_min, band, xk, x, A, g)
-                     : rev_normal_eqs<false>(kp, n, q, I.K, oc, p.z_min, band, xk, x, A, g);
-        ok = ok && chol6_factor<float>(A, L, dinv);
+        if (q < 12) tape[12 * ps + q] = (float)(q < 9 ? x.R[q] : x.t[q - 9]);
+        double A[21], g[6], L[21], dinv[6], d[6];
+        ok = gs == 0 ? rev_normal_eqs<true, double>(kp, n, q, I.K, ocd, p.z_min, band, xk, x, A, g, cl, false)
+                     : rev_normal_eqs<false, double>(kp, n, q, I.K, ocd, p.z_min, band, xk, x, A, g, cl, true);
+        ok = ok && chol6_factor<double>(A, L, dinv);
         if (ok) {
-          chol6_subst<float>(L, dinv, g, d);
-          apply_update<float>(d, oc, x.R, x.t);
+          chol6_subst<double>(L, dinv, g, d);
+          apply_update<double>(d, ocd, x.R, x.t);
         }
       }
+      clb[itr * kRevGroup + q] = (uint8_t)cl;
     }
-    const RevPose xe = x;  // before the final reorthonormalisation
+    const RevPoseT<double> xed = x;  // before the final reorthonormalisation
     reorthonormalise(x.R);
     uint8_t mask = 0;
-    float lo = 1.f, w[3] = {0.f, 0.f, 0.f};
+    float lo = 1.f;
+    double wd[3] = {0.0, 0.0, 0.0};
     if (ok) {
-      if (rev_feasible(kp, n, q, I.K, x, p.z_min)) {
+      if (rev_feasible<double>(kp, n, q, I.K, x, p.z_min)) {
         mask = PURSE_MASK_FEASIBLE;
       } else if (I.has_anchor) {
-        float RaT[9], Q[9];
+        double Rad[9], RaT[9], Q[9];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) RaT[3 * r + c] = I.Ra[3 * c + r];
+          for (int c = 0; c < 3; ++c) {
+            Rad[3 * r + c] = I.Ra[3 * r + c];
+            RaT[3 * r + c] = I.Ra[3 * c + r];
+          }
         matmul3(RaT, x.R, Q);
-        log_so3(Q, w);
+        log_so3(Q, wd);
         lo = 0.f;
         float hi = 1.f;
         for (int bb = 0; bb < p.n_bis; ++bb) {
           const float mid = 0.5f * (lo + hi);
-          const float wm[3] = {mid * w[0], mid * w[1], mid * w[2]};
-          float E[9];
-          RevPose mp;
+          const double wm[3] = {mid * wd[0], mid * wd[1], mid * wd[2]};
+          double E[9];
+          RevPoseT<double> mp;
           exp_so3(wm, E);
-          matmul3(I.Ra, E, mp.R);
+          matmul3(Rad, E, mp.R);
 #pragma unroll
-          for (int r = 0; r < 3; ++r) mp.t[r] = I.ta[r] + mid * (x.t[r] - I.ta[r]);
-          if (rev_feasible(kp, n, q, I.K, mp, p.z_min))
+          for (int r = 0; r < 3; ++r) mp.t[r] = (double)I.ta[r] + mid * (x.t[r] - (double)I.ta[r]);
+          if (rev_feasible<double>(kp, n, q, I.K, mp, p.z_min))
             lo = mid;
           else
             hi = mid;
@@ -1816,11 +1899,15 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
         mask = PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
       }
     }
+    RevPose xf, xe;
+    rev_round(x, xf);
+    rev_round(xed, xe);
+    const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
     __syncthreads();  // the tape is complete
     // ---------------------------------------------------------- reverse
     float Rcb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tcb[3] = {0.f, 0.f, 0.f};
     float Rab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tab[3] = {0.f, 0.f, 0.f};
-    float ob_u[3] = {0.f, 0.f, 0.f}, ob_k[3] = {0.f, 0.f, 0.f};
+    float ob_u[3] = {0.f, 0.f, 0.f};
     float kb[kRevPerLane][6];
 #pragma unroll
     for (int rr = 0; rr < kRevPerLane; ++rr)
@@ -1865,7 +1952,7 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
           }
         rev_exp_adjoint(phi, Eb, phib);
         const float wb[3] = {lo * phib[0], lo * phib[1], lo * phib[2]};
-        matmul3(RaT, x.R, Q);
+        matmul3(RaT, xf.R, Q);
         rev_log_adjoint(Q, wb, Qb);
         // Q = Ra^T R: R_bar = Ra Q_bar, Ra_bar += R Q_bar^T
         matmul3(I.Ra, Qb, xb.R);
@@ -1873,7 +1960,7 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
         for (int r = 0; r < 3; ++r)
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            Rab[3 * r + c] += x.R[3 * r] * Qb[3 * c] + x.R[3 * r + 1] * Qb[3 * c + 1] + x.R[3 * r + 2] * Qb[3 * c + 2];
+            Rab[3 * r + c] += xf.R[3 * r] * Qb[3 * c] + xf.R[3 * r + 1] * Qb[3 * c + 1] + xf.R[3 * r + 2] * Qb[3 * c + 2];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           xb.t[m] = lo * ct[m];
@@ -1884,6 +1971,7 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
       for (int itr = p.n_iters - 1; itr >= 0; --itr) {
         RevPose xk, xkb;
         const float *tk = tape + 12 * (itr * p.n_gn);
+        const uint32_t clbi = clb[itr * kRevGroup + q];
 #pragma unroll
         for (int m = 0; m < 9; ++m) {
           xk.R[m] = tk[m];
@@ -1901,9 +1989,9 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
           for (int m = 0; m < 9; ++m) xin.R[m] = tx[m];
 #pragma unroll
           for (int m = 0; m < 3; ++m) xin.t[m] = tx[9 + m];
-          rev_pass<false>(kp, n, q, I.K, oc, p.z_min, band, xk, xin, xb, xkb, ob_u, ob_k, kb);
+          rev_pass<false>(kp, n, q, I.K, oc, p.z_min, clbi, xk, xin, xb, xkb, ob_u, kb);
         }
-        rev_pass<true>(kp, n, q, I.K, oc, p.z_min, band, xk, xk, xb, xkb, ob_u, ob_k, kb);
+        rev_pass<true>(kp, n, q, I.K, oc, p.z_min, clbi, xk, xk, xb, xkb, ob_u, kb);
       }
       // the start: even s rotate the centre by E about the pivot, odd s shift it
       if ((s & 1) == 0) {
@@ -1937,7 +2025,7 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       fb[9 + m] = tcb[m];
-      fb[12 + m] = ob_u[m] + group_sum<kRevGroup>(ob_k[m]);
+      fb[12 + m] = ob_u[m];
       fb[24 + m] = tab[m];
     }
     // ---------------------------------------------------- contributions
@@ -1955,6 +2043,408 @@ __global__ void __launch_bounds__(64) k_bwd_rev2d(DevBatch b, DevParams p, const
             kp_tangent(I, kp[i], b.shapes + 4 * (I.kp_off + i), b.bounds[I.kp_off + i], p.kappa, c, tk);
             acc = kb[rr][0] * tk.c[0].d + kb[rr][1] * tk.c[1].d + kb[rr][2] * tk.w[0].d + kb[rr][3] * tk.w[1].d +
                   kb[rr][4] * tk.w[2].d + kb[rr][5] * tk.kb.d;
+            const float *tn = tan_all + ((int64_t)j * max_dirs + d) * 27;
+#pragma unroll
+            for (int m = 0; m < 27; ++m) acc += fb[m] * tn[m];
+          }
+          contrib[((int64_t)j * kMaxActive + a) * max_dirs + d] = acc;
+        }
+      }
+    }
+    __syncthreads();  // (the next samples' forward rewrites the tape)
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3D-3D reverse sweep.  One iteration of the refit from x = (R, t):
+//   tt = t + R abar; per keypoint d = tt - c, e = R m + d, s = kappa beta / |e|
+//   when clamped (else 1), q = s e - d; M = sum q m^T, qs = sum q;
+//   R' = proj_SO3(M), t' = tt + qs / N - R' abar.
+// Its adjoint, from (R'_bar, t'_bar): tt_bar = t'_bar, qs_bar = t'_bar / N and
+// R'_bar - t'_bar abar^T into the polar factor, whose adjoint is
+// M_bar = R' [y]x with (tr(S) I - S) y = vee(R'^T R'_bar - R'_bar^T R'),
+// S = R'^T M (differentiating M = R' S with S symmetric and R'^T dR' skew,
+// then moving the symmetric operator Omega -> Omega S + S Omega across the
+// inner product); per keypoint q_bar = M_bar m + qs_bar, e_bar = s q_bar
+// (plus 2 r2_bar e and kappa_beta_bar += s_bar / |e| when clamped, with
+// s_bar = q_bar . e and r2_bar = -s_bar s / (2 |e|^2)), d_bar = e_bar - q_bar,
+// R_bar += e_bar m^T, tt_bar += d_bar, c_bar -= d_bar; finally t_bar = tt_bar
+// and R_bar += tt_bar abar^T.  Same lane groups and tape as the 2D-3D sweep
+// (one pose per iteration), the same frozen decisions.
+
+// Group-summed M and qs of one iteration at x, and tt; projection decisions
+// in cl as in rev_normal_eqs (taken from cl when use_cl, else recorded).
+template <typename T>
+__device__ __forceinline__ void rev3d_sums(const KpRec *__restrict__ kp, int n, int q, const float abar[3],
+                                           float band, const RevPoseT<T> &x, T tt[3], T M[9], T qs[3],
+                                           uint32_t &cl, bool use_cl) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    tt[r] = x.t[r] + x.R[3 * r] * T(abar[0]) + x.R[3 * r + 1] * T(abar[1]) + x.R[3 * r + 2] * T(abar[2]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) qs[k] = T(0);
+  if (!use_cl) cl = 0u;
+  for (int i = q, rr = 0; i < n; i += kRevGroup, ++rr) {
+    const KpRec k = kp[i];
+    T d[3], e[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      d[r] = tt[r] - T(k.c[r]);
+      e[r] = x.R[3 * r] * T(k.m[0]) + x.R[3 * r + 1] * T(k.m[1]) + x.R[3 * r + 2] * T(k.m[2]) + d[r];
+    }
+    const T r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+    if (!use_cl && !(r2 <= T(k.kb2) * T(band))) cl |= 1u << rr;
+    const T sc = ((cl >> rr) & 1u) ? T(k.kb) * drsqrt(r2) : T(1);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const T qq = sc * e[r] - d[r];
+      M[3 * r] += qq * T(k.m[0]);
+      M[3 * r + 1] += qq * T(k.m[1]);
+      M[3 * r + 2] += qq * T(k.m[2]);
+      qs[r] += qq;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = group_sum<kRevGroup>(M[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) qs[k] = group_sum<kRevGroup>(qs[k]);
+}
+
+// M_bar of R = proj_SO3(M) from R_bar (R the computed factor).
+__device__ __forceinline__ void rev_polar_adjoint(const float M[9], const float R[9], const float Rb[9],
+                                                  float Mb[9]) {
+  float S[9], X[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      S[3 * r + c] = R[r] * M[c] + R[3 + r] * M[3 + c] + R[6 + r] * M[6 + c];
+      X[3 * r + c] = R[r] * Rb[c] + R[3 + r] * Rb[3 + c] + R[6 + r] * Rb[6 + c];
+    }
+  const float a[3] = {X[7] - X[5], X[2] - X[6], X[3] - X[1]};
+  // B = tr(S) I - sym(S), solved by its adjugate
+  const float tr = S[0] + S[4] + S[8];
+  const float b00 = tr - S[0], b11 = tr - S[4], b22 = tr - S[8];
+  const float b01 = -0.5f * (S[1] + S[3]), b02 = -0.5f * (S[2] + S[6]), b12 = -0.5f * (S[5] + S[7]);
+  const float c00 = b11 * b22 - b12 * b12, c01 = b02 * b12 - b01 * b22, c02 = b01 * b12 - b02 * b11;
+  const float c11 = b00 * b22 - b02 * b02, c12 = b01 * b02 - b00 * b12, c22 = b00 * b11 - b01 * b01;
+  const float idet = 1.f / (b00 * c00 + b01 * c01 + b02 * c02);
+  const float y[3] = {(c00 * a[0] + c01 * a[1] + c02 * a[2]) * idet, (c01 * a[0] + c11 * a[1] + c12 * a[2]) * idet,
+                      (c02 * a[0] + c12 * a[1] + c22 * a[2]) * idet};
+  // M_bar = R [y]x
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Mb[3 * r] = R[3 * r + 1] * y[2] - R[3 * r + 2] * y[1];
+    Mb[3 * r + 1] = R[3 * r + 2] * y[0] - R[3 * r] * y[2];
+    Mb[3 * r + 2] = R[3 * r] * y[1] - R[3 * r + 1] * y[0];
+  }
+}
+
+// One iteration of the reverse sweep: xb holds the cotangent of the
+// iteration's output (whose rotation is Rn) on entry and of its input x on
+// return; the keypoints' cotangents (c_bar in kb[.][0..2], kappa beta in
+// kb[.][3]) accumulate per lane.
+__device__ __forceinline__ void rev3d_iter(const KpRec *__restrict__ kp, int n, int q, const float abar[3],
+                                           uint32_t clbits, const RevPose &x, const float Rn[9], RevPose &xb,
+                                           float kb[kRevPerLane][6]) {
+  float tt[3], M[9], qs[3];
+  rev3d_sums<float>(kp, n, q, abar, 1.f, x, tt, M, qs, clbits, true);
+  const float inv_n = 1.f / (float)n;
+  float qsb[3], Rpb[9], Mb[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    qsb[r] = xb.t[r] * inv_n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Rpb[3 * r + c] = xb.R[3 * r + c] - xb.t[r] * abar[c];
+  }
+  rev_polar_adjoint(M, Rn, Rpb, Mb);
+  float Rbp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, ttbp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int rr = 0; rr < kRevPerLane; ++rr) {
+    const int i = q + kRevGroup * rr;
+    if (i >= n) break;
+    const KpRec k = kp[i];
+    float d[3], e[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      d[r] = tt[r] - k.c[r];
+      e[r] = x.R[3 * r] * k.m[0] + x.R[3 * r + 1] * k.m[1] + x.R[3 * r + 2] * k.m[2] + d[r];
+    }
+    const float r2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+    const bool cl = (clbits >> rr) & 1u;
+    const float sc = cl ? k.kb * drsqrt(r2) : 1.f;
+    float qb[3], eb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      qb[r] = Mb[3 * r] * k.m[0] + Mb[3 * r + 1] * k.m[1] + Mb[3 * r + 2] * k.m[2] + qsb[r];
+      eb[r] = sc * qb[r];
+    }
+    if (cl) {
+      const float sb = qb[0] * e[0] + qb[1] * e[1] + qb[2] * e[2];
+      kb[rr][3] += sb * drsqrt(r2);
+      const float r2b = -0.5f * sb * sc / r2;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) eb[r] += 2.f * r2b * e[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float db = eb[r] - qb[r];
+      Rbp[3 * r] += eb[r] * k.m[0];
+      Rbp[3 * r + 1] += eb[r] * k.m[1];
+      Rbp[3 * r + 2] += eb[r] * k.m[2];
+      ttbp[r] += db;
+      kb[rr][r] -= db;
+    }
+  }
+  float ttb[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) ttb[r] = xb.t[r] + group_sum<kRevGroup>(ttbp[r]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    xb.t[r] = ttb[r];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xb.R[3 * r + c] = group_sum<kRevGroup>(Rbp[3 * r + c]) + ttb[r] * abar[c];
+  }
+}
+
+// The sampler's 3D-3D feasibility test (group-combined).
+template <typename T>
+__device__ __forceinline__ bool rev3d_feasible(const KpRec *__restrict__ kp, int n, int q, const float abar[3],
+                                               const RevPoseT<T> &x) {
+  T tt[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    tt[r] = x.t[r] + x.R[3 * r] * T(abar[0]) + x.R[3 * r + 1] * T(abar[1]) + x.R[3 * r + 2] * T(abar[2]);
+  bool ok = true;
+  for (int i = q; i < n; i += kRevGroup) {
+    const KpRec k = kp[i];
+    T e[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      e[r] = x.R[3 * r] * T(k.m[0]) + x.R[3 * r + 1] * T(k.m[1]) + x.R[3 * r + 2] * T(k.m[2]) + tt[r] - T(k.c[r]);
+    ok = ok && (dsqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]) <= T(k.bt));
+  }
+  return group_and<kRevGroup>(ok);
+}
+
+// One wavefront per kRevSamples active samples of 3D-3D instances; dynamic
+// LDS: the tape, kRevSamples x n_iters poses of 12 floats.
+__global__ void __launch_bounds__(64) k_bwd_rev3d(DevBatch b, DevParams p, const InstRec *__restrict__ inst,
+                                                  const KpRec *__restrict__ kprec, const BwdRec *recs,
+                                                  const int64_t *__restrict__ item_off,
+                                                  const float *__restrict__ tan_all, float *contrib, int max_dirs) {
+  extern __shared__ float tape_all[];
+  const int64_t total = item_off[b.n_inst];
+  const int lane = threadIdx.x, grp = lane / kRevGroup, q = lane % kRevGroup;
+  const int iters = p.n_iters;
+  const int it_alloc = iters > 0 ? iters : 1;
+  float *tape = tape_all + (int64_t)grp * it_alloc * 12;
+  uint8_t *clb = reinterpret_cast<uint8_t *>(tape_all + (int64_t)kRevSamples * it_alloc * 12) +
+                 (int64_t)grp * it_alloc * kRevGroup;
+  const float band = ClampBand<Dual<float>>::v;
+  for (int64_t wv = blockIdx.x; wv * kRevSamples < total; wv += gridDim.x) {
+    const int64_t it = wv * kRevSamples + grp;
+    const bool live = it < total;
+    int j = 0, a = 0;
+    if (live) rev_items_at(item_off, b.n_inst, it, j, a);
+    const InstRec I = inst[j];
+    const BwdRec *rec = recs + j;
+    const KpRec *kp = kprec + I.kp_off;
+    const int n = live ? I.n_kp : 0;
+    const int s = live ? rec->active[a] : 0;
+    // ---------------------------------------------------------- forward
+    // In float64, as in the 2D-3D sweep (the polar factor by the float64
+    // Jacobi iteration); float32 tape and clamp bits for the sweep.
+    RevPoseT<double> x;
+    {
+      const PoseT<double> x0 = initial_pose<double>(frame_ref(I), I.seed, (uint64_t)s, p);
+#pragma unroll
+      for (int m = 0; m < 9; ++m) x.R[m] = x0.R[m];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) x.t[m] = x0.t[m];
+    }
+    if (live) {
+      const double inv_n = 1.0 / (double)n;
+      for (int itr = 0; itr < iters; ++itr) {
+        if (q < 12) tape[12 * itr + q] = (float)(q < 9 ? x.R[q] : x.t[q - 9]);
+        double tt[3], M[9], qs[3];
+        uint32_t cl = 0u;
+        rev3d_sums<double>(kp, n, q, I.abar, band, x, tt, M, qs, cl, false);
+        clb[itr * kRevGroup + q] = (uint8_t)cl;
+        polar_so3<double>(M, x.R, 10);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          x.t[r] = tt[r] + qs[r] * inv_n -
+                   (x.R[3 * r] * (double)I.abar[0] + x.R[3 * r + 1] * (double)I.abar[1] +
+                    x.R[3 * r + 2] * (double)I.abar[2]);
+      }
+    }
+    uint8_t mask = 0;
+    float lo = 1.f;
+    double wd[3] = {0.0, 0.0, 0.0};
+    if (live) {
+      if (rev3d_feasible<double>(kp, n, q, I.abar, x)) {
+        mask = PURSE_MASK_FEASIBLE;
+      } else if (I.has_anchor) {
+        double Rad[9], RaT[9], Q[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Rad[3 * r + c] = I.Ra[3 * r + c];
+            RaT[3 * r + c] = I.Ra[3 * c + r];
+          }
+        matmul3(RaT, x.R, Q);
+        log_so3(Q, wd);
+        lo = 0.f;
+        float hi = 1.f;
+        for (int bb = 0; bb < p.n_bis; ++bb) {
+          const float mid = 0.5f * (lo + hi);
+          const double wm[3] = {mid * wd[0], mid * wd[1], mid * wd[2]};
+          double E[9];
+          RevPoseT<double> mp;
+          exp_so3(wm, E);
+          matmul3(Rad, E, mp.R);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) mp.t[r] = (double)I.ta[r] + mid * (x.t[r] - (double)I.ta[r]);
+          if (rev3d_feasible<double>(kp, n, q, I.abar, mp))
+            lo = mid;
+          else
+            hi = mid;
+        }
+        mask = PURSE_MASK_FEASIBLE | PURSE_MASK_PULLED_IN;
+      }
+    }
+    RevPose xf;
+    rev_round(x, xf);
+    const float w[3] = {(float)wd[0], (float)wd[1], (float)wd[2]};
+    __syncthreads();  // the tape is complete
+    // ---------------------------------------------------------- reverse
+    float Rcb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tcb[3] = {0.f, 0.f, 0.f};
+    float Rab[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, tab[3] = {0.f, 0.f, 0.f};
+    float ob_u[3] = {0.f, 0.f, 0.f};
+    float kb[kRevPerLane][6];
+#pragma unroll
+    for (int rr = 0; rr < kRevPerLane; ++rr)
+#pragma unroll
+      for (int m = 0; m < 6; ++m) kb[rr][m] = 0.f;
+    if (mask & PURSE_MASK_FEASIBLE) {
+      float cR[9], ct[3];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) cR[m] = (float)rec->cot[a][m];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) ct[m] = (float)rec->cot[a][9 + m];
+      RevPose xb;
+      if (!(mask & PURSE_MASK_PULLED_IN)) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) xb.R[m] = cR[m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xb.t[m] = ct[m];
+      } else if (lo == 0.f) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          Rab[m] += cR[m];
+          xb.R[m] = 0.f;
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          tab[m] += ct[m];
+          xb.t[m] = 0.f;
+        }
+      } else {
+        // out = (Ra Exp(lo w), ta + lo (t - ta)), w = Log(Ra^T R)
+        const float phi[3] = {lo * w[0], lo * w[1], lo * w[2]};
+        float E[9], Eb[9], phib[3], Qb[9], RaT[9], Q[9];
+        exp_so3(phi, E);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Rab[3 * r + c] += cR[3 * r] * E[3 * c] + cR[3 * r + 1] * E[3 * c + 1] + cR[3 * r + 2] * E[3 * c + 2];
+            Eb[3 * r + c] = I.Ra[r] * cR[c] + I.Ra[3 + r] * cR[3 + c] + I.Ra[6 + r] * cR[6 + c];
+            RaT[3 * r + c] = I.Ra[3 * c + r];
+          }
+        rev_exp_adjoint(phi, Eb, phib);
+        const float wb[3] = {lo * phib[0], lo * phib[1], lo * phib[2]};
+        matmul3(RaT, xf.R, Q);
+        rev_log_adjoint(Q, wb, Qb);
+        matmul3(I.Ra, Qb, xb.R);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Rab[3 * r + c] += xf.R[3 * r] * Qb[3 * c] + xf.R[3 * r + 1] * Qb[3 * c + 1] + xf.R[3 * r + 2] * Qb[3 * c + 2];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          xb.t[m] = lo * ct[m];
+          tab[m] += (1.f - lo) * ct[m];
+        }
+      }
+      for (int itr = iters - 1; itr >= 0; --itr) {
+        RevPose xin;
+        float Rn[9];
+        const float *tx = tape + 12 * itr;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          xin.R[m] = tx[m];
+          Rn[m] = itr + 1 < iters ? tx[12 + m] : xf.R[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) xin.t[m] = tx[9 + m];
+        rev3d_iter(kp, n, q, I.abar, clb[itr * kRevGroup + q], xin, Rn, xb, kb);
+      }
+      // the start: even s rotate the centre by E about the pivot, odd s shift it
+      if ((s & 1) == 0) {
+        float dd[3];
+        trajectory_direction(I.seed, (uint64_t)s, dd);
+        const float w0[3] = {p.omega0 * dd[0], p.omega0 * dd[1], p.omega0 * dd[2]};
+        float E[9];
+        exp_so3(w0, E);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Rcb[3 * r + c] += E[r] * xb.R[c] + E[3 + r] * xb.R[3 + c] + E[6 + r] * xb.R[6 + c];
+          const float et = E[r] * xb.t[0] + E[3 + r] * xb.t[1] + E[6 + r] * xb.t[2];
+          tcb[r] += et;
+          ob_u[r] += xb.t[r] - et;
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Rcb[m] += xb.R[m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) tcb[m] += xb.t[m];
+      }
+    }
+    float fb[27];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      fb[m] = Rcb[m];
+      fb[15 + m] = Rab[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      fb[9 + m] = tcb[m];
+      fb[12 + m] = ob_u[m];
+      fb[24 + m] = tab[m];
+    }
+    // ---------------------------------------------------- contributions
+    if (live) {
+      const bool feas = (mask & PURSE_MASK_FEASIBLE) != 0;
+      const int dpk = dirs_per_kp(PURSE_KIND_3D3D);
+#pragma unroll
+      for (int rr = 0; rr < kRevPerLane; ++rr) {
+        const int i = q + kRevGroup * rr;
+        if (i >= n) break;
+        for (int c = 0; c < dpk; ++c) {
+          const int d = dpk * i + c;
+          float acc = 0.f;
+          if (feas) {
+            KpT<Dual<float>> tk;
+            kp_tangent(I, kp[i], b.shapes + 4 * (I.kp_off + i), b.bounds[I.kp_off + i], p.kappa, c, tk);
+            acc = kb[rr][0] * tk.c[0].d + kb[rr][1] * tk.c[1].d + kb[rr][2] * tk.c[2].d + kb[rr][3] * tk.kb.d;
             const float *tn = tan_all + ((int64_t)j * max_dirs + d) * 27;
 #pragma unroll
             for (int m = 0; m < 27; ++m) acc += fb[m] * tn[m];
@@ -2089,10 +2579,11 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
   // 2D-3D: one reverse sweep per active sample while the tape fits in LDS,
   // else (or when asked) one forward-mode re-run per input direction
   const int passes = p.n_iters * p.n_gn;
-  const bool reverse = passes <= kRevMaxPasses && !(p.flags & PURSE_FLAG_FORWARD_TANGENTS);
+  const size_t lds2 = rev_lds(passes, p.n_iters);
+  const bool reverse = lds2 <= kRevLds && !(p.flags & PURSE_FLAG_FORWARD_TANGENTS);
   if (reverse) {
-    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, stream, b, inst, recs, items);
-    const size_t lds = sizeof(float) * 12 * (size_t)kRevSamples * (size_t)(passes > 0 ? passes : 1);
+    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_2D3D, items);
+    const size_t lds = lds2;
     hipLaunchKernelGGL(k_bwd_rev2d, dim3(kItemGrid), dim3(64), lds, stream, b, p, inst, kp, recs, items, tan,
                        contrib, max_dirs);
   } else {
@@ -2101,10 +2592,21 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
     hipLaunchKernelGGL(k_bwd_traj2d_group<kTrajGroup>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
                        items, tan, contrib, max_dirs);
   }
-  hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
-                     items + (n + 1));
-  hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
-                     items + (n + 1), tan, contrib, max_dirs);
+  // 3D-3D likewise, with one tape pose per iteration
+  const size_t lds3 = rev_lds(p.n_iters, p.n_iters);
+  const bool reverse3 = lds3 <= kRevLds && !(p.flags & PURSE_FLAG_FORWARD_TANGENTS);
+  if (reverse3) {
+    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D,
+                       items + (n + 1));
+    const size_t lds = lds3;
+    hipLaunchKernelGGL(k_bwd_rev3d, dim3(kItemGrid), dim3(64), lds, stream, b, p, inst, kp, recs, items + (n + 1),
+                       tan, contrib, max_dirs);
+  } else {
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
+                       items + (n + 1));
+    hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
+                       items + (n + 1), tan, contrib, max_dirs);
+  }
   hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
                      g_shapes, g_bounds, bwd_status);
   return hipSuccess;

@@ -90,6 +90,25 @@ def test_backward_c4_full_size():
     assert _compare(b, res, gp, 0, g_radii, g_centre, gpu) <= 1e-3
 
 
+@pytest.mark.parametrize("j", [9, 29, 44, 4])
+def test_backward_on_the_uneven_batch_matches_oracle(j):
+    """Instances of the 512-instance batch's generator (the first 48: N up to
+    48, ellipse semi-axes down to 3 px, 50 iterations, both kinds), whose
+    gradients go through the reverse sweeps: 9 and 29 are 2D-3D instances
+    where the pivot's cotangent, summed from first-order terms, once lost
+    float32 precision; 44 and 4 are 3D-3D."""
+    _log("case: backward on batch instance", j)
+    import paper_2403_09990_amd as P
+    b = W.config_c3(0, n_inst=48)
+    gp = P.purse_default_params(n_iters=50)
+    res = PT.run_gpu(b, gp)
+    rng = np.random.default_rng(11)
+    g_radii = rng.normal(size=(b.n_inst, 2))
+    g_centre = rng.normal(size=(b.n_inst, 6))
+    full = _gpu_backward(res, gp, g_radii, g_centre)
+    assert _compare(b, res, gp, j, g_radii, g_centre, full) <= 1e-3
+
+
 def test_backward_batched_equals_single():
     """Gradients of a batch equal the gradients of each instance alone."""
     _log("case: backward batched")

@@ -1,20 +1,30 @@
-"""The backward's reverse sweep over 2D-3D trajectories (one per active
-sample) against its forward mode (one re-run per input direction,
-PURSE_FLAG_FORWARD_TANGENTS): the same derivative of the same float32
-computation, so the gradients agree to float32 rounding of two summation
-orders (relative 2e-3 of each array's largest entry).  The forward mode is
-itself checked against the oracle's reverse pass (test_gpu_backward.py)."""
+"""The backward's reverse sweeps (2D-3D and 3D-3D: one float64 recomputation
+of each active sample's trajectory, which fixes its decisions, then a float32
+sweep back through it) against the oracle's float64 reverse pass on the same
+trace: relative error of each instance's gradient vector at most 1e-3.  The
+forward mode (one float32 re-run per input direction,
+PURSE_FLAG_FORWARD_TANGENTS) is compared with the oracle too, on instances
+where no decision of an active sample lies within float32 rounding of its
+threshold: there a float32 recomputation may take the decision the other way
+and differentiate the other (equally valid) frozen-decision map."""
 import sys
 
 import numpy as np
 import pytest
 import torch
 
+from oracle.adjoint import backward as oracle_backward
+from oracle.adjoint import decision_margins, radius_argmax
 from paper_2403_09990_amd import workloads as W
+from paper_2403_09990_amd._native import PURSE_KIND_2D3D
 from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
-RTOL = 2e-3
+RTOL = 1e-3
+# decisions within this relative margin (r_i against its clamp threshold, the
+# in_purse ratio, the bisection's first steps) count as hazards for a float32
+# recomputation: float32 trajectories reproduce r_i to a few 1e-6 (measured)
+HAZARD = 2e-5
 
 
 def _log(*a):
@@ -37,25 +47,87 @@ def _grads(P, res, gp, flags, g_radii, g_centre):
     return [x.cpu().numpy() for x in g], st.cpu().numpy()
 
 
+# radius samples whose distance to the centre is within this relative margin
+# of the largest are ties: the backward's float64 centre and the forward's
+# float32 one may order them differently, and each gives its own derivative
+RADIUS_TIE = 1e-4
+
+
+def _radius_candidates(poses, mask, C):
+    """Samples realising the rotation and the translation radius to within
+    RADIUS_TIE (the first entries are those radius_argmax picks)."""
+    sD, sd = radius_argmax(poses, mask, C[:9].reshape(3, 3), C[9:])
+    f = (mask & 1) != 0
+    R = poses[:, :9].reshape(-1, 3, 3).astype(np.float64)
+    t = poses[:, 9:].astype(np.float64)
+    ang = PT.rot_angle(R, C[:9].reshape(1, 3, 3))
+    dt = np.sqrt(((t - C[9:]) ** 2).sum(1))
+    out = []
+    for best, dist in ((sD, ang), (sd, dt)):
+        near = np.nonzero(f & (dist >= dist[best] * (1.0 - RADIUS_TIE)))[0]
+        near = near[np.argsort(-dist[near], kind="stable")]
+        out.append([int(best)] + [int(i) for i in near if i != best][:2])
+    return out
+
+
+def _oracle(b, res, gp, j, g_radii, g_centre):
+    """The oracle's gradients of instance j, one per choice of the radius
+    samples among ties, and the smallest decision margin of the samples its
+    descent touched."""
+    inst = PT.as_f32_instance(b.instances[j])
+    off, end = res["db"].sample_off_host[j], res["db"].sample_off_host[j + 1]
+    poses = res["poses"][off:end].cpu().numpy()
+    mask = res["mask"][off:end].cpu().numpy()
+    trace = res["trace"][j].cpu().numpy()
+    s0 = int(np.nonzero(mask & 1)[0][0])
+    C = res["centre"][j].cpu().numpy().astype(np.float64)
+    cand_D, cand_d = _radius_candidates(poses, mask, C)
+    op = PT.oracle_params(gp)
+    grads = []
+    for sD in cand_D:
+        for sd in cand_d:
+            ora = oracle_backward(inst, op, trace, s0, sD, sd, g_radii[j], g_centre[j])
+            grads.append(np.concatenate([x.ravel() for x in ora]))
+    ids = sorted(set(trace[:, 0].tolist()) | set(trace[:, 1].tolist()) | {s0} | set(cand_D) | set(cand_d))
+    margin = float(decision_margins(inst, op, ids).min())
+    return grads, margin
+
+
+def _rel(g, kof, kend, grads):
+    """Relative error against the closest of the oracle's gradients."""
+    a = np.concatenate([x[kof:kend].ravel() for x in g])
+    return min(float(np.linalg.norm(a - o) / max(1e-12, np.linalg.norm(o))) for o in grads)
+
+
 _CASES = {
     # 2D-3D, N = 12, 65,536 samples, 40 iterations (80 passes on the tape)
-    "c2": (lambda: W.config_c2(0), 40),
+    "c2": (lambda: W.config_c2(0), 40, None),
     # 2D-3D, N = 24, 20 iterations: most samples pulled in by bisection
-    "c4-64k": (lambda: W.config_c4(0, n_samples=65536), 20),
+    "c4-64k": (lambda: W.config_c4(0, n_samples=65536), 20, None),
     # the headline instances (N = 48) at 2^16 samples, 50 iterations
-    "c5-4": (lambda: W.config_c5(0, n_inst=4, n_samples=1 << 16), 50),
-    # both kinds in one batch (3D-3D stays in forward mode)
-    "mixed-10": (lambda: W.config_c3(3, n_inst=10, m_range=(2000, 8000), n_range=(6, 48)), 30),
-    # 160 iterations (320 passes): the largest tape
-    "c1-2d-160": (lambda: W.Batch([W.make_2d3d(np.random.default_rng(9), 10, 2.0, (5.0, 20.0), 4096)]), 160),
+    "c5-4": (lambda: W.config_c5(0, n_inst=4, n_samples=1 << 16), 50, None),
+    # both kinds in one batch
+    "mixed-10": (lambda: W.config_c3(3, n_inst=10, m_range=(2000, 8000), n_range=(6, 48)), 30, None),
+    # 3D-3D, N = 8, 1,024 samples, 50 iterations
+    "c1": (lambda: W.config_c1(0), 50, None),
+    # 3D-3D after 3 iterations: most samples pulled in by bisection
+    "c1-3it": (lambda: W.config_c1(1), 3, None),
+    # instances of the 512-instance batch's generator (N up to 48, semi-axes
+    # down to 3 px, both kinds), among them two 2D-3D instances whose active
+    # samples end a float32 recomputation with a clamp decision on the other
+    # side of its threshold, and two 3D-3D ones where differentiating the
+    # polar factor's Jacobi sweeps (the forward mode) is off by several 1e-3
+    "c3-48": (lambda: W.config_c3(0, n_inst=48), 50, [4, 9, 17, 29, 44]),
+    # 140 iterations (280 passes): the largest tape that fits the sweep's LDS
+    "c1-2d-140": (lambda: W.Batch([W.make_2d3d(np.random.default_rng(9), 10, 2.0, (5.0, 20.0), 4096)]), 140, None),
 }
 
 
 @pytest.mark.parametrize("case", sorted(_CASES))
-def test_reverse_sweep_equals_forward_mode(case):
+def test_reverse_sweep_matches_oracle(case):
     import paper_2403_09990_amd as P
-    _log("case: reverse vs forward tangents", case)
-    make, iters = _CASES[case]
+    _log("case: reverse sweep vs oracle", case)
+    make, iters, which = _CASES[case]
     b = make()
     gp = P.purse_default_params(n_iters=iters)
     res = PT.run_gpu(b, gp)
@@ -69,8 +141,15 @@ def test_reverse_sweep_equals_forward_mode(case):
     assert ok.any()
     for name, a, c in zip(("g_centres", "g_shapes", "g_bounds"), rev, fwd):
         assert np.array_equal(np.isnan(a), np.isnan(c)), name
-        a, c = np.nan_to_num(a), np.nan_to_num(c)
-        scale = max(np.abs(c).max(), 1e-12)
-        err = np.abs(a - c).max() / scale
-        _log(name, "max |rev - fwd| / max |fwd| =", err, "scale", scale)
-        assert err <= RTOL, (name, err)
+    js = [j for j in (range(b.n_inst) if which is None else which) if ok[j]]
+    ko = res["db"].kp_off_host
+    for j in js:
+        grads, margin = _oracle(b, res, gp, j, g_radii, g_centre)
+        r_rev = _rel(rev, ko[j], ko[j + 1], grads)
+        r_fwd = _rel(fwd, ko[j], ko[j + 1], grads)
+        kind = b.instances[j].kind
+        _log("instance", j, "kind", kind, "rel(rev, oracle) %.3g  rel(fwd, oracle) %.3g  margin %.2g" % (
+            r_rev, r_fwd, margin))
+        assert r_rev <= RTOL, (j, r_rev)
+        if margin >= HAZARD and kind == PURSE_KIND_2D3D:
+            assert r_fwd <= RTOL, (j, r_fwd)
