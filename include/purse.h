@@ -111,11 +111,20 @@ typedef int32_t purse_status;
                                      wavefronts per SIMD, each workgroup taking its next tile of the
                                      heaviest-first schedule from an atomic counter until none is left
                                      (the same samples; speed only) */
-#define PURSE_FLAG_FORWARD_TANGENTS 1024 /* purse_megb_backward: differentiate the 2D-3D trajectories in
-                                           forward mode, one re-run per input direction (6N per active
-                                           sample), instead of one reverse sweep per active sample (the
-                                           default while n_iters * n_gn <= 320); the same derivative to
-                                           float32 rounding */
+#define PURSE_FLAG_FORWARD_TANGENTS 1024 /* purse_megb_backward: differentiate the trajectories in
+                                           forward mode, one float32 re-run per input direction (6N or 4N
+                                           per active sample), instead of one reverse sweep per active
+                                           sample (the default while the sweep's tape and decisions fit
+                                           64 KB of LDS: 2D-3D up to about 280 Gauss-Newton passes, 3D-3D
+                                           up to 256 iterations); the reverse sweep takes its decisions
+                                           from a float64 recomputation, the forward mode from float32
+                                           ones, so the two differ where a decision sits within float32
+                                           rounding of its threshold */
+#define PURSE_FLAG_SERIAL_GROUPS 4096 /* purse_sample: launch the three trajectory launch groups (3D-3D;
+                                        2D-3D with the unrolled or lane-group loop; 2D-3D with the
+                                        general loop) one after the other on the caller's stream instead
+                                        of concurrently on it and two auxiliary streams (the same
+                                        samples; speed only) */
 
 /*
  * A ragged batch of PURSE instances.  Instance j owns keypoints

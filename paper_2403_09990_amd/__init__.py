@@ -12,7 +12,7 @@ from typing import Optional
 
 from . import _native
 from ._native import (PURSE_FLAG_EXACT_MEB, PURSE_FLAG_FORCE_FP64_POLAR, PURSE_FLAG_FORWARD_TANGENTS,
-                      PURSE_FLAG_WORK_QUEUE, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
+                      PURSE_FLAG_WORK_QUEUE, PURSE_FLAG_SERIAL_GROUPS, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_NO_PRUNING,  # noqa: F401
                       PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_MATRIX_COTANGENT, PURSE_FLAG_PAIR_LANES,
                       PURSE_FLAG_QUAD_LANES, PURSE_BWD_BAD_TRACE, PURSE_BWD_EMPTY, PURSE_BWD_NON_FINITE,
                       PURSE_BWD_OK, PURSE_BWD_OVERFLOW, PURSE_BWD_STALE,

@@ -47,6 +47,7 @@ PURSE_FLAG_MATRIX_COTANGENT = 256
 PURSE_FLAG_EXACT_MEB = 512
 PURSE_FLAG_FORWARD_TANGENTS = 1024
 PURSE_FLAG_WORK_QUEUE = 2048
+PURSE_FLAG_SERIAL_GROUPS = 4096
 
 EXPORTED = ("purse_default_params", "purse_workspace_size", "purse_sample", "purse_sample_noalloc",
             "purse_megb", "purse_megb_backward", "purse_walk_default_params", "purse_walk_workspace_size",

@@ -7,9 +7,11 @@ instances of at most 16 keypoints, the keypoint loop (unrolled; the general
 one with PURSE_FLAG_GENERIC_LOOP; two or four lanes per trajectory with
 PURSE_FLAG_PAIR_LANES or PURSE_FLAG_QUAD_LANES) change its speed; the last
 three change float32 rounding only.  A second stage tries, on the fastest of
-those, the persistent work-queue kernels (PURSE_FLAG_WORK_QUEUE) and caps of
-4 and 2 resident wavefronts per SIMD (params.waves_per_simd), which change
-speed only.
+those, the persistent work-queue kernels (PURSE_FLAG_WORK_QUEUE), caps of 4
+and 2 resident wavefronts per SIMD (params.waves_per_simd) and the launch
+groups one after the other on one stream (PURSE_FLAG_SERIAL_GROUPS; by
+default they run concurrently, which overlaps their tails on mixed batches
+but costs a fork and a join on single-group ones), which change speed only.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -21,16 +23,17 @@ import os
 from typing import Optional
 
 from . import (PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_INSTANCE_ORDER, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES,
-               PURSE_FLAG_WORK_QUEUE, purse_default_params, purse_sample)
+               PURSE_FLAG_SERIAL_GROUPS, PURSE_FLAG_WORK_QUEUE, purse_default_params, purse_sample)
 
 TILES = (64, 128, 256)
 ORDERS = (0, PURSE_FLAG_INSTANCE_ORDER)
 LOOPS = (0, PURSE_FLAG_GENERIC_LOOP, PURSE_FLAG_PAIR_LANES, PURSE_FLAG_QUAD_LANES)
 SMALL_N = 16
 _TUNED = (PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_LANES | PURSE_FLAG_QUAD_LANES |
-          PURSE_FLAG_WORK_QUEUE)
+          PURSE_FLAG_WORK_QUEUE | PURSE_FLAG_SERIAL_GROUPS)
 # second stage, on the fastest tile / order / loop: (flags, waves per SIMD)
-STAGE2 = ((PURSE_FLAG_WORK_QUEUE, 0), (0, 4), (0, 2))
+STAGE2 = ((PURSE_FLAG_WORK_QUEUE, 0), (0, 4), (0, 2), (PURSE_FLAG_SERIAL_GROUPS, 0),
+          (PURSE_FLAG_SERIAL_GROUPS | PURSE_FLAG_WORK_QUEUE, 0))
 
 
 def default_cache_path() -> str:
@@ -90,6 +93,8 @@ def _name(tile, flags, waves=0):
     name = "%d/%s/%s" % (tile, "instance" if flags & PURSE_FLAG_INSTANCE_ORDER else "heaviest-first", loop)
     if flags & PURSE_FLAG_WORK_QUEUE:
         name += "/queue"
+    if flags & PURSE_FLAG_SERIAL_GROUPS:
+        name += "/serial"
     if waves:
         name += "/%dwaves" % waves
     return name

@@ -143,8 +143,9 @@ purse_status sample_into(const purse_batch *b, const purse_params *p, float *pos
   const int tile = p->tile ? p->tile : 256;
   if (purse::sample_grid(b->total_samples, b->n_inst, tile / 2) > INT32_MAX)
     return fail(PURSE_E_BAD_ARG, "too many sample tiles for one launch");
-  purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile, b->total_samples,
-                       p->waves_per_simd, st);
+  const hipError_t e = purse::launch_sample(db, dp, inst, kp, at<int32_t>(ws, L.sched), poses, mask, tile,
+                                            b->total_samples, p->waves_per_simd, st);
+  if (e != hipSuccess) return hip_check(e, "sampler stream join");
   return hip_check(hipGetLastError(), "sampler launch");
 }
 

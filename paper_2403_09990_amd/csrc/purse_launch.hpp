@@ -16,10 +16,13 @@ int64_t sample_grid(int64_t total_samples, int n_inst, int tile);
 // Builds the tile schedule (sched: sched_ints(n_inst) int32 per kind, then
 // one work-queue counter per kind) and runs both kinds' trajectories; tile:
 // samples per workgroup (64, 128 or 256); waves_per_simd: residency cap (0:
-// none).
-void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
-                   float *poses, uint8_t *mask, int tile, int64_t grid_samples, int waves_per_simd,
-                   hipStream_t stream);
+// none).  The launch groups run on the stream and two auxiliary streams
+// unless PURSE_FLAG_SERIAL_GROUPS; returns an error (after launching the
+// work) if the auxiliary streams' join could not be recorded; launch errors
+// are left to hipGetLastError.
+hipError_t launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp,
+                         int32_t *sched, float *poses, uint8_t *mask, int tile, int64_t grid_samples,
+                         int waves_per_simd, hipStream_t stream);
 
 // ckpt: the rotation iterates C_0, C_ck, ... of every descent, left for the
 // backward ([n_inst][ckpt_count] quaternions) with their trace signature in rec.

@@ -10,6 +10,7 @@
 // heaviest tiles start first and the tail of the launch is made of light ones
 // (longest-processing-time-first list scheduling).
 #include <algorithm>
+#include <mutex>
 
 #include "purse_launch.hpp"
 #include "purse_traj.hpp"
@@ -245,10 +246,57 @@ int64_t sample_grid(int64_t total_samples, int n_inst, int tile) {
   return total_samples / tile + n_inst;
 }
 
-void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp, int32_t *sched,
-                   float *poses, uint8_t *mask, int tile, int64_t grid_samples, int waves_per_simd,
-                   hipStream_t stream) {
+namespace {
+
+// Two auxiliary streams (default priority) and three events per device for
+// the concurrent launch groups, created on first use and kept until the
+// process ends.
+struct GroupAux {
+  hipStream_t s[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+  bool ok = false, tried = false;
+};
+std::mutex g_group_mu;
+GroupAux g_group[64];
+
+GroupAux *group_aux() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  GroupAux &a = g_group[dev];
+  if (!a.tried) {
+    a.tried = true;
+    bool ok = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = hipStreamCreateWithFlags(&a.s[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming) == hipSuccess;
+    a.ok = ok;
+  }
+  return a.ok ? &a : nullptr;
+}
+
+}  // namespace
+
+hipError_t launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, const KpRec *kp,
+                         int32_t *sched, float *poses, uint8_t *mask, int tile, int64_t grid_samples,
+                         int waves_per_simd, hipStream_t stream) {
   hipLaunchKernelGGL(k_schedule, dim3(1), dim3(kSchedBlock), 0, stream, inst, b.n_inst, tile, p.flags, sched);
+  // The three launch groups write disjoint samples and read only the
+  // prologue's records and the schedules: they run concurrently on the
+  // caller's stream and two auxiliary streams (a fork and a join by events,
+  // which graph capture records as edges), so one group's tail overlaps the
+  // others' work.  Serially on the caller's stream when asked or when the
+  // auxiliary streams could not be created or forked to.
+  std::unique_lock<std::mutex> lk(g_group_mu);
+  GroupAux *aux = (p.flags & PURSE_FLAG_SERIAL_GROUPS) ? nullptr : group_aux();
+  hipStream_t gs[3] = {stream, stream, stream};
+  if (aux && hipEventRecord(aux->fork, stream) == hipSuccess &&
+      hipStreamWaitEvent(aux->s[0], aux->fork, 0) == hipSuccess &&
+      hipStreamWaitEvent(aux->s[1], aux->fork, 0) == hipSuccess) {
+    gs[1] = aux->s[0];
+    gs[2] = aux->s[1];
+  } else {
+    aux = nullptr;
+  }
   // waves per SIMD: at most 8 resident (the hardware's limit), or the cap,
   // which each workgroup's LDS padding enforces: just over the share of the
   // compute unit's LDS that would admit one more workgroup, within the
@@ -297,16 +345,24 @@ void launch_sample(const DevBatch &b, const DevParams &p, const InstRec *inst, c
                        b.n_inst, p, poses, mask);
   }
   if (queue) {
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, true>), grid, dim3(tile), lds, stream, inst, kp, sched, b.n_inst,
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, true>), grid, dim3(tile), lds, gs[1], inst, kp, sched, b.n_inst,
                        p, poses, mask);
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, true>), grid, dim3(tile), lds, stream, inst, kp, sched, b.n_inst,
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, true>), grid, dim3(tile), lds, gs[2], inst, kp, sched, b.n_inst,
                        p, poses, mask);
   } else {
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, false>), grid, dim3(tile), lds, stream, inst, kp, sched,
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_2D3D, 0, false>), grid, dim3(tile), lds, gs[1], inst, kp, sched,
                        b.n_inst, p, poses, mask);
-    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, false>), grid, dim3(tile), lds, stream, inst, kp, sched,
+    hipLaunchKernelGGL((k_sample<PURSE_KIND_3D3D, 0, false>), grid, dim3(tile), lds, gs[2], inst, kp, sched,
                        b.n_inst, p, poses, mask);
   }
+  if (aux) {
+    for (int k = 0; k < 2; ++k) {
+      hipError_t e = hipEventRecord(aux->join[k], aux->s[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, aux->join[k], 0);
+      if (e != hipSuccess) return e;  // the caller's stream is not joined to that group
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace purse

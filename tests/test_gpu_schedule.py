@@ -62,10 +62,13 @@ def test_every_schedule_writes_every_sample_identically():
                 assert (poses[off[-2]:off[-1]] == 0).all() and (mask[off[-2]:off[-1]] == 0).all()
             else:
                 assert torch.equal(poses, ref[0]) and torch.equal(mask, ref[1]) and torch.equal(status, ref[2])
-    # persistent work-queue kernels and residency caps: the same samples
+    # persistent work-queue kernels, residency caps and the launch groups one
+    # after the other on the caller's stream: the same samples
     for tile in (64, 256):
         for flags, waves in ((P.PURSE_FLAG_WORK_QUEUE, 0), (0, 2), (P.PURSE_FLAG_WORK_QUEUE, 4),
-                             (P.PURSE_FLAG_WORK_QUEUE | P.PURSE_FLAG_INSTANCE_ORDER, 1)):
+                             (P.PURSE_FLAG_WORK_QUEUE | P.PURSE_FLAG_INSTANCE_ORDER, 1),
+                             (P.PURSE_FLAG_SERIAL_GROUPS, 0),
+                             (P.PURSE_FLAG_SERIAL_GROUPS | P.PURSE_FLAG_WORK_QUEUE, 0)):
             _log("case: schedule tile", tile, "flags", flags, "waves", waves)
             gp = P.purse_default_params(n_iters=15, tile=tile, flags=flags, waves_per_simd=waves)
             poses, mask, status = _run(P, db, gp)
