@@ -347,14 +347,9 @@ __device__ __forceinline__ bool gn_pass2d_unrolled(const KPL &kpl, int n, const 
 
 // NMAX > 0: at most NMAX keypoints, loops unrolled (gn_pass2d_unrolled).
 template <int NMAX, typename T, typename KPL>
-__device__ __forceinline__ bool traj2d(const KPL &kpl, int n, const float Ks[4], const T oc[3], int n_iters,
+__device__ __forceinline__ bool traj2d(const KPL &kpl, int n, const float K[4], const T oc[3], int n_iters,
                                        int n_gn, float z_min, PoseT<T> &x) {
   const float band = ClampBand<T>::v;
-  // The principal point in vector registers for the whole trajectory: a
-  // projection's u = fx (X / Z) + cx then takes one scalar operand (fx), as a
-  // vector instruction can, instead of a copy of cx per keypoint and pass.
-  float K[4] = {Ks[0], Ks[1], Ks[2], Ks[3]};
-  asm volatile("" : "+v"(K[2]), "+v"(K[3]));
   for (int it = 0; it < n_iters; ++it) {
     if constexpr (NMAX > 0) {
       T tq[NMAX][2];
