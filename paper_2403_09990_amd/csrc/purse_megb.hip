@@ -33,16 +33,16 @@ constexpr int kBins = 256;
 constexpr int kGlobalSteps = 64;
 constexpr int kChainBlock = 512;  // threads of a pipelined chain workgroup (the larger variant)
 constexpr int kChainWaves = kChainBlock / 64;
-// Sequential chains run in workgroups of 128 threads with a shell of 1536
-// entries, so that five of them share a compute unit (LDS, 128 VGPRs): the
-// shell steps run in wave 0 alone, and a second wave streams the rescans
-// about as fast as four (measured: 1.6 % faster than four waves on a batch of
-// 1,024 chains, 12 % faster than one); pipelined ones need the eight waves
-// and keep the larger shell.
-template <bool PIPE>
-constexpr int chain_block() { return PIPE ? kChainBlock : 128; }
-template <bool PIPE>
-constexpr int chain_cap() { return PIPE ? 7168 : 1536; }
+// Variants of the chain workgroup:
+//  - kChainWide: eight waves, a shell of 7168 entries and 256 VGPRs (one
+//    chain per compute unit);
+//  - kChainNarrow: four waves, a shell of 1280 entries and 128 VGPRs, so that
+//    four chains share a compute unit (LDS).
+constexpr int kChainWide = 1, kChainNarrow = 2;
+template <int V>
+constexpr int chain_block() { return V == kChainWide ? kChainBlock : 256; }
+template <int V>
+constexpr int chain_cap() { return V == kChainWide ? 7168 : 1280; }
 constexpr int kUnroll = 8;
 constexpr int kCap = 7168;
 constexpr int kMaxChunks = kCap / 64;
@@ -555,7 +555,7 @@ struct ChainShared {
   int (*red_i)[kChainWaves];
 };
 
-template <int CHAIN, bool PIPE>
+template <int CHAIN, int V>
 __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *__restrict__ sample_off,
                                           int64_t max_m, const float4 *__restrict__ pts, MegbRec *rec,
                                           float *dref_all, int64_t total_samples, int32_t *trace,
@@ -576,11 +576,16 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   __shared__ int pl_go;
 
   constexpr int chain = CHAIN;
-  constexpr int BLK = chain_block<PIPE>(), NW = BLK / 64;
-  // elements per thread and round in the passes over d_ref: the pipelined
-  // variant has the registers to keep more loads in flight, which these
+  constexpr int BLK = chain_block<V>(), NW = BLK / 64;
+  // verifier waves of a pipelined segment: every wave but wave 0 and, in the
+  // eight-wave group, the one that shares wave 0's SIMD (waves go round the
+  // four SIMDs)
+  constexpr int kSkipWave = NW > 4 ? kVerifySkip : NW;
+  constexpr int kVerifiers = NW > 4 ? NW - 2 : NW - 1;
+  // elements per thread and round in the passes over d_ref: the wide variant
+  // has the registers to keep more loads in flight, which these
   // latency-bound passes of one workgroup need
-  constexpr int UF = PIPE ? 32 : kUnroll;
+  constexpr int UF = V == kChainWide ? 32 : kUnroll;
   const int j = blockIdx.x >> 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int64_t off, M64;
@@ -668,10 +673,10 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       float rref = 0.f;
 #pragma unroll
       for (int k = 0; k < NW; ++k) rref = fmaxf(rref, S.red_k[0][k]);
-      // (the sequential variant, which runs batches of more chains than
-      // compute units, keeps its registers for four chains per compute unit
-      // and leaves a stale global shell to full rescans)
-      if (PIPE && ep && !use_gs && i0 - sg.built_at >= kMinShellSteps) {
+      // (the narrow variant, which runs batches of more chains than compute
+      // units, keeps its registers for four chains per compute unit and
+      // leaves a stale global shell to full rescans)
+      if (V == kChainWide && ep && !use_gs && i0 - sg.built_at >= kMinShellSteps) {
         // ---------------------------------- rebuild the global shell at C_ref
         const float gw = rref / (float)kShellBins;
         if (gw > 0.f) {
@@ -1097,7 +1102,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               trv = lane == i - ib ? wi : trv;
               if (ACC) accumulate_iterate(C, chain, acc);
               ++i;
-              if (PIPE && SHORT && !ACC) {
+              if (SHORT && !ACC) {
                 last_w = wi;
                 const bool known = (__ballot(cand_id == wi) & 0xFFull) != 0ull;
                 const bool ins = !known && lane == nins;
@@ -1109,7 +1114,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               }
               if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
               if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
-              if (PIPE && SHORT && !ACC && stable >= backoff && end - i + 1 >= 2 * kPipeSteps) return kPipe;
+              if (SHORT && !ACC && stable >= backoff && end - i + 1 >= 2 * kPipeSteps) return kPipe;
             }
             return kRangeDone;
           };
@@ -1143,7 +1148,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
           for (int k = lane; k < 3; k += 64) pl_fail[k] = INT32_MAX;
         }
         __syncthreads();
-        if (!PIPE || !pl_go) break;
+        if (!pl_go) break;
         // ------------------------------------------------ pipelined segment
         const int pi0 = st_i, pend = last_plain;
         const int nrounds = (pend - pi0 + kPipeSteps) / kPipeSteps;
@@ -1254,13 +1259,12 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
               }
               if (r == nrounds - 1 && lane == 0) pl_Cend = Cs;
             }
-          } else if (r >= 1 && wave != kVerifySkip) {
-            // check the steps of round r - 1, one wave per step (not the wave
-            // that shares a SIMD with wave 0)
+          } else if (r >= 1 && wave != kSkipWave) {
+            // check the steps of round r - 1, one wave per step
             const int s_p = s_r - kPipeSteps, n_p = min(kPipeSteps, pend - s_p + 1);
             const int pslot = (r + 2) % 3;
-            const int vw = wave < kVerifySkip ? wave - 1 : wave - 2;
-            for (int k = vw; k < n_p; k += NW - 2) {
+            const int vw = wave < kSkipWave ? wave - 1 : wave - 2;
+            for (int k = vw; k < n_p; k += kVerifiers) {
               const float4 Cv = pl_C[pslot][k];
               const int pid = pl_W[pslot][k];
               const float dC = drift(Cv);
@@ -1369,13 +1373,13 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
   }
 }
 
-// One workgroup of chain_block<PIPE>() threads per (instance, chain): even blocks
+// One workgroup of chain_block<V>() threads per (instance, chain): even blocks
 // run the rotation chain, odd blocks the translation chain.
-// The sequential variant (four waves, 128 VGPRs, a few spills outside the
-// step loop) lets four chains share each compute unit: a chain's steps run in
-// one wavefront, which leaves most issue slots free.
-template <bool PIPE>
-__global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
+// The narrow variant is held to 128 VGPRs (a few spills outside the step
+// loops), so that four chains share a compute unit: a chain's steps run in
+// one wavefront, which leaves most issue slots to the other chains' waves.
+template <int V>
+__global__ void __launch_bounds__(chain_block<V>(), V == kChainWide ? 1 : 4) k_megb_chain(const int64_t *__restrict__ sample_off, int64_t max_m,
                                                             const float4 *__restrict__ quat,
                                                             const float4 *__restrict__ trans, MegbRec *rec,
                                                             float *dref_all, int64_t total_samples,
@@ -1390,10 +1394,10 @@ __global__ void __launch_bounds__(chain_block<PIPE>(), PIPE ? 1 : 4) k_megb_chai
   __shared__ int red_i[2][kChainWaves];
   const ChainShared S{sh_pt, reinterpret_cast<int *>(sh_pt + cap), hist, cursor, chunk_ub, red_k, red_i};
   if (blockIdx.x & 1)
-    chain_run<1, PIPE>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
+    chain_run<1, V>(S, sample_off, max_m, trans, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
                        no_prune, gid, gpt, gstride);
   else
-    chain_run<0, PIPE>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
+    chain_run<0, V>(S, sample_off, max_m, quat, rec, dref_all, total_samples, trace, ckpt, ck, T, avg, cap,
                        no_prune, gid, gpt, gstride);
 }
 
@@ -1863,16 +1867,17 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
   hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      mask, rec, quat, trans);
-  // Pipelined shell steps trade extra work (every step's argmax checked on
-  // other wavefronts) for a shorter chain; they pay while the chains leave
-  // compute units idle, i.e. while there are at most as many chain
-  // workgroups as compute units.  The two variants keep shells of different
-  // capacities, which the first-phase kernel must know.
+  // The wide variant while there are at most as many chains as compute
+  // units, else the narrow one (measured on batches of 256-1,024 uneven
+  // instances: 1.4-2.3 times faster than the shell steps of one wave with no
+  // pipelined segments, which ran at the same four chains per compute unit).
+  // The variants keep shells of different capacities, which the first-phase
+  // kernel must know.
   int dev = 0, n_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     n_cu = 0;
-  const bool pipe = 2 * n <= n_cu;
-  const int cap = pipe ? chain_cap<true>() : chain_cap<false>();
+  const bool wide = 2 * n <= n_cu;
+  const int cap = wide ? chain_cap<kChainWide>() : chain_cap<kChainNarrow>();
   const size_t lds = (size_t)cap * (sizeof(float4) + sizeof(int));
   const int no_prune = (p.flags & PURSE_FLAG_NO_PRUNING) ? 1 : 0;
   const int64_t gstride = gshell_stride(total_samples, max_samples);
@@ -1887,14 +1892,14 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
                        max_samples, quat, trans, rec, es, dref, gid, gpt, gstride, p.megb_iters, p.megb_avg, cap,
                        no_prune);
   }
-  if (pipe)
-    hipLaunchKernelGGL(k_megb_chain<true>, dim3(2 * n), dim3(chain_block<true>()), lds, stream, b.sample_off,
-                       max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
-                       cap, no_prune, gid, gpt, gstride);
+  if (wide)
+    hipLaunchKernelGGL(k_megb_chain<kChainWide>, dim3(2 * n), dim3(chain_block<kChainWide>()), lds, stream,
+                       b.sample_off, max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters,
+                       p.megb_avg, cap, no_prune, gid, gpt, gstride);
   else
-    hipLaunchKernelGGL(k_megb_chain<false>, dim3(2 * n), dim3(chain_block<false>()), lds, stream, b.sample_off,
-                       max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters, p.megb_avg,
-                       cap, no_prune, gid, gpt, gstride);
+    hipLaunchKernelGGL(k_megb_chain<kChainNarrow>, dim3(2 * n), dim3(chain_block<kChainNarrow>()), lds, stream,
+                       b.sample_off, max_samples, quat, trans, rec, dref, total_samples, trace, ckpt, ck, p.megb_iters,
+                       p.megb_avg, cap, no_prune, gid, gpt, gstride);
   hipLaunchKernelGGL(k_megb_sign, dim3(n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      trace, rec, p.megb_iters, ck);
   if (p.flags & PURSE_FLAG_EXACT_MEB)

@@ -303,13 +303,17 @@ def test_megb_ties_take_the_lowest_id():
     assert torch.equal(full["radii"], pr["radii"])
 
 
-def test_megb_sequential_variant_is_exact():
-    """A batch with more chains than compute units runs the sequential shell
-    steps (four chains per compute unit): bitwise the trace, centre and radii
-    of scanning every sample at every step."""
-    _log("case: sequential variant, 160 instances")
+@pytest.mark.parametrize("n_inst", [160, 600])
+def test_megb_shared_cu_variants_are_exact(n_inst):
+    """Batches with more chains than compute units run four chain workgroups
+    per compute unit: pipelined in narrow workgroups up to four chains per
+    compute unit (160 instances: 320 chains), sequential beyond (600
+    instances: 1,200 chains).  Either gives bitwise the trace, centre and
+    radii of scanning every sample at every step."""
+    _log("case: shared compute units,", n_inst, "instances")
     import paper_2403_09990_amd as P
-    b = W.config_c3(4, n_inst=160, m_range=(1024, 4096), n_range=(6, 16))
+    mr = (1024, 4096) if n_inst <= 160 else (1024, 2048)
+    b = W.config_c3(4, n_inst=n_inst, m_range=mr, n_range=(6, 16))
     gp = _params(n_iters=20)
     res = PT.run_gpu(b, gp)
     gp2 = _params(n_iters=20, flags=P.PURSE_FLAG_NO_PRUNING)
