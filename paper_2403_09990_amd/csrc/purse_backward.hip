@@ -2575,7 +2575,16 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
     }
   }
   // the tangent kernels walk lists of the (instance, active sample,
-  // direction block) items the active sets need
+  // direction block) items the active sets need: the 2D-3D ones on the
+  // caller's stream and the 3D-3D ones on the auxiliary stream beside them
+  // (they touch disjoint items and contributions), joined before the
+  // reduction
+  std::unique_lock<std::mutex> lk(g_aux_mu);
+  Aux *a = aux_stream();
+  const bool fork = a && hipEventRecord(a->fork, stream) == hipSuccess &&
+                    hipStreamWaitEvent(a->s, a->fork, 0) == hipSuccess;
+  if (!fork) lk.unlock();
+  hipStream_t s3 = fork ? a->s : stream;
   // 2D-3D: one reverse sweep per active sample while the tape fits in LDS,
   // else (or when asked) one forward-mode re-run per input direction
   const int passes = p.n_iters * p.n_gn;
@@ -2596,16 +2605,21 @@ hipError_t launch_backward(const DevBatch &b, const DevParams &p, const float *p
   const size_t lds3 = rev_lds(p.n_iters, p.n_iters);
   const bool reverse3 = lds3 <= kRevLds && !(p.flags & PURSE_FLAG_FORWARD_TANGENTS);
   if (reverse3) {
-    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D,
+    hipLaunchKernelGGL(k_bwd_items_rev, dim3(1), dim3(1024), 0, s3, b, inst, recs, (int)PURSE_KIND_3D3D,
                        items + (n + 1));
     const size_t lds = lds3;
-    hipLaunchKernelGGL(k_bwd_rev3d, dim3(kItemGrid), dim3(64), lds, stream, b, p, inst, kp, recs, items + (n + 1),
+    hipLaunchKernelGGL(k_bwd_rev3d, dim3(kItemGrid), dim3(64), lds, s3, b, p, inst, kp, recs, items + (n + 1),
                        tan, contrib, max_dirs);
   } else {
-    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, stream, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
+    hipLaunchKernelGGL(k_bwd_items, dim3(1), dim3(1024), 0, s3, b, inst, recs, (int)PURSE_KIND_3D3D, 1,
                        items + (n + 1));
-    hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, stream, b, p, inst, kp, recs,
+    hipLaunchKernelGGL(k_bwd_traj<PURSE_KIND_3D3D>, dim3(kItemGrid), dim3(64), 0, s3, b, p, inst, kp, recs,
                        items + (n + 1), tan, contrib, max_dirs);
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(a->join, a->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, a->join, 0);
+    if (e != hipSuccess) return e;  // no join: the reduction is not launched
   }
   hipLaunchKernelGGL(k_bwd_reduce, dim3(n), dim3(kMaxDirs), 0, stream, b, inst, recs, contrib, max_dirs, g_centres,
                      g_shapes, g_bounds, bwd_status);
