@@ -303,17 +303,17 @@ def test_megb_ties_take_the_lowest_id():
     assert torch.equal(full["radii"], pr["radii"])
 
 
-@pytest.mark.parametrize("n_inst", [160, 600])
-def test_megb_shared_cu_variants_are_exact(n_inst):
-    """Batches with more chains than compute units run four chain workgroups
-    per compute unit: pipelined in narrow workgroups up to four chains per
-    compute unit (160 instances: 320 chains), sequential beyond (600
-    instances: 1,200 chains).  Either gives bitwise the trace, centre and
-    radii of scanning every sample at every step."""
-    _log("case: shared compute units,", n_inst, "instances")
+@pytest.mark.parametrize("n_inst,m_range", [(160, (1024, 4096)), (600, (1024, 2048)), (140, (32768, 40000))])
+def test_megb_shared_cu_variants_are_exact(n_inst, m_range):
+    """Batches with more chains than compute units run the narrow pipelined
+    chain workgroups, four per compute unit: 160 instances (320 chains, all
+    resident), 600 instances (1,200 chains, more than fit at once), and 140
+    instances of at least 32,768 samples (the first phase and the global
+    shell, which the narrow variant never rebuilds).  Each gives bitwise the
+    trace, centre and radii of scanning every sample at every step."""
+    _log("case: shared compute units,", n_inst, "instances, M in", m_range)
     import paper_2403_09990_amd as P
-    mr = (1024, 4096) if n_inst <= 160 else (1024, 2048)
-    b = W.config_c3(4, n_inst=n_inst, m_range=mr, n_range=(6, 16))
+    b = W.config_c3(4, n_inst=n_inst, m_range=m_range, n_range=(6, 16))
     gp = _params(n_iters=20)
     res = PT.run_gpu(b, gp)
     gp2 = _params(n_iters=20, flags=P.PURSE_FLAG_NO_PRUNING)
