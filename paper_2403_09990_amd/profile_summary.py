@@ -203,8 +203,8 @@ _F32_OPS = {"SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_MUL_F32": 1, "SQ_INSTS_VA
 
 def valu(dirname, kernel, out=None, cmd=None):
     """FP32 operations per dispatch of a kernel from the F32 VALU instruction
-    counters: 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions (packed
-    FP32 instructions are not generated by this build), stamped with the hash
+    counters: 64 lanes x (2 FMA + MUL + ADD + TRANS) wave instructions (the
+    library is compiled with packed FP32 instructions disabled), stamped with the hash
     of the kernel's sources."""
     c = counters(dirname, kernel)
     missing = [k for k in _F32_OPS if k not in c]
