@@ -48,11 +48,21 @@ constexpr int kCap = 7168;
 constexpr int kMaxChunks = kCap / 64;
 constexpr int kRecentreChunks = 4;  // a step scanning more chunks than this ...
 constexpr int kMinShellSteps = 64;   // ... at least this many steps after a rescan triggers a new one
+constexpr int kRecentreDiv = 2048;   // (more chunks, up to kRecentreMax, when a rescan streams more
+constexpr int kRecentreMax = 32;     //  entries: one chunk per kRecentreDiv of them)
 constexpr int kPipeSteps = 64;       // steps per round of a pipelined segment (one per lane)
 constexpr int kVerifySkip = 4;       // wave on wave 0's SIMD (waves go round the 4 SIMDs)
 constexpr int kPipeMinSeq = 8;       // steps with no new winner before a pipelined segment, doubled after
 constexpr int kPipeMaxSeq = 256;     // each failed prediction up to this
 static_assert(kCap % 64 == 0, "chunks of 64 tile the shell");
+
+// Chunks a shell step may scan before its stage ends and the chain rescans
+// (once kMinShellSteps steps have been taken since the last rescan).  A
+// rescan that streams n_src entries costs in proportion to them, so the more
+// it streams the more chunks a step may scan first.
+__device__ __forceinline__ int recentre_chunks(int n_src) {
+  return min(kRecentreMax, max(kRecentreChunks, n_src / kRecentreDiv));
+}
 
 __device__ __forceinline__ bool feasible_pt(float4 a, int chain) {
   return chain == 0 ? (a.x >= 0.f) : (a.w != 0.f);
@@ -636,6 +646,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.f;
   bool stalled = false;
+  int recentre = kRecentreChunks;  // chunks a shell step may scan (set by each rescan)
   int stage_groups = 0;
 
   while (true) {
@@ -652,6 +663,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
       const float4 *src = from_gs ? gpt : D;
       const int n_src = from_gs ? sg.n : M;
       const int n_src_feas = from_gs ? sg.n : n_feas;
+      recentre = recentre_chunks(n_src);
       float mx = 0.f;
       stream_rounds<BLK>(src, n_src, make_float4(-2.f, 0.f, 0.f, 0.f), [&](const float4 *a, int s0) {
 #pragma unroll
@@ -1112,7 +1124,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 nins = known ? nins : ((nins + 1) & 7);
                 stable = known ? stable + 1 : 0;
               }
-              if (g > kRecentreChunks && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
+              if (g > recentre && i - i0 > kMinShellSteps) return kStageEnds;  // re-centre the shell
               if (W == 1 && g > 1 && ++misses * 4 > i - i0 && i - i0 >= 16) return kGoWide;
               if (SHORT && !ACC && stable >= backoff && end - i + 1 >= 2 * kPipeSteps) return kPipe;
             }
@@ -1297,7 +1309,7 @@ __device__ __forceinline__ void chain_run(const ChainShared &S, const int64_t *_
                 if (theta >= 0.f && !beats(wk, theta)) ok = false;
                 // a step that needs many chunks goes to a sequential segment,
                 // which re-centres the shell
-                if (g > kRecentreChunks && s_p + k - i0 > kMinShellSteps) ok = false;
+                if (g > recentre && s_p + k - i0 > kMinShellSteps) ok = false;
               }
               if (ok) {
                 const unsigned long long win = __ballot(bk == wk);
