@@ -31,6 +31,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBins = 256;
 constexpr int kGlobalSteps = 64;
+constexpr int kPassPer = 4;  // samples per thread of the per-sample passes (k_megb_prep, k_megb_radii)
 constexpr int kChainBlock = 512;  // threads of a pipelined chain workgroup (the larger variant)
 constexpr int kChainWaves = kChainBlock / 64;
 // Variants of the chain workgroup:
@@ -498,20 +499,40 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
   const int j = blockIdx.y;
   int64_t off, M;
   sample_range(sample_off, j, total, max_m, off, M);
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * kPassPer) + threadIdx.x;
   __shared__ int cnt[kWaves];
   __shared__ int firsts[kWaves];
   int feas = 0, first = INT32_MAX;
-  if (s < M) {
+  // kPassPer samples per thread, kBlock apart: the masks first, then the
+  // poses of the feasible ones, every load of a round in flight together
+  uint8_t m[kPassPer];
+#pragma unroll
+  for (int u = 0; u < kPassPer; ++u) {
+    const int64_t s = s0 + u * kBlock;
+    m[u] = s < M ? mask[off + s] : (uint8_t)0;
+  }
+  float4 a[kPassPer], b[kPassPer], c[kPassPer];
+#pragma unroll
+  for (int u = 0; u < kPassPer; ++u) {
+    const int64_t s = s0 + u * kBlock;
+    if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
+      const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * (off + s));
+      a[u] = pp[0];
+      b[u] = pp[1];
+      c[u] = pp[2];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPassPer; ++u) {
+    const int64_t s = s0 + u * kBlock;
+    if (s >= M) continue;
     const int64_t g = off + s;
-    if (mask[g] & PURSE_MASK_FEASIBLE) {
-      const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * g);
-      float4 a = pp[0], b = pp[1], c = pp[2];
-      float R[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x};
+    if (m[u] & PURSE_MASK_FEASIBLE) {
+      float R[9] = {a[u].x, a[u].y, a[u].z, a[u].w, b[u].x, b[u].y, b[u].z, b[u].w, c[u].x};
       quat[g] = quat_from_rot(R);
-      trans[g] = make_float4(c.y, c.z, c.w, 1.f);
-      feas = 1;
-      first = (int)s;
+      trans[g] = make_float4(c[u].y, c[u].z, c[u].w, 1.f);
+      ++feas;
+      first = min(first, (int)s);
     } else {
       quat[g] = make_float4(-2.f, 0.f, 0.f, 0.f);
       trans[g] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1420,21 +1441,46 @@ __global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict
   const int j = blockIdx.y;
   int64_t off, M;
   sample_range(sample_off, j, total, max_m, off, M);
-  const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * kPassPer) + threadIdx.x;
   __shared__ double red[2][kWaves];
   double fr = 0.0, ft = 0.0;
-  if (s < M && rec[j].first != INT32_MAX) {
-    const int64_t g = off + s;
-    if (mask[g] & PURSE_MASK_FEASIBLE) {
-      const float *P = poses + 12 * g;
-      const float *C = rec[j].centre;
-      for (int k = 0; k < 9; ++k) {
-        double d = (double)C[k] - (double)P[k];
-        fr += d * d;
+  if (rec[j].first != INT32_MAX) {
+    // kPassPer samples per thread, kBlock apart, loads in flight together
+    uint8_t m[kPassPer];
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+      const int64_t s = s0 + u * kBlock;
+      m[u] = s < M ? mask[off + s] : (uint8_t)0;
+    }
+    float4 pa[kPassPer], pb[kPassPer], pc[kPassPer];
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+      const int64_t s = s0 + u * kBlock;
+      if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
+        const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * (off + s));
+        pa[u] = pp[0];
+        pb[u] = pp[1];
+        pc[u] = pp[2];
       }
-      for (int k = 9; k < 12; ++k) {
-        double d = (double)C[k] - (double)P[k];
-        ft += d * d;
+    }
+    const float *C = rec[j].centre;
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+      const int64_t s = s0 + u * kBlock;
+      if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
+        const float P[12] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w, pb[u].x, pb[u].y,
+                             pb[u].z, pb[u].w, pc[u].x, pc[u].y, pc[u].z, pc[u].w};
+        double r = 0.0, t = 0.0;
+        for (int k = 0; k < 9; ++k) {
+          double d = (double)C[k] - (double)P[k];
+          r += d * d;
+        }
+        for (int k = 9; k < 12; ++k) {
+          double d = (double)C[k] - (double)P[k];
+          t += d * d;
+        }
+        fr = fmax(fr, r);
+        ft = fmax(ft, t);
       }
     }
   }
@@ -1876,7 +1922,7 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   const int ck = ckpt_spacing(p.ckpt_every);
   const int n = b.n_inst;
   hipLaunchKernelGGL(k_megb_init, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec);
-  dim3 grid((unsigned)((max_samples + kBlock - 1) / kBlock), (unsigned)n);
+  dim3 grid((unsigned)((max_samples + kBlock * kPassPer - 1) / (kBlock * kPassPer)), (unsigned)n);
   hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
                      mask, rec, quat, trans);
   // The wide variant while there are at most as many chains as compute
