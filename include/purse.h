@@ -28,11 +28,13 @@
  *    per-instance outcomes are written asynchronously to inst_status.
  *  - Concurrent calls sharing one workspace race; give each in-flight call
  *    its own workspace.
- *  - purse_megb_backward runs part of its work on an auxiliary stream of the
- *    current device (default priority; created with two events on the first
- *    call and kept until the process ends), forked from and joined back to
- *    `stream` by events, so the call stays ordered on `stream` and can be
- *    captured in a graph once that first call has happened outside capture.
+ *  - purse_megb_backward runs part of its work (the frame tangents, then the
+ *    3D-3D reverse sweeps) on an auxiliary stream of the current device, and
+ *    purse_sample two of its three trajectory launch groups on two others
+ *    (default priority; created with their events on the first call and kept
+ *    until the process ends), forked from and joined back to `stream` by
+ *    events, so every call stays ordered on `stream` and can be captured in a
+ *    graph once that first call has happened outside capture.
  */
 #ifndef PURSE_H
 #define PURSE_H
