@@ -1,9 +1,10 @@
 // Per-instance prologue: validation, keypoint records, centre fit (float64),
-// pivot and feasible anchor.  Two wavefronts per instance: the 2D-3D centre
-// fit is a float64 Gauss-Newton iteration from two starts, one start per
-// wavefront (formed by lane 0, iterated with one keypoint per lane), so the
-// two run on different SIMDs at once; everything else is serial in lane 0 of
-// wavefront 0.
+// pivot and feasible anchor.  Two wavefronts per instance: validation and the
+// keypoint records take one keypoint per lane of wavefront 0; the 2D-3D
+// centre fit is a float64 Gauss-Newton iteration from two starts, one start
+// per wavefront (formed by lane 0, iterated with one keypoint per lane), so
+// the two run on different SIMDs at once; the rest (Arun's fit, the pivot,
+// the anchor) is serial in lane 0 of wavefront 0.
 #include "purse_bwd_check.hpp"
 #include "purse_fit.hpp"
 #include "purse_launch.hpp"
@@ -24,39 +25,31 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
   __shared__ int64_t fp_ko;
   InstRec I;                                 // (lane 0 of wavefront 0)
   double ab[3] = {0, 0, 0};
-  if (tid == 0) {
-    I.kind = b.kind[j];
-    I.n_kp = b.n_kp[j];
-    I.kp_off = b.kp_off[j];
+  if (tid < 64) {
+    // ---- header: every lane of wavefront 0 reads it, lane 0 keeps the record
+    const int kind = b.kind[j];
+    const int n = b.n_kp[j];
+    const int64_t kp_off = b.kp_off[j];
     int64_t soff, sM;
     sample_range(b.sample_off, j, b.total_samples, b.max_samples, soff, sM);
-    I.sample_off = soff;
-    I.n_samples = sM;
-    const bool kp_ok = I.kp_off >= 0 && b.kp_off[j + 1] - I.kp_off == (int64_t)I.n_kp &&
-                       b.kp_off[j + 1] <= b.total_kp;
-    I.seed = b.seed[j];
-    I.has_anchor = 0;
-    I.status = PURSE_INST_OK;
-    for (int k = 0; k < 4; ++k) I.K[k] = (I.kind == PURSE_KIND_2D3D) ? b.intrinsics[4 * j + k] : 0.f;
-    for (int k = 0; k < 9; ++k) I.Rc[k] = I.Ra[k] = (k % 4 == 0) ? 1.f : 0.f;
-    for (int k = 0; k < 3; ++k) I.tc[k] = I.ta[k] = I.oc[k] = I.abar[k] = 0.f;
-    I.data_fp = 0ull;
-    const int n = I.n_kp;
-    const bool is2d = I.kind == PURSE_KIND_2D3D;
-    const int64_t ko = kp_ok ? I.kp_off : 0;
-    fp_n = (kp_ok && n >= 0 && n <= PURSE_MAX_KP) ? n : 0;
-    fp_ko = ko;
+    const bool kp_ok = kp_off >= 0 && b.kp_off[j + 1] - kp_off == (int64_t)n && b.kp_off[j + 1] <= b.total_kp;
+    const bool is2d = kind == PURSE_KIND_2D3D;
+    const int64_t ko = kp_ok ? kp_off : 0;
+    float K[4];
+    for (int k = 0; k < 4; ++k) K[k] = is2d ? b.intrinsics[4 * j + k] : 0.f;
     const float *a = b.model_pts + 3 * ko;
     const float *c = b.centres + 3 * ko;
     const float *L = b.shapes + 4 * ko;
     const float *beta = b.bounds + ko;
-    // ---- validation
-    if ((I.kind != PURSE_KIND_3D3D && !is2d) || !kp_ok || n < (is2d ? 6 : 3) || n > PURSE_MAX_KP ||
-        I.n_samples < 1 || n > b.max_kp) {
-      I.status = PURSE_INST_BAD_SIZE;
+    int status = PURSE_INST_OK;
+    // ---- validation: keypoint i on lane i (at most PURSE_MAX_KP = 64)
+    if ((kind != PURSE_KIND_3D3D && !is2d) || !kp_ok || n < (is2d ? 6 : 3) || n > PURSE_MAX_KP || sM < 1 ||
+        n > b.max_kp) {
+      status = PURSE_INST_BAD_SIZE;
     } else {
       bool good = true;
-      for (int i = 0; i < n && good; ++i) {
+      if (tid < n) {
+        const int i = tid;
         for (int r = 0; r < 3; ++r) good = good && finite_f(a[3 * i + r]);
         good = good && finite_f(c[3 * i]) && finite_f(c[3 * i + 1]) && (is2d || finite_f(c[3 * i + 2]));
         good = good && finite_f(beta[i]) && beta[i] >= 0.f;
@@ -67,19 +60,20 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
         }
       }
       if (is2d)
-        for (int k = 0; k < 4; ++k) good = good && finite_f(I.K[k]);
-      if (is2d) good = good && I.K[0] > 0.f && I.K[1] > 0.f;
-      if (!good) I.status = PURSE_INST_BAD_SHAPE;
+        for (int k = 0; k < 4; ++k) good = good && finite_f(K[k]);
+      if (is2d) good = good && K[0] > 0.f && K[1] > 0.f;
+      if (__ballot(!good) != 0ull) status = PURSE_INST_BAD_SHAPE;
     }
-    if (I.status == PURSE_INST_OK) {
-      // ---- keypoint records (and the whitening factors of the fit)
-      for (int i = 0; i < n; ++i)
-        for (int r = 0; r < 3; ++r) ab[r] += a[3 * i + r];
+    if (status == PURSE_INST_OK) {
+      // ---- model centroid (a sum over the lanes in a fixed butterfly order)
+      // and the record of keypoint `tid` (with the whitening factors of the fit)
+      for (int r = 0; r < 3; ++r) ab[r] = tid < n ? (double)a[3 * tid + r] : 0.0;
+      for (int o = 32; o >= 1; o >>= 1)
+        for (int r = 0; r < 3; ++r) ab[r] += __shfl_xor(ab[r], o, 64);
       for (int r = 0; r < 3; ++r) ab[r] /= n;
-      for (int r = 0; r < 3; ++r) I.abar[r] = (float)ab[r];
       const float tau = is2d ? p.tau2 : p.tau3;
-      KpRec *kp = kprec + I.kp_off;
-      for (int i = 0; i < n; ++i) {
+      if (tid < n) {
+        const int i = tid;
         KpRec k;
         for (int r = 0; r < 3; ++r) {
           k.m[r] = is2d ? a[3 * i + r] : (float)((double)a[3 * i + r] - ab[r]);
@@ -94,10 +88,27 @@ __global__ void __launch_bounds__(kPrologueBlock) k_prologue(DevBatch b, DevPara
         k.kb = (float)((double)p.kappa * beta[i]);
         k.kb2 = k.kb * k.kb;
         k.bt = (float)((double)beta[i] + tau);
-        kp[i] = k;
+        kprec[kp_off + i] = k;
       }
     }
-    stage = I.status != PURSE_INST_OK ? 0 : (is2d ? 2 : 1);
+    if (tid == 0) {
+      I.kind = kind;
+      I.n_kp = n;
+      I.kp_off = kp_off;
+      I.sample_off = soff;
+      I.n_samples = sM;
+      I.seed = b.seed[j];
+      I.has_anchor = 0;
+      I.status = status;
+      for (int k = 0; k < 4; ++k) I.K[k] = K[k];
+      for (int k = 0; k < 9; ++k) I.Rc[k] = I.Ra[k] = (k % 4 == 0) ? 1.f : 0.f;
+      for (int k = 0; k < 3; ++k) I.tc[k] = I.ta[k] = I.oc[k] = 0.f;
+      for (int r = 0; r < 3; ++r) I.abar[r] = status == PURSE_INST_OK ? (float)ab[r] : 0.f;
+      I.data_fp = 0ull;
+      fp_n = (kp_ok && n >= 0 && n <= PURSE_MAX_KP) ? n : 0;
+      fp_ko = ko;
+      stage = status != PURSE_INST_OK ? 0 : (is2d ? 2 : 1);
+    }
   }
   __syncthreads();
   const int st = stage;
