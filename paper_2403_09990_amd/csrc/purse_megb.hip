@@ -31,7 +31,10 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kBins = 256;
 constexpr int kGlobalSteps = 64;
-constexpr int kPassPer = 4;  // samples per thread of the per-sample passes (k_megb_prep, k_megb_radii)
+// samples per thread of the per-sample passes (k_megb_prep, k_megb_radii):
+// kPassPer on instances of at least kPassPerMin samples, else one
+constexpr int kPassPer = 4;
+constexpr int64_t kPassPerMin = 1 << 17;
 constexpr int kChainBlock = 512;  // threads of a pipelined chain workgroup (the larger variant)
 constexpr int kChainWaves = kChainBlock / 64;
 // Variants of the chain workgroup:
@@ -492,6 +495,7 @@ __global__ void __launch_bounds__(kEarlyBlock) k_megb_gshell_collect(const int64
 
 // Per sample: quaternion (w >= 0; w = -2 marks an infeasible sample) and
 // translation (w = 1 feasible, 0 not); first feasible index; feasible count.
+template <int PER>
 __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict__ sample_off, int64_t total,
                                                       int64_t max_m, const float *__restrict__ poses,
                                                       const uint8_t *__restrict__ mask, MegbRec *rec,
@@ -499,21 +503,21 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
   const int j = blockIdx.y;
   int64_t off, M;
   sample_range(sample_off, j, total, max_m, off, M);
-  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * kPassPer) + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * PER) + threadIdx.x;
   __shared__ int cnt[kWaves];
   __shared__ int firsts[kWaves];
   int feas = 0, first = INT32_MAX;
-  // kPassPer samples per thread, kBlock apart: the masks first, then the
+  // PER samples per thread, kBlock apart: the masks first, then the
   // poses of the feasible ones, every load of a round in flight together
-  uint8_t m[kPassPer];
+  uint8_t m[PER];
 #pragma unroll
-  for (int u = 0; u < kPassPer; ++u) {
+  for (int u = 0; u < PER; ++u) {
     const int64_t s = s0 + u * kBlock;
     m[u] = s < M ? mask[off + s] : (uint8_t)0;
   }
-  float4 a[kPassPer], b[kPassPer], c[kPassPer];
+  float4 a[PER], b[PER], c[PER];
 #pragma unroll
-  for (int u = 0; u < kPassPer; ++u) {
+  for (int u = 0; u < PER; ++u) {
     const int64_t s = s0 + u * kBlock;
     if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
       const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * (off + s));
@@ -523,7 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_prep(const int64_t *__restrict_
     }
   }
 #pragma unroll
-  for (int u = 0; u < kPassPer; ++u) {
+  for (int u = 0; u < PER; ++u) {
     const int64_t s = s0 + u * kBlock;
     if (s >= M) continue;
     const int64_t g = off + s;
@@ -1435,26 +1439,27 @@ __global__ void __launch_bounds__(chain_block<V>(), V == kChainWide ? 1 : 4) k_m
 }
 
 // float64 radii about the centre: max ||R* - R_s||_F^2 and ||t* - t_s||^2.
+template <int PER>
 __global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict__ sample_off, int64_t total,
                                                        int64_t max_m, const float *__restrict__ poses,
                                                        const uint8_t *__restrict__ mask, MegbRec *rec) {
   const int j = blockIdx.y;
   int64_t off, M;
   sample_range(sample_off, j, total, max_m, off, M);
-  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * kPassPer) + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * (kBlock * PER) + threadIdx.x;
   __shared__ double red[2][kWaves];
   double fr = 0.0, ft = 0.0;
   if (rec[j].first != INT32_MAX) {
-    // kPassPer samples per thread, kBlock apart, loads in flight together
-    uint8_t m[kPassPer];
+    // PER samples per thread, kBlock apart, loads in flight together
+    uint8_t m[PER];
 #pragma unroll
-    for (int u = 0; u < kPassPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int64_t s = s0 + u * kBlock;
       m[u] = s < M ? mask[off + s] : (uint8_t)0;
     }
-    float4 pa[kPassPer], pb[kPassPer], pc[kPassPer];
+    float4 pa[PER], pb[PER], pc[PER];
 #pragma unroll
-    for (int u = 0; u < kPassPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int64_t s = s0 + u * kBlock;
       if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
         const float4 *pp = reinterpret_cast<const float4 *>(poses + 12 * (off + s));
@@ -1465,7 +1470,7 @@ __global__ void __launch_bounds__(kBlock) k_megb_radii(const int64_t *__restrict
     }
     const float *C = rec[j].centre;
 #pragma unroll
-    for (int u = 0; u < kPassPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int64_t s = s0 + u * kBlock;
       if (s < M && (m[u] & PURSE_MASK_FEASIBLE)) {
         const float P[12] = {pa[u].x, pa[u].y, pa[u].z, pa[u].w, pb[u].x, pb[u].y,
@@ -1922,9 +1927,17 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   const int ck = ckpt_spacing(p.ckpt_every);
   const int n = b.n_inst;
   hipLaunchKernelGGL(k_megb_init, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec);
-  dim3 grid((unsigned)((max_samples + kBlock * kPassPer - 1) / (kBlock * kPassPer)), (unsigned)n);
-  hipLaunchKernelGGL(k_megb_prep, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples, poses,
-                     mask, rec, quat, trans);
+  // (several samples per thread on large instances: fewer workgroups and
+  // atomics; one on small ones, whose passes are latency-bound)
+  const bool per4 = max_samples >= kPassPerMin;
+  const int per = per4 ? kPassPer : 1;
+  dim3 grid((unsigned)((max_samples + kBlock * per - 1) / (kBlock * per)), (unsigned)n);
+  if (per4)
+    hipLaunchKernelGGL(k_megb_prep<kPassPer>, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples,
+                       max_samples, poses, mask, rec, quat, trans);
+  else
+    hipLaunchKernelGGL(k_megb_prep<1>, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
+                       poses, mask, rec, quat, trans);
   // The wide variant while there are at most as many chains as compute
   // units, else the narrow one (measured on batches of 256-1,024 uneven
   // instances: 1.4-2.3 times faster than the shell steps of one wave with no
@@ -1963,8 +1976,12 @@ void launch_megb(const DevBatch &b, const DevParams &p, const float *poses, cons
   if (p.flags & PURSE_FLAG_EXACT_MEB)
     hipLaunchKernelGGL(k_megb_exact, dim3(2 * n), dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
                        quat, trans, rec);
-  hipLaunchKernelGGL(k_megb_radii, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
-                     poses, mask, rec);
+  if (per4)
+    hipLaunchKernelGGL(k_megb_radii<kPassPer>, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples,
+                       max_samples, poses, mask, rec);
+  else
+    hipLaunchKernelGGL(k_megb_radii<1>, grid, dim3(kBlock), 0, stream, b.sample_off, total_samples, max_samples,
+                       poses, mask, rec);
   hipLaunchKernelGGL(k_megb_final, dim3((n + 255) / 256), dim3(256), 0, stream, n, rec, centre, radii,
                      n_feasible, inst_status);
 }
