@@ -256,6 +256,7 @@ def main():
     mask = torch.empty(db.total_samples, dtype=torch.uint8, device=dev)
     status = torch.empty(db.n_inst, dtype=torch.int32, device=dev)
     schedule = "default"
+    candidates_ms = None
     _progress("workload", args.config, "samples", db.total_samples)
     if not args.no_tune:
         # the sampler's launch schedule (tile size, tile order, keypoint loop),
@@ -264,6 +265,10 @@ def main():
         reps = 1 if db.total_samples > (1 << 23) else 3
         gp, rep = autotune.tune(db, gp, ws, poses, mask, status, reps=reps)
         schedule = rep["choice"] if "choice" in rep else "tuned"
+        if isinstance(rep.get("candidates_ms"), dict):
+            # every candidate's time (warm, HIP events): the spread says how
+            # close the choice was, the level how fast this device runs
+            candidates_ms = {k: round(float(v), 3) for k, v in rep["candidates_ms"].items()}
     centre = torch.empty(db.n_inst, 12, dtype=torch.float32, device=dev)
     radii = torch.empty(db.n_inst, 2, dtype=torch.float64, device=dev)
     nfeas = torch.empty(db.n_inst, dtype=torch.int64, device=dev)
@@ -392,6 +397,7 @@ def main():
                    "step": "sample + MEGB" + ("" if args.no_backward else " + backward (all instances, one call)"),
                    "parallelism": "single GPU"},
         "sampler_schedule": schedule,
+        "sampler_candidates_ms": candidates_ms,
         "timed_as": "graph replay" if graph is not None else "eager launches",
         "graph_replay_equals_eager": graph_check,
         "ms_per_step_eager": ms_step_eager,

@@ -11,7 +11,8 @@ those, the persistent work-queue kernels (PURSE_FLAG_WORK_QUEUE), caps of 4
 and 2 resident wavefronts per SIMD (params.waves_per_simd) and the launch
 groups one after the other on one stream (PURSE_FLAG_SERIAL_GROUPS; by
 default they run concurrently, which overlaps their tails on mixed batches
-but costs a fork and a join on single-group ones), which change speed only.
+but costs a fork and a join on single-group ones), alone and with either
+cap, which change speed only.
 tune() times every candidate with HIP events on the given batch and keeps the
 fastest; the choice is cached in a JSON file keyed by the workload's
 signature (kinds, keypoint counts, sample counts, iteration counts, device
@@ -33,7 +34,8 @@ _TUNED = (PURSE_FLAG_INSTANCE_ORDER | PURSE_FLAG_GENERIC_LOOP | PURSE_FLAG_PAIR_
           PURSE_FLAG_WORK_QUEUE | PURSE_FLAG_SERIAL_GROUPS)
 # second stage, on the fastest tile / order / loop: (flags, waves per SIMD)
 STAGE2 = ((PURSE_FLAG_WORK_QUEUE, 0), (0, 4), (0, 2), (PURSE_FLAG_SERIAL_GROUPS, 0),
-          (PURSE_FLAG_SERIAL_GROUPS | PURSE_FLAG_WORK_QUEUE, 0))
+          (PURSE_FLAG_SERIAL_GROUPS | PURSE_FLAG_WORK_QUEUE, 0), (PURSE_FLAG_SERIAL_GROUPS, 4),
+          (PURSE_FLAG_SERIAL_GROUPS, 2))
 
 
 def default_cache_path() -> str:
